@@ -1,0 +1,237 @@
+/*
+ * hmg.h -- C-ABI of libhmg, an MI355X (gfx950) implementation of the
+ * multigrid-preconditioned Bi-CGSTAB solver for the 2-D Helmholtz equation
+ * of I. Livshits, "Shifted Laplacian based multigrid preconditioners for
+ * solving indefinite Helmholtz equations" (arXiv:1312.2880).
+ *
+ * Problem (Section 1, eq:diff and the Sommerfeld condition after it):
+ *     Lap u + k(x)^2 u = f  on [0,1]^2,   du/dn - i k u = 0 on the boundary,
+ * discretised by the second-order 5-point stencil (eq:disc) with the
+ * boundary condition closed by central-difference ghost points.
+ *
+ * Grid and array conventions used by every call:
+ *   - n interior nodes per side, n = 2^m - 1; h = 1/(n+1) on the unit square
+ *     (any h > 0 is accepted: the domain is then [0, (n+1) h]^2);
+ *   - every node (i,j), 0 <= i,j <= n+1, is an unknown, node (i,j) sits at
+ *     (i h, j h);
+ *   - arrays are row-major with x fastest: element (i,j) at j*(n+2) + i,
+ *     (n+2)^2 elements per field;
+ *   - wavenumber k: real double per node (k, not k^2), finite and > 0;
+ *   - complex fields: hmg_c64 (two doubles, re then im; the layout of C99
+ *     double _Complex and of torch.complex128).
+ *
+ * Ownership: the caller owns every pointer it passes.  Host inputs are copied
+ * before the call returns; host outputs are written only on HMG_OK (and on
+ * HMG_ERR_NOT_CONVERGED / HMG_ERR_BREAKDOWN for solution arrays, which then
+ * hold the last iterate).  Functions with the suffix _dev take device
+ * pointers and a hipStream_t (passed as void*, NULL = the grid's own stream);
+ * they enqueue work on that stream and may return before it completes unless
+ * stated otherwise.  Handles are opaque and released by their destroy call.
+ *
+ * Errors: every call returns an hmg_status and never throws.  A thread-local
+ * message for the last failure is available from hmg_last_error().
+ *
+ * Threading: hmg_submit / hmg_poll / hmg_cancel are thread-safe; all other
+ * calls on one handle must be serialised by the caller.
+ */
+#ifndef HMG_H
+#define HMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hmg_c64;
+
+typedef enum {
+    HMG_OK = 0,
+    HMG_ERR_INVALID = 1,        /* bad argument; nothing was done               */
+    HMG_ERR_NOMEM = 2,          /* device or host allocation failed             */
+    HMG_ERR_DEVICE = 3,         /* a HIP call failed                            */
+    HMG_ERR_NOT_CONVERGED = 4,  /* maxit reached; x holds the last iterate      */
+    HMG_ERR_BREAKDOWN = 5,      /* repeated Bi-CGSTAB breakdown                 */
+    HMG_PENDING = 6,            /* request not finished yet                     */
+    HMG_ERR_TOO_LARGE = 7,      /* request footprint above the context budget   */
+    HMG_ERR_UNKNOWN_TICKET = 8,
+    HMG_ERR_CANCELLED = 9
+} hmg_status;
+
+/* Section 5: the three V-cycle variants.  SL-V uses M = L + i beta k^2 for
+ * relaxation and residuals; HLM-V uses L for both; HYB-V uses L for residuals
+ * everywhere and M for relaxation on the levels near kH = 0.625 and 1.25. */
+typedef enum { HMG_SL = 0, HMG_HLM = 1, HMG_HYB = 2 } hmg_variant;
+
+/* FP64: the whole path in double.  MIXED: the V-cycle (preconditioner) in
+ * complex float, the outer Bi-CGSTAB, inner products, the true residual and
+ * the coarsest-grid solve in double. */
+typedef enum { HMG_FP64 = 0, HMG_MIXED = 1 } hmg_precision;
+
+typedef enum { HMG_SM_GS = 0, HMG_SM_KACZ = 1, HMG_SM_LU = 2 } hmg_smoother;
+
+typedef struct {
+    int    variant;          /* hmg_variant, default HMG_HYB                      */
+    int    precision;        /* hmg_precision, default HMG_FP64                   */
+    double beta;             /* shift of eq:mh, default 0.5                       */
+    int    nu_pre, nu_post;  /* red-black Gauss-Seidel sweeps, default 1 + 1      */
+    int    kacz_pre, kacz_post; /* 5-colour Kaczmarz sweeps, default 4 + 4        */
+    int    kacz_band;        /* 1: Kaczmarz on the kH ~ 1.25 levels (default)     */
+    int    coarsest_n;       /* interior size of the dense-LU level, default 7    */
+    int    use_graph;        /* 1: replay each Bi-CGSTAB iteration as a hipGraph  */
+    int    reserved[7];
+} hmg_opts;
+
+#define HMG_MAX_LEVELS 24
+
+/* The level plan chosen at grid creation (Section 5 level rules). */
+typedef struct {
+    int    nlev;
+    int    n[HMG_MAX_LEVELS];
+    double H[HMG_MAX_LEVELS];
+    double kHmin[HMG_MAX_LEVELS], kHmax[HMG_MAX_LEVELS];
+    int    smoother[HMG_MAX_LEVELS];      /* hmg_smoother                     */
+    double sigma_relax[HMG_MAX_LEVELS];   /* role (A): relaxation operator    */
+    double sigma_resid[HMG_MAX_LEVELS];   /* role (B): residual operator      */
+    int    pre[HMG_MAX_LEVELS], post[HMG_MAX_LEVELS];
+} hmg_plan;
+
+typedef struct {
+    double iters;            /* Bi-CGSTAB iterations, counted in halves (Section 6) */
+    int    halfsteps;
+    double rel_res_true;     /* ||b - L x|| / ||b|| recomputed in FP64 at exit  */
+    int    status;           /* hmg_status of this solve                       */
+    int    levels;
+    int    restarts;         /* breakdown / true-residual restarts             */
+    double seconds;          /* wall time of the solve                         */
+} hmg_solve_info;
+
+typedef struct hmg_ctx  hmg_ctx;
+typedef struct hmg_grid hmg_grid;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Fill *o with the defaults above (the paper's constants, Section 5). */
+void        hmg_opts_default(hmg_opts *o);
+/* Open device `device` (HIP ordinal).  hbm_budget_bytes bounds the device
+ * memory admitted by the request server (0 = 90% of free memory). */
+hmg_status  hmg_ctx_create(int device, size_t hbm_budget_bytes, hmg_ctx **out);
+void        hmg_ctx_destroy(hmg_ctx *ctx);
+const char *hmg_last_error(void);
+
+/* ---- grid ----------------------------------------------------------------- */
+
+/* Build the hierarchy for one problem (Section 1 problem statement; Section 5
+ * V-cycle components): n = 2^m - 1 >= opts->coarsest_n, h > 0, k per node
+ * ((n+2)^2 doubles), f: nrhs right-hand sides of (n+2)^2 complex each (NULL:
+ * all zero), nrhs >= 1.  Coarse grids halve the interval count down to
+ * coarsest_n, take k by injection and rediscretise the 5-point operator; the
+ * coarsest operator is factored by dense LU in FP64 on the host.  opts NULL
+ * means the defaults.  All inputs are copied. */
+hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const double *k,
+                           const hmg_c64 *f, int nrhs, const hmg_opts *opts,
+                           hmg_grid **out);
+void       hmg_grid_destroy(hmg_grid *g);
+hmg_status hmg_grid_plan(const hmg_grid *g, hmg_plan *plan);
+/* Replace right-hand side `rhs` (host array of (n+2)^2). */
+hmg_status hmg_grid_set_rhs(hmg_grid *g, int rhs, const hmg_c64 *f);
+/* Device bytes held by the grid. */
+size_t     hmg_grid_footprint(const hmg_grid *g);
+
+/* ---- preconditioner: one V-cycle (Section 5) -------------------------------
+ * z = B_V r: one V-cycle from a zero initial guess on every level (pre-
+ * relaxation, residual, full weighting, recursion, bilinear correction,
+ * post-relaxation; dense solve on the coarsest level).  r and z are complex
+ * FP64 fields of (n+2)^2; in MIXED precision the cycle runs in complex float
+ * between the FP64 input and output. */
+hmg_status hmg_vcycle(hmg_grid *g, const hmg_c64 *r, hmg_c64 *z);
+hmg_status hmg_vcycle_dev(hmg_grid *g, const void *d_r, void *d_z, void *stream);
+
+/* ---- solve: right-preconditioned Bi-CGSTAB (Section 6) ---------------------
+ * Solves L^h x = f for every right-hand side of the grid from the zero
+ * initial guess of Section 6.  x: nrhs fields of (n+2)^2, the solutions on
+ * exit.  Stops when ||r|| / ||f|| <= rtol (checked at every
+ * half iteration and confirmed with the recomputed FP64 residual) or after
+ * maxit iterations.  info: nrhs entries (may be NULL).  Returns the worst
+ * status over the right-hand sides. */
+hmg_status hmg_solve(hmg_grid *g, hmg_c64 *x, double rtol, int maxit,
+                     hmg_solve_info *info);
+/* Device variant for right-hand side `rhs`: d_b (input, may be NULL = the
+ * grid's stored f) and d_x (in: initial guess if x0_given, out: solution) are
+ * caller-owned complex FP64 device fields.  Synchronises the stream before
+ * returning (the iteration count is data dependent). */
+hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void *d_x,
+                         int x0_given, double rtol, int maxit,
+                         hmg_solve_info *info, void *stream);
+
+/* ---- batching: many grids and right-hand sides in one launch plan ----------
+ * Solves every right-hand side of every grid (zero initial guess); x[q] holds
+ * grids[q]'s nrhs solutions, info[q] its nrhs infos (NULL allowed). */
+hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *grids,
+                           hmg_c64 *const *x, double rtol, int maxit,
+                           hmg_solve_info *const *info);
+
+/* ---- serving: continuous batching of solve requests -------------------------
+ * A request is copied at submit; the server admits queued requests in arrival
+ * order while the sum of admitted device footprints stays within the context
+ * budget, advances every admitted solve one Bi-CGSTAB iteration per step
+ * (work of different requests overlaps on the device), and retires finished
+ * ones.  poll returns HMG_PENDING until the request is finished, then its
+ * final status and (if x_out != NULL) copies the solution; the ticket is
+ * released by the first non-pending poll. */
+typedef struct {
+    int            n;
+    double         h;
+    const double  *k;
+    const hmg_c64 *f;
+    hmg_opts       opts;
+    double         rtol;
+    int            maxit;
+} hmg_request;
+
+typedef struct {
+    int    status;
+    double iters;
+    double rel_res_true;
+    double t_arrive, t_admit, t_done;   /* seconds on the context's clock     */
+    size_t footprint_bytes;
+} hmg_result;
+
+hmg_status hmg_submit(hmg_ctx *ctx, const hmg_request *req, uint64_t *ticket);
+hmg_status hmg_poll(hmg_ctx *ctx, uint64_t ticket, hmg_c64 *x_out, hmg_result *res);
+hmg_status hmg_cancel(hmg_ctx *ctx, uint64_t ticket);
+/* Limit the number of requests in flight at once (0 = limited by the budget
+ * only; 1 = serve one request at a time, the serial baseline). */
+hmg_status hmg_ctx_set_max_active(hmg_ctx *ctx, int max_active);
+/* Seconds since the context was created (the clock of hmg_result). */
+double     hmg_ctx_clock(const hmg_ctx *ctx);
+
+/* ---- single kernels on one level (parity tests) ----------------------------
+ * Each call enqueues one building block of the V-cycle on level `level` of the
+ * grid's hierarchy, on caller-owned device fields of (n_l+2)^2 elements in
+ * the grid's V-cycle precision (complex double for FP64, complex float for
+ * MIXED).  sigma selects L (0) or M (beta).
+ *   apply:    out = A_sigma u                       (Section 1 operator)
+ *   smooth:   `sweeps` sweeps of red-black Gauss-Seidel (HMG_SM_GS) or
+ *             5-colour Kaczmarz (HMG_SM_KACZ) on A_sigma u = f, in place on u;
+ *             zero_guess = 1 treats the incoming u as zero (u need not be
+ *             initialised)                          (Sections 4 and 5)
+ *   restrict: fc = R (f - A_sigma u), full weighting to level+1 (Section 5)
+ *   prolong:  u += P ec, bilinear from level+1 to level (Section 5)
+ *   coarsest: u = A_c^{-1} f on the last level (dense, FP64)              */
+hmg_status hmg_op_apply_dev(hmg_grid *g, int level, double sigma, const void *d_u,
+                            void *d_out, void *stream);
+hmg_status hmg_op_smooth_dev(hmg_grid *g, int level, int smoother, double sigma,
+                             int sweeps, int zero_guess, const void *d_f, void *d_u,
+                             void *stream);
+hmg_status hmg_op_restrict_dev(hmg_grid *g, int level, double sigma, const void *d_f,
+                               const void *d_u, void *d_fc, void *stream);
+hmg_status hmg_op_prolong_dev(hmg_grid *g, int level, const void *d_ec, void *d_u,
+                              void *stream);
+hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_u, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMG_H */

@@ -1,0 +1,558 @@
+// hmg_api.hip -- host side of libhmg: the C-ABI of include/hmg.h, the level
+// plan, the hierarchy, the coarsest-grid factorisation, the V-cycle schedule
+// and the Bi-CGSTAB driver (Livshits, arXiv:1312.2880, Sections 1, 5, 6).
+
+#include "hmg.h"
+#include "hmg_internal.h"
+#include "hmg_host.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace hmgk;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+hmg_status hmg_fail(hmg_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+extern "C" const char *hmg_last_error(void) { return g_last_error.c_str(); }
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return hmg_fail(HMG_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+double hmg_now() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// options and plan
+// ---------------------------------------------------------------------------
+extern "C" void hmg_opts_default(hmg_opts *o) {
+    std::memset(o, 0, sizeof *o);
+    o->variant = HMG_HYB;
+    o->precision = HMG_FP64;
+    o->beta = 0.5;
+    o->nu_pre = 1;
+    o->nu_post = 1;
+    o->kacz_pre = 4;
+    o->kacz_post = 4;
+    o->kacz_band = 1;
+    o->coarsest_n = 7;
+    o->use_graph = 1;
+}
+
+// Level classification (Section 5).  The paper states its rules on grids
+// with kH = 0.3125 * 2^j and constant k; for a level whose nodes span
+// [kH_min, kH_max] the first matching rule applies:
+//   last level                       -> dense LU on M (SL) or L (HLM, HYB);
+//   kacz_band, span meets [1.25/sqrt2, 1.25 sqrt2)
+//                                    -> Kaczmarz 4+4 on M (SL, HYB) or L (HLM);
+//   HYB, span meets [0.625/sqrt2, 0.625 sqrt2)
+//                                    -> Gauss-Seidel on M;
+//   relaxation on L and an interior node with |k^2 H^2 - 4| < 1 (vanishing
+//   Gauss-Seidel pivot)              -> Kaczmarz 4+4 on L;
+//   otherwise                        -> Gauss-Seidel on M (SL) or L (HLM, HYB).
+// Residuals (role (B)) use M for SL and L for HLM and HYB.
+static void classify_level(const hmg_opts &o, hmg_plan &pl, int l, bool last, const double *k) {
+    int n = pl.n[l], M = n + 2;
+    double H = pl.H[l], lo = 1e300, hi = -1e300, beta = o.beta;
+    bool guard = false;
+    for (int j = 0; j < M; ++j)
+        for (int i = 0; i < M; ++i) {
+            double kh = k[(size_t)j * M + i] * H;
+            lo = std::min(lo, kh);
+            hi = std::max(hi, kh);
+            if (i > 0 && j > 0 && i < M - 1 && j < M - 1 && std::fabs(kh * kh - 4.0) < 1.0) guard = true;
+        }
+    pl.kHmin[l] = lo;
+    pl.kHmax[l] = hi;
+    bool sl = (o.variant == HMG_SL);
+    pl.sigma_resid[l] = sl ? beta : 0.0;
+    if (last) {
+        pl.smoother[l] = HMG_SM_LU;
+        pl.sigma_relax[l] = sl ? beta : 0.0;
+        pl.pre[l] = pl.post[l] = 0;
+        return;
+    }
+    const double r2 = std::sqrt(2.0);
+    bool band_k = hi >= 1.25 / r2 && lo < 1.25 * r2;
+    bool band_m = hi >= 0.625 / r2 && lo < 0.625 * r2;
+    if (o.kacz_band && band_k) {
+        pl.smoother[l] = HMG_SM_KACZ;
+        pl.sigma_relax[l] = (o.variant == HMG_HLM) ? 0.0 : beta;
+        pl.pre[l] = o.kacz_pre;
+        pl.post[l] = o.kacz_post;
+        return;
+    }
+    if (o.variant == HMG_HYB && band_m) {
+        pl.smoother[l] = HMG_SM_GS;
+        pl.sigma_relax[l] = beta;
+        pl.pre[l] = o.nu_pre;
+        pl.post[l] = o.nu_post;
+        return;
+    }
+    double sig = sl ? beta : 0.0;
+    if (sig == 0.0 && guard) {
+        pl.smoother[l] = HMG_SM_KACZ;
+        pl.sigma_relax[l] = 0.0;
+        pl.pre[l] = o.kacz_pre;
+        pl.post[l] = o.kacz_post;
+        return;
+    }
+    pl.smoother[l] = HMG_SM_GS;
+    pl.sigma_relax[l] = sig;
+    pl.pre[l] = o.nu_pre;
+    pl.post[l] = o.nu_post;
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: dense A_sigma, LU with partial pivoting, explicit inverse
+// ---------------------------------------------------------------------------
+typedef std::complex<double> cd;
+
+static void dense_operator(int n, double H, const double *k, double sigma, std::vector<cd> &A) {
+    int M = n + 2, N = n + 1;
+    size_t m = (size_t)M * M;
+    A.assign(m * m, cd(0.0, 0.0));
+    double ih2 = 1.0 / (H * H);
+    for (int j = 0; j <= N; ++j)
+        for (int i = 0; i <= N; ++i) {
+            size_t p = (size_t)j * M + i;
+            double kp = k[p];
+            int b = (i == 0) + (i == N) + (j == 0) + (j == N);
+            A[p * m + p] = cd(-4.0 * ih2 + kp * kp, 2.0 * kp * H * b * ih2 + kp * kp * sigma);
+            if (i > 0) A[p * m + p - 1] += ((i == N) ? 2.0 : 1.0) * ih2;
+            if (i < N) A[p * m + p + 1] += ((i == 0) ? 2.0 : 1.0) * ih2;
+            if (j > 0) A[p * m + p - M] += ((j == N) ? 2.0 : 1.0) * ih2;
+            if (j < N) A[p * m + p + M] += ((j == 0) ? 2.0 : 1.0) * ih2;
+        }
+}
+
+// Inverse of A (m x m, row-major) via LU with partial pivoting; returns it
+// column-major (out[c*m + r] = inv(r, c)).  false if singular.
+static bool invert_dense(size_t m, std::vector<cd> A, std::vector<cd> &out) {
+    std::vector<size_t> piv(m);
+    for (size_t c = 0; c < m; ++c) {
+        size_t p = c;
+        double best = std::abs(A[c * m + c]);
+        for (size_t r = c + 1; r < m; ++r)
+            if (std::abs(A[r * m + c]) > best) { best = std::abs(A[r * m + c]); p = r; }
+        if (best == 0.0) return false;
+        piv[c] = p;
+        if (p != c)
+            for (size_t q = 0; q < m; ++q) std::swap(A[c * m + q], A[p * m + q]);
+        for (size_t r = c + 1; r < m; ++r) {
+            cd l = A[r * m + c] / A[c * m + c];
+            A[r * m + c] = l;
+            for (size_t q = c + 1; q < m; ++q) A[r * m + q] -= l * A[c * m + q];
+        }
+    }
+    out.assign(m * m, cd(0.0, 0.0));
+    std::vector<cd> x(m);
+    for (size_t c = 0; c < m; ++c) {
+        std::fill(x.begin(), x.end(), cd(0.0, 0.0));
+        x[c] = 1.0;
+        for (size_t q = 0; q < m; ++q)
+            if (piv[q] != q) std::swap(x[q], x[piv[q]]);
+        for (size_t r = 0; r < m; ++r)
+            for (size_t q = 0; q < r; ++q) x[r] -= A[r * m + q] * x[q];
+        for (size_t r = m; r-- > 0;) {
+            for (size_t q = r + 1; q < m; ++q) x[r] -= A[r * m + q] * x[q];
+            x[r] /= A[r * m + r];
+        }
+        for (size_t r = 0; r < m; ++r) out[c * m + r] = x[r];
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// device memory: one allocation per grid, carved into 256-byte aligned parts
+// ---------------------------------------------------------------------------
+struct Carver {
+    size_t off = 0;
+    char  *base = nullptr;
+    void  *take(size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+static bool valid_n(int n, int nc) {
+    if (n < 1 || n < nc) return false;
+    unsigned v = (unsigned)n + 1;
+    return (v & (v - 1)) == 0;
+}
+
+// Lay out (or size, when c.base is null) every device buffer of the grid.
+static void layout(hmg_grid *g, Carver &c) {
+    size_t csz = (g->prec == P64) ? 16 : 8, rsz = (g->prec == P64) ? 8 : 4;
+    for (int l = 0; l < g->nlev; ++l) {
+        Level &L = g->lev[l];
+        size_t m = (size_t)L.geo.M * L.geo.M;
+        L.k = c.take(m * rsz);
+    }
+    g->k0 = (double *)c.take((size_t)g->lev[0].geo.M * g->lev[0].geo.M * 8);
+    int mc = g->lev[g->nlev - 1].geo.M;
+    g->ainv_t = (double *)c.take((size_t)mc * mc * (size_t)mc * mc * 16);
+    size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+    int nb = krylov_nblocks(g->lev[0].geo);
+    for (int s = 0; s < g->nrhs; ++s) {
+        Slot &S = g->slot[s];
+        for (int l = 0; l < g->nlev; ++l) {
+            size_t m = (size_t)g->lev[l].geo.M * g->lev[l].geo.M;
+            bool own = (l > 0) || (g->prec == P32);
+            S.f[l] = own ? c.take(m * csz) : nullptr;
+            S.u[l] = own ? c.take(m * csz) : nullptr;
+        }
+        Krylov &K = S.K;
+        double **vecs[] = {&K.b, &K.x, &K.r, &K.rh, &K.p, &K.v, &K.s, &K.t, &K.ph, &K.sh};
+        for (double **v : vecs) *v = (double *)c.take(m0 * 16);
+        K.nblocks = nb;
+        K.partials = (double *)c.take((size_t)3 * nb * 8);
+        S.hist_cap = 0;
+        K.hist = nullptr;
+        K.st = (KState *)c.take(sizeof(KState));
+    }
+}
+
+// Device bytes of a grid of size n with options o (sizes do not depend on k).
+size_t estimate_footprint(int n, const hmg_opts &o) {
+    hmg_grid g;
+    g.nrhs = 1;
+    g.prec = (o.precision == HMG_MIXED) ? P32 : P64;
+    int nl = n, l = 0;
+    double H = 1.0;
+    for (;; ++l) {
+        g.lev[l].geo = make_geo(nl, H);
+        if (nl <= o.coarsest_n || l == HMG_MAX_LEVELS - 1) break;
+        nl = (nl - 1) / 2;
+        H *= 2.0;
+    }
+    g.nlev = l + 1;
+    g.slot.resize(1);
+    Carver c;
+    layout(&g, c);
+    return c.off + 256;
+}
+
+extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const double *k, const hmg_c64 *f, int nrhs,
+                                      const hmg_opts *opts, hmg_grid **out) {
+    if (!ctx || !out) return hmg_fail(HMG_ERR_INVALID, "null context or output handle");
+    *out = nullptr;
+    hmg_opts o;
+    if (opts) o = *opts;
+    else hmg_opts_default(&o);
+    if (o.coarsest_n < 1 || o.coarsest_n > 31 || !valid_n(o.coarsest_n, 1))
+        return hmg_fail(HMG_ERR_INVALID, "coarsest_n must be 2^m - 1 in [1, 31], got %d", o.coarsest_n);
+    if (!valid_n(n, o.coarsest_n))
+        return hmg_fail(HMG_ERR_INVALID, "n must be 2^m - 1 >= coarsest_n (%d), got %d", o.coarsest_n, n);
+    if (!(h > 0.0) || !std::isfinite(h)) return hmg_fail(HMG_ERR_INVALID, "h must be finite and > 0");
+    if (!k) return hmg_fail(HMG_ERR_INVALID, "k is required");
+    if (nrhs < 1 || nrhs > 4096) return hmg_fail(HMG_ERR_INVALID, "nrhs must be in [1, 4096]");
+    if (o.variant < 0 || o.variant > 2) return hmg_fail(HMG_ERR_INVALID, "bad variant");
+    if (o.precision != HMG_FP64 && o.precision != HMG_MIXED) return hmg_fail(HMG_ERR_INVALID, "bad precision");
+    if (!std::isfinite(o.beta) || o.nu_pre < 0 || o.nu_post < 0 || o.kacz_pre < 0 || o.kacz_post < 0 ||
+        o.nu_pre > 64 || o.nu_post > 64 || o.kacz_pre > 64 || o.kacz_post > 64)
+        return hmg_fail(HMG_ERR_INVALID, "bad sweep counts or beta");
+    size_t m0 = (size_t)(n + 2) * (n + 2);
+    for (size_t q = 0; q < m0; ++q)
+        if (!(k[q] > 0.0) || !std::isfinite(k[q])) return hmg_fail(HMG_ERR_INVALID, "k must be finite and > 0");
+    if (f)
+        for (size_t q = 0; q < m0 * (size_t)nrhs; ++q)
+            if (!std::isfinite(f[q].re) || !std::isfinite(f[q].im))
+                return hmg_fail(HMG_ERR_INVALID, "f must be finite");
+
+    hmg_grid *g = new hmg_grid();
+    g->ctx = ctx;
+    g->opts = o;
+    g->n = n;
+    g->h = h;
+    g->nrhs = nrhs;
+    g->prec = (o.precision == HMG_MIXED) ? P32 : P64;
+
+    // hierarchy: halve the interval count down to coarsest_n, k by injection
+    std::vector<std::vector<double>> kl;
+    kl.emplace_back(k, k + m0);
+    int nl = n;
+    double H = h;
+    for (int l = 0;; ++l) {
+        g->plan.n[l] = nl;
+        g->plan.H[l] = H;
+        if (nl <= o.coarsest_n || l == HMG_MAX_LEVELS - 1) {
+            g->nlev = l + 1;
+            break;
+        }
+        int nc = (nl - 1) / 2, Mc = nc + 2, M = nl + 2;
+        std::vector<double> kc((size_t)Mc * Mc);
+        for (int J = 0; J < Mc; ++J)
+            for (int I = 0; I < Mc; ++I) kc[(size_t)J * Mc + I] = kl.back()[(size_t)(2 * J) * M + 2 * I];
+        kl.push_back(std::move(kc));
+        nl = nc;
+        H *= 2.0;
+    }
+    g->plan.nlev = g->nlev;
+    for (int l = 0; l < g->nlev; ++l) {
+        classify_level(o, g->plan, l, l == g->nlev - 1, kl[l].data());
+        g->lev[l].geo = make_geo(g->plan.n[l], g->plan.H[l]);
+    }
+    int lc = g->nlev - 1;
+    std::vector<cd> A, inv;
+    dense_operator(g->plan.n[lc], g->plan.H[lc], kl[lc].data(), g->plan.sigma_relax[lc], A);
+    size_t mc = (size_t)(g->plan.n[lc] + 2) * (g->plan.n[lc] + 2);
+    if (!invert_dense(mc, A, inv)) {
+        delete g;
+        return hmg_fail(HMG_ERR_INVALID, "coarsest operator is singular");
+    }
+
+    g->slot.resize(nrhs);
+    Carver sizer;
+    layout(g, sizer);
+    g->bytes = sizer.off + 256;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&g->mem, g->bytes);
+    if (e != hipSuccess) {
+        delete g;
+        return hmg_fail(HMG_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", sizer.off, hipGetErrorString(e));
+    }
+    Carver c;
+    c.base = g->mem;
+    layout(g, c);
+    hmg_status st = grid_init_device(g, kl, inv, f);
+    if (st != HMG_OK) {
+        hmg_grid_destroy(g);
+        return st;
+    }
+    *out = g;
+    return HMG_OK;
+}
+
+hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> &kl, const std::vector<cd> &inv,
+                            const hmg_c64 *f) {
+    HIPCHK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    HIPCHK(hipHostMalloc((void **)&g->host_state, 4 * sizeof(KState), hipHostMallocDefault));
+    for (int q = 0; q < 4; ++q) HIPCHK(hipEventCreateWithFlags(&g->ev[q], hipEventDisableTiming));
+    for (int l = 0; l < g->nlev; ++l) {
+        size_t m = kl[l].size();
+        if (g->prec == P64) {
+            HIPCHK(hipMemcpy(g->lev[l].k, kl[l].data(), m * 8, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> kf(m);
+            for (size_t q = 0; q < m; ++q) kf[q] = (float)kl[l][q];
+            HIPCHK(hipMemcpy(g->lev[l].k, kf.data(), m * 4, hipMemcpyHostToDevice));
+        }
+    }
+    HIPCHK(hipMemcpy(g->k0, kl[0].data(), kl[0].size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->ainv_t, inv.data(), inv.size() * 16, hipMemcpyHostToDevice));
+    size_t m0 = kl[0].size();
+    for (int s = 0; s < g->nrhs; ++s) {
+        if (f) HIPCHK(hipMemcpy(g->slot[s].K.b, f + m0 * s, m0 * 16, hipMemcpyHostToDevice));
+        else HIPCHK(hipMemsetAsync(g->slot[s].K.b, 0, m0 * 16, g->stream));
+    }
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return HMG_OK;
+}
+
+extern "C" void hmg_grid_destroy(hmg_grid *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    for (Slot &S : g->slot) {
+        if (S.iter_graph) (void)hipGraphExecDestroy(S.iter_graph);
+        if (S.K.hist) (void)hipFree(S.K.hist);
+    }
+    if (g->mem) (void)hipFree(g->mem);
+    for (int q = 0; q < 4; ++q)
+        if (g->ev[q]) (void)hipEventDestroy(g->ev[q]);
+    if (g->host_state) (void)hipHostFree(g->host_state);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+extern "C" hmg_status hmg_grid_plan(const hmg_grid *g, hmg_plan *plan) {
+    if (!g || !plan) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    *plan = g->plan;
+    return HMG_OK;
+}
+
+extern "C" size_t hmg_grid_footprint(const hmg_grid *g) { return g ? g->bytes : 0; }
+
+extern "C" hmg_status hmg_grid_set_rhs(hmg_grid *g, int rhs, const hmg_c64 *f) {
+    if (!g || !f || rhs < 0 || rhs >= g->nrhs) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+    for (size_t q = 0; q < m0; ++q)
+        if (!std::isfinite(f[q].re) || !std::isfinite(f[q].im)) return hmg_fail(HMG_ERR_INVALID, "f must be finite");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    HIPCHK(hipMemcpy(g->slot[rhs].K.b, f, m0 * 16, hipMemcpyHostToDevice));
+    return HMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle schedule (Section 5): zero initial guess on every level,
+//   pre-relax (role A) -> residual (role B) + full weighting -> recurse ->
+//   bilinear correction -> post-relax (role A); dense solve on the coarsest.
+// ---------------------------------------------------------------------------
+static void relax(hmg_grid *g, int l, const void *f, void *u, int sweeps, bool zero_guess, hipStream_t s,
+                  const int *skip) {
+    const Level &L = g->lev[l];
+    double sig = g->plan.sigma_relax[l];
+    if (g->plan.smoother[l] == HMG_SM_GS) {
+        if (sweeps == 0 && zero_guess)
+            launch_fill_zero(g->prec, s, u, (size_t)L.geo.M * L.geo.M, skip);
+        for (int q = 0; q < sweeps; ++q) {
+            launch_gs_colour(g->prec, s, L.geo, L.k, sig, f, u, 0, (zero_guess && q == 0) ? 1 : 0, skip);
+            launch_gs_colour(g->prec, s, L.geo, L.k, sig, f, u, 1, 0, skip);
+        }
+    } else {
+        if (zero_guess) launch_fill_zero(g->prec, s, u, (size_t)L.geo.M * L.geo.M, skip);
+        for (int q = 0; q < sweeps; ++q)
+            for (int c = 0; c < 5; ++c) launch_kacz_colour(g->prec, s, L.geo, L.k, sig, f, u, c, skip);
+    }
+}
+
+static void vcycle_level(hmg_grid *g, Slot &S, int l, const void *f, void *u, hipStream_t s, const int *skip) {
+    const Level &L = g->lev[l];
+    if (g->plan.smoother[l] == HMG_SM_LU) {
+        launch_coarsest(g->prec, s, L.geo.M * L.geo.M, g->ainv_t, f, u, skip);
+        return;
+    }
+    relax(g, l, f, u, g->plan.pre[l], true, s, skip);
+    launch_residual_fw(g->prec, s, L.geo, L.k, g->plan.sigma_resid[l], f, u, S.f[l + 1], skip);
+    vcycle_level(g, S, l + 1, S.f[l + 1], S.u[l + 1], s, skip);
+    launch_prolong_add(g->prec, s, L.geo, S.u[l + 1], u, skip);
+    relax(g, l, f, u, g->plan.post[l], false, s, skip);
+}
+
+// z = B_V r on FP64 device fields r, z (finest level).
+void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip) {
+    if (g->prec == P64) {
+        vcycle_level(g, S, 0, r, z, s, skip);
+    } else {
+        size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+        launch_convert(s, 1, r, S.f[0], m0, skip);
+        vcycle_level(g, S, 0, S.f[0], S.u[0], s, skip);
+        launch_convert(s, 0, S.u[0], z, m0, skip);
+    }
+}
+
+static hipStream_t pick_stream(hmg_grid *g, void *stream) { return stream ? (hipStream_t)stream : g->stream; }
+
+extern "C" hmg_status hmg_vcycle_dev(hmg_grid *g, const void *d_r, void *d_z, void *stream) {
+    if (!g || !d_r || !d_z) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    hipStream_t s = pick_stream(g, stream);
+    enqueue_vcycle(g, g->slot[0], (const double *)d_r, (double *)d_z, s, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_vcycle(hmg_grid *g, const hmg_c64 *r, hmg_c64 *z) {
+    if (!g || !r || !z) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+    Slot &S = g->slot[0];
+    HIPCHK(hipMemcpyAsync(S.K.p, r, m0 * 16, hipMemcpyHostToDevice, g->stream));
+    enqueue_vcycle(g, S, S.K.p, S.K.ph, g->stream, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(z, S.K.ph, m0 * 16, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    return HMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single building blocks (parity tests)
+// ---------------------------------------------------------------------------
+static hmg_status check_level(hmg_grid *g, int level, bool need_coarser) {
+    if (!g) return hmg_fail(HMG_ERR_INVALID, "null grid");
+    if (level < 0 || level >= g->nlev || (need_coarser && level >= g->nlev - 1))
+        return hmg_fail(HMG_ERR_INVALID, "level %d out of range", level);
+    HIPCHK(hipSetDevice(g->ctx->device));
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_apply_dev(hmg_grid *g, int level, double sigma, const void *d_u, void *d_out,
+                                       void *stream) {
+    hmg_status st = check_level(g, level, false);
+    if (st) return st;
+    if (!d_u || !d_out) return hmg_fail(HMG_ERR_INVALID, "null field");
+    const Level &L = g->lev[level];
+    launch_apply(g->prec, pick_stream(g, stream), L.geo, L.k, sigma, d_u, d_out);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_smooth_dev(hmg_grid *g, int level, int smoother, double sigma, int sweeps,
+                                        int zero_guess, const void *d_f, void *d_u, void *stream) {
+    hmg_status st = check_level(g, level, false);
+    if (st) return st;
+    if (!d_f || !d_u || sweeps < 0) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    if (smoother != HMG_SM_GS && smoother != HMG_SM_KACZ) return hmg_fail(HMG_ERR_INVALID, "bad smoother");
+    const Level &L = g->lev[level];
+    hipStream_t s = pick_stream(g, stream);
+    if (smoother == HMG_SM_GS) {
+        if (sweeps == 0 && zero_guess) launch_fill_zero(g->prec, s, d_u, (size_t)L.geo.M * L.geo.M, nullptr);
+        for (int q = 0; q < sweeps; ++q) {
+            launch_gs_colour(g->prec, s, L.geo, L.k, sigma, d_f, d_u, 0, (zero_guess && q == 0) ? 1 : 0, nullptr);
+            launch_gs_colour(g->prec, s, L.geo, L.k, sigma, d_f, d_u, 1, 0, nullptr);
+        }
+    } else {
+        if (zero_guess) launch_fill_zero(g->prec, s, d_u, (size_t)L.geo.M * L.geo.M, nullptr);
+        for (int q = 0; q < sweeps; ++q)
+            for (int c = 0; c < 5; ++c) launch_kacz_colour(g->prec, s, L.geo, L.k, sigma, d_f, d_u, c, nullptr);
+    }
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_restrict_dev(hmg_grid *g, int level, double sigma, const void *d_f, const void *d_u,
+                                          void *d_fc, void *stream) {
+    hmg_status st = check_level(g, level, true);
+    if (st) return st;
+    if (!d_f || !d_u || !d_fc) return hmg_fail(HMG_ERR_INVALID, "null field");
+    const Level &L = g->lev[level];
+    launch_residual_fw(g->prec, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, d_fc, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_prolong_dev(hmg_grid *g, int level, const void *d_ec, void *d_u, void *stream) {
+    hmg_status st = check_level(g, level, true);
+    if (st) return st;
+    if (!d_ec || !d_u) return hmg_fail(HMG_ERR_INVALID, "null field");
+    launch_prolong_add(g->prec, pick_stream(g, stream), g->lev[level].geo, d_ec, d_u, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_u, void *stream) {
+    if (!g || !d_f || !d_u) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    const Level &L = g->lev[g->nlev - 1];
+    launch_coarsest(g->prec, pick_stream(g, stream), L.geo.M * L.geo.M, g->ainv_t, d_f, d_u, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}

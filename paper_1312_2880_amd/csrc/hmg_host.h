@@ -1,0 +1,65 @@
+// hmg_host.h -- host-side objects of libhmg (context, grid, solve slots).
+// Internal to the library; the public interface is include/hmg.h.
+#pragma once
+
+#include "hmg.h"
+#include "hmg_internal.h"
+
+#include <complex>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+struct ServerState;
+
+struct hmg_ctx {
+    int    device = 0;
+    size_t budget = 0;      // bytes of device memory the server may admit
+    double t0 = 0.0;        // clock origin
+    std::unique_ptr<ServerState> server;
+};
+
+struct Level {
+    hmgk::Geo geo;
+    void     *k = nullptr;  // wavenumber in the V-cycle precision
+};
+
+// Per right-hand side: level fields of one V-cycle in flight and the
+// finest-level Krylov vectors and scalars.
+struct Slot {
+    void        *f[HMG_MAX_LEVELS] = {};
+    void        *u[HMG_MAX_LEVELS] = {};
+    hmgk::Krylov K{};
+    int          hist_cap = 0;
+    hipGraphExec_t iter_graph = nullptr;
+};
+
+struct hmg_grid {
+    hmg_ctx   *ctx = nullptr;
+    hmg_opts   opts{};
+    int        n = 0, nrhs = 0, nlev = 0;
+    double     h = 0.0;
+    hmgk::Prec prec = hmgk::P64;
+    hmg_plan   plan{};
+    Level      lev[HMG_MAX_LEVELS];
+    double    *k0 = nullptr;      // finest k in FP64 (outer operator)
+    double    *ainv_t = nullptr;  // coarsest inverse, column-major complex FP64
+    std::vector<Slot> slot;
+    char      *mem = nullptr;
+    size_t     bytes = 0;
+    hipStream_t stream = nullptr;
+    hmgk::KState *host_state = nullptr;   // pinned, 4 entries
+    hipEvent_t ev[4] = {};
+};
+
+hmg_status hmg_fail(hmg_status st, const char *fmt, ...);
+double     hmg_now();
+hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> &kl,
+                            const std::vector<std::complex<double>> &inv, const hmg_c64 *f);
+size_t     estimate_footprint(int n, const hmg_opts &o);
+void       enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s,
+                          const int *skip);

@@ -1,0 +1,82 @@
+// hmg_internal.h -- declarations shared by the kernel and host translation
+// units of libhmg.  Not part of the public C-ABI (include/hmg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hmgk {
+
+enum Prec { P64 = 0, P32 = 1 };
+
+// Geometry of one level: n interior nodes per side, M = n + 2 nodes per
+// side, N = n + 1 intervals, spacing H.  Fields are dense M x M, x fastest.
+struct Geo {
+    int    n, M, N;
+    double H;
+};
+
+inline Geo make_geo(int n, double H) { return Geo{n, n + 2, n + 1, H}; }
+
+// Scalars of one Bi-CGSTAB solve, resident in device memory.  Complex
+// numbers are stored as (re, im) pairs.
+struct KState {
+    double rho[2], rho_old[2], alpha[2], omega[2], beta[2];
+    double bnorm;        // ||b|| (1 if b = 0)
+    double rnorm2;       // ||r||^2 of the current residual
+    double snorm2;       // ||s||^2 of the current half step
+    double rhat_norm2;   // ||rhat||^2
+    double rtol;
+    double true_rel;     // ||b - L x|| / ||b|| from the last true-residual check
+    int    halfsteps;
+    int    maxhalf;
+    int    done;         // 0 running, 1 recursive residual met rtol, 2 maxit
+    int    half_exit;    // converged at the half step of this iteration
+    int    restart;      // next p-update restarts with rhat = p = r
+    int    stop;         // done || half_exit: later kernels of the iteration skip
+    int    restarts;
+    int    hist_cap;
+};
+
+// Device pointers of one solve slot (finest-level Krylov vectors).
+struct Krylov {
+    double *b, *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;   // complex interleaved
+    double *partials;    // reduction scratch: NQ x nblocks doubles
+    double *hist;        // relative residual per half step
+    KState *st;
+    int     nblocks;
+};
+
+// ---- multigrid building blocks (templated on precision via Prec) --------
+// k: real field of the level in the level precision; complex fields likewise.
+void launch_apply(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma,
+                  const void *u, void *out);
+void launch_gs_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma,
+                      const void *f, void *u, int colour, int zero_guess, const int *skip);
+void launch_kacz_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma,
+                        const void *f, void *u, int colour, const int *skip);
+void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *skip);
+void launch_residual_fw(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma,
+                        const void *f, const void *u, void *fc, const int *skip);
+void launch_prolong_add(Prec p, hipStream_t s, const Geo &gfine, const void *ec, void *u,
+                        const int *skip);
+void launch_coarsest(Prec p, hipStream_t s, int m, const double *ainv_t, const void *f,
+                     void *u, const int *skip);
+void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, size_t count,
+                    const int *skip);
+
+// ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
+int  krylov_nblocks(const Geo &g);
+void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given,
+              double rtol, int maxhalf);
+void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K);
+void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
+void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K);
+void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
+void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K);
+void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
+void kry_restart_from_true(hipStream_t s, const Krylov &K);
+
+}  // namespace hmgk

@@ -1,0 +1,747 @@
+// hmg_kernels.hip -- gfx950 kernels of the multigrid-preconditioned
+// Bi-CGSTAB Helmholtz solver (Livshits, arXiv:1312.2880).
+//
+// Layout: every field of a level is dense (n+2) x (n+2), x fastest; complex
+// values are interleaved (re, im) in the level precision T (double or
+// float).  Threads are laid out 64 x 4 per block so that each 64-wide wave
+// reads 64 consecutive nodes of one grid row.
+//
+// Discrete operator (Section 1, eq:diff / eq:disc / eq:mh), for node p =
+// (i, j) on a level with spacing H and N = n+1 intervals:
+//   a_pp = (-4 + 2 i k_p H b_p) / H^2 + k_p^2 (1 + i sigma)
+//   a_pq = w_pq / H^2,  w_pq = 2 for the inward neighbour across a boundary
+//                       face of p, 1 otherwise,
+// with b_p the number of boundary faces of p.  This is the 5-point stencil
+// with the Sommerfeld condition du/dn - i k u = 0 closed by central-
+// difference ghost points; sigma = 0 gives L, sigma = beta gives M.
+
+#include "hmg_internal.h"
+
+namespace hmgk {
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) C {
+    T x, y;
+};
+
+template <typename T> __device__ __forceinline__ C<T> cmk(T a, T b) { C<T> z; z.x = a; z.y = b; return z; }
+template <typename T> __device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return cmk(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return cmk(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ C<T> cscale(T s, C<T> a) { return cmk(s * a.x, s * a.y); }
+template <typename T> __device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a / (dre + i dim)
+template <typename T> __device__ __forceinline__ C<T> cdiv(C<T> a, T dre, T dim) {
+    T inv = T(1) / (dre * dre + dim * dim);
+    return cmk((a.x * dre + a.y * dim) * inv, (a.y * dre - a.x * dim) * inv);
+}
+
+constexpr int BX = 64, BY = 4, NT = BX * BY;
+
+// Row p of A_sigma: diagonal (dre + i dim) and neighbour weights / H^2.
+template <typename T>
+struct Row {
+    T dre, dim, wl, wr, wd, wu;
+};
+
+template <typename T>
+__device__ __forceinline__ Row<T> row_at(int i, int j, int N, T H, T ih2, T kp, T sigma) {
+    Row<T> r;
+    int b = (i == 0) + (i == N) + (j == 0) + (j == N);
+    T k2 = kp * kp;
+    r.dre = T(-4) * ih2 + k2;
+    r.dim = T(2) * kp * H * T(b) * ih2 + k2 * sigma;
+    r.wl = (i > 0) ? ((i == N) ? T(2) : T(1)) * ih2 : T(0);
+    r.wr = (i < N) ? ((i == 0) ? T(2) : T(1)) * ih2 : T(0);
+    r.wd = (j > 0) ? ((j == N) ? T(2) : T(1)) * ih2 : T(0);
+    r.wu = (j < N) ? ((j == 0) ? T(2) : T(1)) * ih2 : T(0);
+    return r;
+}
+
+// sum_{q != p} a_pq u_q, neighbours in the order left, right, down, up
+template <typename T>
+__device__ __forceinline__ C<T> offsum(const Row<T> &r, const C<T> *u, int i, int j, int N, int M) {
+    C<T> s = cmk(T(0), T(0));
+    size_t p = (size_t)j * M + i;
+    if (i > 0) s = cadd(s, cscale(r.wl, u[p - 1]));
+    if (i < N) s = cadd(s, cscale(r.wr, u[p + 1]));
+    if (j > 0) s = cadd(s, cscale(r.wd, u[p - M]));
+    if (j < N) s = cadd(s, cscale(r.wu, u[p + M]));
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ C<T> row_apply(const Row<T> &r, const C<T> *u, int i, int j, int N, int M) {
+    C<T> up = u[(size_t)j * M + i];
+    return cadd(cmul(cmk(r.dre, r.dim), up), offsum(r, u, i, j, N, M));
+}
+
+struct GeoT {
+    int n, M, N;
+};
+
+// ---------------------------------------------------------------------------
+// Operator apply: out = A_sigma u
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_apply(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
+                                              const C<T> *__restrict__ u, C<T> *__restrict__ out) {
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    if (i > g.N || j > g.N) return;
+    size_t p = (size_t)j * g.M + i;
+    Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
+    out[p] = row_apply(r, u, i, j, g.N, g.M);
+}
+
+// ---------------------------------------------------------------------------
+// Red-black Gauss-Seidel half sweep (Section 4 relaxation, red = (i+j) even).
+// u_p <- (f_p - sum_{q != p} a_pq u_q) / a_pp for every node of one colour;
+// nodes of one colour are not coupled, so the update is order independent.
+// zero_guess (colour 0 of a first sweep): the other colour counts as zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_gs_colour(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
+                                                  const C<T> *__restrict__ f, C<T> *u, int colour,
+                                                  int zero_guess, const int *skip) {
+    if (skip && *skip) return;
+    int j = blockIdx.y * BY + threadIdx.y;
+    int i = 2 * (blockIdx.x * BX + threadIdx.x) + ((colour + j) & 1);
+    if (i > g.N || j > g.N) return;
+    size_t p = (size_t)j * g.M + i;
+    Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
+    C<T> num = f[p];
+    if (!zero_guess) num = csub(num, offsum(r, u, i, j, g.N, g.M));
+    u[p] = cdiv(num, r.dre, r.dim);
+}
+
+// ---------------------------------------------------------------------------
+// 5-colour Kaczmarz pass (Section 4: relaxation of the normal equations,
+// row-action form).  For every row p with (i + 2j) mod 5 == colour:
+//   delta = (f_p - (A u)_p) / ||a_p||^2,  u_q += conj(a_pq) delta, q in row p.
+// Rows of one colour are >= 3 apart, so their stencils are disjoint.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_kacz_colour(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
+                                                    const C<T> *__restrict__ f, C<T> *u, int colour,
+                                                    const int *skip) {
+    if (skip && *skip) return;
+    int j = blockIdx.y * BY + threadIdx.y;
+    int i0 = ((colour - 2 * j) % 5 + 5) % 5;
+    int i = i0 + 5 * (blockIdx.x * BX + threadIdx.x);
+    if (i > g.N || j > g.N) return;
+    size_t p = (size_t)j * g.M + i;
+    Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
+    C<T> res = csub(f[p], row_apply(r, u, i, j, g.N, g.M));
+    T nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+    C<T> d = cmk(res.x / nrm, res.y / nrm);
+    C<T> up = u[p];
+    u[p] = cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x));
+    if (i > 0) u[p - 1] = cadd(u[p - 1], cscale(r.wl, d));
+    if (i < g.N) u[p + 1] = cadd(u[p + 1], cscale(r.wr, d));
+    if (j > 0) u[p - g.M] = cadd(u[p - g.M], cscale(r.wd, d));
+    if (j < g.N) u[p + g.M] = cadd(u[p + g.M], cscale(r.wu, d));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_zero(C<T> *u, size_t count, const int *skip) {
+    if (skip && *skip) return;
+    size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < count) u[q] = cmk(T(0), T(0));
+}
+
+// ---------------------------------------------------------------------------
+// Residual + full weighting (Section 5): fc(I,J) = (1/16) sum_{d,e} (2-|d|)
+// (2-|e|) r(2I+d, 2J+e), r = f - A_sigma u, fine values outside the grid
+// mirrored (r(-1) = r(1), r(N+1) = r(N-1)).  One thread per coarse node.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_residual_fw(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
+                                                    const C<T> *__restrict__ f, const C<T> *__restrict__ u,
+                                                    C<T> *__restrict__ fc, const int *skip) {
+    if (skip && *skip) return;
+    int Nc = g.N / 2, Mc = Nc + 1;
+    int I = blockIdx.x * BX + threadIdx.x;
+    int J = blockIdx.y * BY + threadIdx.y;
+    if (I > Nc || J > Nc) return;
+    C<T> s = cmk(T(0), T(0));
+    for (int e = -1; e <= 1; ++e) {
+        int j = 2 * J + e;
+        j = (j < 0) ? -j : ((j > g.N) ? 2 * g.N - j : j);
+        for (int d = -1; d <= 1; ++d) {
+            int i = 2 * I + d;
+            i = (i < 0) ? -i : ((i > g.N) ? 2 * g.N - i : i);
+            size_t p = (size_t)j * g.M + i;
+            Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
+            C<T> res = csub(f[p], row_apply(r, u, i, j, g.N, g.M));
+            T w = T((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
+            s = cadd(s, cscale(w, res));
+        }
+    }
+    fc[(size_t)J * Mc + I] = cscale(T(0.0625), s);
+}
+
+// ---------------------------------------------------------------------------
+// Bilinear prolongation + correction (Section 5): u += P ec.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_prolong_add(GeoT g, const C<T> *__restrict__ ec, C<T> *u,
+                                                    const int *skip) {
+    if (skip && *skip) return;
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    if (i > g.N || j > g.N) return;
+    int Mc = g.N / 2 + 1;
+    int I = i >> 1, J = j >> 1;
+    size_t q = (size_t)J * Mc + I;
+    C<T> e;
+    if (!(i & 1) && !(j & 1)) {
+        e = ec[q];
+    } else if ((i & 1) && !(j & 1)) {
+        e = cscale(T(0.5), cadd(ec[q], ec[q + 1]));
+    } else if (!(i & 1) && (j & 1)) {
+        e = cscale(T(0.5), cadd(ec[q], ec[q + Mc]));
+    } else {
+        e = cscale(T(0.25), cadd(cadd(cadd(ec[q], ec[q + 1]), ec[q + Mc]), ec[q + Mc + 1]));
+    }
+    size_t p = (size_t)j * g.M + i;
+    u[p] = cadd(u[p], e);
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest level: u = A_c^{-1} f with the inverse precomputed in FP64
+// (stored transposed, ainv_t[c*m + r] = inv[r][c], so that consecutive
+// threads read consecutive rows).  One workgroup.
+// ---------------------------------------------------------------------------
+constexpr int MAX_COARSE = 33 * 33;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarsest(int m, const C<double> *__restrict__ ainv_t,
+                                                  const C<T> *__restrict__ f, C<T> *__restrict__ u,
+                                                  const int *skip) {
+    if (skip && *skip) return;
+    __shared__ C<double> fs[MAX_COARSE];
+    for (int q = threadIdx.x; q < m; q += 256) fs[q] = cmk((double)f[q].x, (double)f[q].y);
+    __syncthreads();
+    for (int r = threadIdx.x; r < m; r += 256) {
+        C<double> acc = cmk(0.0, 0.0);
+        for (int c = 0; c < m; ++c) acc = cadd(acc, cmul(ainv_t[(size_t)c * m + r], fs[c]));
+        u[r] = cmk((T)acc.x, (T)acc.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_to_float(const C<double> *__restrict__ src, C<float> *__restrict__ dst,
+                                                  size_t count, const int *skip) {
+    if (skip && *skip) return;
+    size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < count) dst[q] = cmk((float)src[q].x, (float)src[q].y);
+}
+
+__global__ __launch_bounds__(256) void k_to_double(const C<float> *__restrict__ src, C<double> *__restrict__ dst,
+                                                   size_t count, const int *skip) {
+    if (skip && *skip) return;
+    size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (q < count) dst[q] = cmk((double)src[q].x, (double)src[q].y);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline GeoT geot(const Geo &g) { return GeoT{g.n, g.M, g.N}; }
+static inline dim3 grid2(int nx, int ny) { return dim3((nx + BX - 1) / BX, (ny + BY - 1) / BY); }
+
+template <typename T>
+static void apply_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *u, void *out) {
+    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    k_apply<T><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, (T)sigma,
+                                                         (const C<T> *)u, (C<T> *)out);
+}
+void launch_apply(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *u, void *out) {
+    if (p == P64) apply_t<double>(s, g, k, sigma, u, out);
+    else apply_t<float>(s, g, k, sigma, u, out);
+}
+
+template <typename T>
+static void gs_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u, int colour,
+                 int zero_guess, const int *skip) {
+    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    k_gs_colour<T><<<grid2((g.M + 1) / 2, g.M), dim3(BX, BY), 0, s>>>(
+        geot(g), H, ih2, (const T *)k, (T)sigma, (const C<T> *)f, (C<T> *)u, colour, zero_guess, skip);
+}
+void launch_gs_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u,
+                      int colour, int zero_guess, const int *skip) {
+    if (p == P64) gs_t<double>(s, g, k, sigma, f, u, colour, zero_guess, skip);
+    else gs_t<float>(s, g, k, sigma, f, u, colour, zero_guess, skip);
+}
+
+template <typename T>
+static void kacz_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u, int colour,
+                   const int *skip) {
+    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    k_kacz_colour<T><<<grid2((g.M + 4) / 5, g.M), dim3(BX, BY), 0, s>>>(
+        geot(g), H, ih2, (const T *)k, (T)sigma, (const C<T> *)f, (C<T> *)u, colour, skip);
+}
+void launch_kacz_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u,
+                        int colour, const int *skip) {
+    if (p == P64) kacz_t<double>(s, g, k, sigma, f, u, colour, skip);
+    else kacz_t<float>(s, g, k, sigma, f, u, colour, skip);
+}
+
+void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *skip) {
+    unsigned nb = (unsigned)((count + 255) / 256);
+    if (p == P64) k_fill_zero<double><<<nb, 256, 0, s>>>((C<double> *)u, count, skip);
+    else k_fill_zero<float><<<nb, 256, 0, s>>>((C<float> *)u, count, skip);
+}
+
+template <typename T>
+static void rfw_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, const void *u, void *fc,
+                  const int *skip) {
+    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    int Mc = g.N / 2 + 1;
+    k_residual_fw<T><<<grid2(Mc, Mc), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, (T)sigma,
+                                                             (const C<T> *)f, (const C<T> *)u, (C<T> *)fc, skip);
+}
+void launch_residual_fw(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f,
+                        const void *u, void *fc, const int *skip) {
+    if (p == P64) rfw_t<double>(s, g, k, sigma, f, u, fc, skip);
+    else rfw_t<float>(s, g, k, sigma, f, u, fc, skip);
+}
+
+void launch_prolong_add(Prec p, hipStream_t s, const Geo &g, const void *ec, void *u, const int *skip) {
+    if (p == P64)
+        k_prolong_add<double><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), (const C<double> *)ec,
+                                                                       (C<double> *)u, skip);
+    else
+        k_prolong_add<float><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), (const C<float> *)ec,
+                                                                      (C<float> *)u, skip);
+}
+
+void launch_coarsest(Prec p, hipStream_t s, int m, const double *ainv_t, const void *f, void *u, const int *skip) {
+    if (p == P64)
+        k_coarsest<double><<<1, 256, 0, s>>>(m, (const C<double> *)ainv_t, (const C<double> *)f, (C<double> *)u,
+                                             skip);
+    else
+        k_coarsest<float><<<1, 256, 0, s>>>(m, (const C<double> *)ainv_t, (const C<float> *)f, (C<float> *)u,
+                                            skip);
+}
+
+void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, size_t count, const int *skip) {
+    unsigned nb = (unsigned)((count + 255) / 256);
+    if (to_float) k_to_float<<<nb, 256, 0, s>>>((const C<double> *)src, (C<float> *)dst, count, skip);
+    else k_to_double<<<nb, 256, 0, s>>>((const C<float> *)src, (C<double> *)dst, count, skip);
+}
+
+// ===========================================================================
+// Bi-CGSTAB (Section 6), FP64 on the finest grid.  Right preconditioning:
+//   p = r + beta (p - omega v);  ph = B p;  v = L ph;  alpha = rho / (rh, v)
+//   s = r - alpha v  (half step; stop if ||s|| <= rtol ||b||, x += alpha ph)
+//   sh = B s;  t = L sh;  omega = (t, s) / (t, t)
+//   x += alpha ph + omega sh;  r = s - omega t;  rho' = (rh, r)
+//   beta = (rho' / rho)(alpha / omega)
+// Inner products (a, b) = sum conj(a) b.  Each reduction writes one partial
+// per block (fixed block order) and a single-block kernel sums the partials
+// in a fixed order, so results do not depend on scheduling.
+// ===========================================================================
+
+// Sum NV values over a 256-thread block; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
+    __shared__ double red[NV][NT / 64];
+    int tid = threadIdx.y * BX + threadIdx.x;
+    int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[q][wave] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double x = red[q][0];
+            for (int w = 1; w < NT / 64; ++w) x += red[q][w];
+            out[q] = x;
+        }
+    }
+}
+
+// Writes the block's NV sums to partials[q * nblocks + block].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials) {
+    double tot[NV];
+    block_sum<NV>(v, tot);
+    int nb = gridDim.x * gridDim.y;
+    int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) partials[(size_t)q * nb + b] = tot[q];
+    }
+}
+
+// Single 256-thread block: total of each of NV partial rows (fixed order:
+// thread t sums t, t+256, ... sequentially, then a fixed tree).
+template <int NV>
+__device__ __forceinline__ void finalize_sums(const double *partials, int nb, double *tot) {
+    double v[NV];
+    int tid = threadIdx.y * BX + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = 0.0;
+        for (int b = tid; b < nb; b += NT) x += partials[(size_t)q * nb + b];
+        v[q] = x;
+    }
+    __shared__ double out[NV];
+    block_sum<NV>(v, out);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) tot[q] = out[q];
+}
+
+struct KDev {
+    C<double> *b, *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;
+    double *partials, *hist;
+    KState *st;
+};
+
+static inline KDev kdev(const Krylov &K) {
+    return KDev{(C<double> *)K.b,  (C<double> *)K.x, (C<double> *)K.r,  (C<double> *)K.rh,
+                (C<double> *)K.p,  (C<double> *)K.v, (C<double> *)K.s,  (C<double> *)K.t,
+                (C<double> *)K.ph, (C<double> *)K.sh, K.partials, K.hist, K.st};
+}
+
+__device__ __forceinline__ C<double> cdivc(C<double> a, C<double> b) { return cdiv(a, b.x, b.y); }
+__device__ __forceinline__ C<double> ld2(const double *p) { return cmk(p[0], p[1]); }
+__device__ __forceinline__ void st2(double *p, C<double> z) { p[0] = z.x; p[1] = z.y; }
+
+// ---- init: r = b - L x (or r = b, x = 0), rh = r, p = v = 0 --------------
+__global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, const double *__restrict__ k,
+                                                 KDev K, int x0_given) {
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    double v[2] = {0.0, 0.0};
+    if (i <= g.N && j <= g.N) {
+        size_t p = (size_t)j * g.M + i;
+        C<double> bp = K.b[p], rp;
+        if (x0_given) {
+            Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
+            rp = csub(bp, row_apply(r, K.x, i, j, g.N, g.M));
+        } else {
+            K.x[p] = cmk(0.0, 0.0);
+            rp = bp;
+        }
+        K.r[p] = rp;
+        K.rh[p] = rp;
+        K.p[p] = cmk(0.0, 0.0);
+        K.v[p] = cmk(0.0, 0.0);
+        v[0] = bp.x * bp.x + bp.y * bp.y;
+        v[1] = rp.x * rp.x + rp.y * rp.y;
+    }
+    block_partials<2>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol, int maxhalf, int hist_cap) {
+    double tot[2];
+    finalize_sums<2>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    KState *s = K.st;
+    double bn = sqrt(tot[0]);
+    if (bn == 0.0) bn = 1.0;
+    s->bnorm = bn;
+    s->rnorm2 = tot[1];
+    s->rhat_norm2 = tot[1];
+    s->rho[0] = tot[1]; s->rho[1] = 0.0;
+    s->rho_old[0] = 1.0; s->rho_old[1] = 0.0;
+    s->alpha[0] = 1.0; s->alpha[1] = 0.0;
+    s->omega[0] = 1.0; s->omega[1] = 0.0;
+    s->beta[0] = 0.0; s->beta[1] = 0.0;
+    s->rtol = rtol;
+    s->halfsteps = 0;
+    s->maxhalf = maxhalf;
+    s->restart = 1;          // first p-update: p = r (p = v = 0, beta = rho)
+    s->half_exit = 0;
+    s->restarts = 0;
+    s->hist_cap = hist_cap;
+    double rel = sqrt(tot[1]) / bn;
+    if (hist_cap > 0) K.hist[0] = rel;
+    s->done = (rel <= rtol) ? 1 : 0;
+    s->stop = s->done;
+    s->true_rel = -1.0;
+}
+
+// ---- p = r + beta (p - omega v); on restart rh = r and p = r ----------------
+__global__ __launch_bounds__(NT) void k_kry_update_p(GeoT g, KDev K) {
+    const KState *s = K.st;
+    if (s->done) return;
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    if (i > g.N || j > g.N) return;
+    size_t p = (size_t)j * g.M + i;
+    C<double> r = K.r[p];
+    if (s->restart) {
+        K.rh[p] = r;
+        K.p[p] = r;
+    } else {
+        C<double> beta = ld2(s->beta), omega = ld2(s->omega);
+        K.p[p] = cadd(r, cmul(beta, csub(K.p[p], cmul(omega, K.v[p]))));
+    }
+}
+
+// ---- v = L ph, partial (rh, v) ----------------------------------------------
+__global__ __launch_bounds__(NT) void k_kry_matvec_alpha(GeoT g, double H, double ih2, const double *__restrict__ k,
+                                                         KDev K) {
+    if (K.st->done) return;
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    double v[2] = {0.0, 0.0};
+    if (i <= g.N && j <= g.N) {
+        size_t p = (size_t)j * g.M + i;
+        Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
+        C<double> vp = row_apply(r, K.ph, i, j, g.N, g.M);
+        K.v[p] = vp;
+        C<double> a = K.rh[p];
+        v[0] = a.x * vp.x + a.y * vp.y;      // conj(a) * vp
+        v[1] = a.x * vp.y - a.y * vp.x;
+    }
+    block_partials<2>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K, int nb) {
+    if (K.st->done) return;
+    double tot[2];
+    finalize_sums<2>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    KState *s = K.st;
+    s->restart = 0;
+    st2(s->alpha, cdivc(ld2(s->rho), cmk(tot[0], tot[1])));
+}
+
+// ---- s = r - alpha v, partial ||s||^2 ----------------------------------------
+__global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K) {
+    if (K.st->done) return;
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (i <= g.N && j <= g.N) {
+        size_t p = (size_t)j * g.M + i;
+        C<double> alpha = ld2(K.st->alpha);
+        C<double> sp = csub(K.r[p], cmul(alpha, K.v[p]));
+        K.s[p] = sp;
+        v[0] = sp.x * sp.x + sp.y * sp.y;
+    }
+    block_partials<1>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_s_fin(KDev K, int nb) {
+    if (K.st->done) return;
+    double tot[1];
+    finalize_sums<1>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    KState *s = K.st;
+    s->halfsteps += 1;
+    s->snorm2 = tot[0];
+    double rel = sqrt(tot[0]) / s->bnorm;
+    if (s->halfsteps < s->hist_cap) K.hist[s->halfsteps] = rel;
+    if (rel <= s->rtol) {
+        s->half_exit = 1;
+        s->stop = 1;
+    }
+}
+
+// ---- t = L sh, partials (t, s), (t, t) -----------------------------------------
+__global__ __launch_bounds__(NT) void k_kry_matvec_omega(GeoT g, double H, double ih2, const double *__restrict__ k,
+                                                         KDev K) {
+    if (K.st->stop) return;
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (i <= g.N && j <= g.N) {
+        size_t p = (size_t)j * g.M + i;
+        Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
+        C<double> tp = row_apply(r, K.sh, i, j, g.N, g.M);
+        K.t[p] = tp;
+        C<double> sp = K.s[p];
+        v[0] = tp.x * sp.x + tp.y * sp.y;    // conj(t) s
+        v[1] = tp.x * sp.y - tp.y * sp.x;
+        v[2] = tp.x * tp.x + tp.y * tp.y;
+    }
+    block_partials<3>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_omega_fin(KDev K, int nb) {
+    if (K.st->stop) return;
+    double tot[3];
+    finalize_sums<3>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    st2(K.st->omega, cdivc(cmk(tot[0], tot[1]), cmk(tot[2], 0.0)));
+}
+
+// ---- x += alpha ph + omega sh; r = s - omega t; partials ||r||^2, (rh, r) -----
+__global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
+    const KState *s = K.st;
+    if (s->done) return;
+    int half = s->half_exit;
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (i <= g.N && j <= g.N) {
+        size_t p = (size_t)j * g.M + i;
+        C<double> alpha = ld2(s->alpha);
+        if (half) {
+            K.x[p] = cadd(K.x[p], cmul(alpha, K.ph[p]));
+        } else {
+            C<double> omega = ld2(s->omega);
+            K.x[p] = cadd(K.x[p], cadd(cmul(alpha, K.ph[p]), cmul(omega, K.sh[p])));
+            C<double> rp = csub(K.s[p], cmul(omega, K.t[p]));
+            K.r[p] = rp;
+            C<double> a = K.rh[p];
+            v[0] = rp.x * rp.x + rp.y * rp.y;
+            v[1] = a.x * rp.x + a.y * rp.y;  // conj(rh) r
+            v[2] = a.x * rp.y - a.y * rp.x;
+        }
+    }
+    if (!half) block_partials<3>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
+    KState *s = K.st;
+    if (s->done) return;
+    if (s->half_exit) {
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            s->done = 1;
+            s->stop = 1;
+        }
+        return;
+    }
+    double tot[3];
+    finalize_sums<3>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    s->halfsteps += 1;
+    s->rnorm2 = tot[0];
+    double rn = sqrt(tot[0]);
+    double rel = rn / s->bnorm;
+    if (s->halfsteps < s->hist_cap) K.hist[s->halfsteps] = rel;
+    if (rel <= s->rtol) {
+        s->done = 1;
+        s->stop = 1;
+        return;
+    }
+    if (s->halfsteps >= s->maxhalf) {
+        s->done = 2;
+        s->stop = 1;
+        return;
+    }
+    C<double> rho_new = cmk(tot[1], tot[2]);
+    double mag = sqrt(rho_new.x * rho_new.x + rho_new.y * rho_new.y);
+    if (mag <= 1e-14 * sqrt(s->rhat_norm2) * rn) {
+        // breakdown: restart with rh = r
+        s->restart = 1;
+        s->restarts += 1;
+        s->rho[0] = tot[0]; s->rho[1] = 0.0;
+        s->rho_old[0] = 1.0; s->rho_old[1] = 0.0;
+        s->alpha[0] = 1.0; s->alpha[1] = 0.0;
+        s->omega[0] = 1.0; s->omega[1] = 0.0;
+        s->rhat_norm2 = tot[0];
+        return;
+    }
+    C<double> rho = ld2(s->rho);
+    C<double> beta = cmul(cdivc(rho_new, rho), cdivc(ld2(s->alpha), ld2(s->omega)));
+    st2(s->beta, beta);
+    st2(s->rho_old, rho);
+    st2(s->rho, rho_new);
+}
+
+// ---- true residual r = b - L x, ||r||^2 ----------------------------------------
+__global__ __launch_bounds__(NT) void k_kry_true(GeoT g, double H, double ih2, const double *__restrict__ k,
+                                                 KDev K) {
+    int i = blockIdx.x * BX + threadIdx.x;
+    int j = blockIdx.y * BY + threadIdx.y;
+    double v[1] = {0.0};
+    if (i <= g.N && j <= g.N) {
+        size_t p = (size_t)j * g.M + i;
+        Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
+        C<double> rp = csub(K.b[p], row_apply(r, K.x, i, j, g.N, g.M));
+        K.r[p] = rp;
+        v[0] = rp.x * rp.x + rp.y * rp.y;
+    }
+    block_partials<1>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_true_fin(KDev K, int nb) {
+    double tot[1];
+    finalize_sums<1>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    KState *s = K.st;
+    s->rnorm2 = tot[0];
+    s->true_rel = sqrt(tot[0]) / s->bnorm;
+}
+
+// restart from the recomputed residual: rh = r, p = r on the next update
+__global__ void k_kry_restart(KDev K) {
+    KState *s = K.st;
+    s->restart = 1;
+    s->restarts += 1;
+    s->rho[0] = s->rnorm2; s->rho[1] = 0.0;
+    s->rho_old[0] = 1.0; s->rho_old[1] = 0.0;
+    s->alpha[0] = 1.0; s->alpha[1] = 0.0;
+    s->omega[0] = 1.0; s->omega[1] = 0.0;
+    s->rhat_norm2 = s->rnorm2;
+    s->done = 0;
+    s->half_exit = 0;
+    s->stop = 0;
+}
+
+int krylov_nblocks(const Geo &g) {
+    dim3 gr = grid2(g.M, g.M);
+    return (int)(gr.x * gr.y);
+}
+
+static inline void hk(const Geo &g, double &H, double &ih2) { H = g.H; ih2 = 1.0 / (g.H * g.H); }
+
+void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given, double rtol,
+              int maxhalf) {
+    double H, ih2;
+    hk(g, H, ih2);
+    KDev d = kdev(K);
+    k_kry_init<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, x0_given);
+    // the history buffer holds maxhalf + 2 entries (allocated by the caller)
+    k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2);
+}
+void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K) {
+    k_kry_update_p<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));
+}
+void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+    double H, ih2;
+    hk(g, H, ih2);
+    KDev d = kdev(K);
+    k_kry_matvec_alpha<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K) {
+    KDev d = kdev(K);
+    k_kry_update_s<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), d);
+    k_kry_s_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+    double H, ih2;
+    hk(g, H, ih2);
+    KDev d = kdev(K);
+    k_kry_matvec_omega<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_omega_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K) {
+    KDev d = kdev(K);
+    k_kry_update_xr<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), d);
+    k_kry_iter_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+    double H, ih2;
+    hk(g, H, ih2);
+    KDev d = kdev(K);
+    k_kry_true<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_true_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_restart_from_true(hipStream_t s, const Krylov &K) { k_kry_restart<<<1, 1, 0, s>>>(kdev(K)); }
+
+}  // namespace hmgk

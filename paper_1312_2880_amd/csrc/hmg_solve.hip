@@ -1,0 +1,589 @@
+// hmg_solve.hip -- context, Bi-CGSTAB driver, batched solves and the request
+// server of libhmg (Livshits, arXiv:1312.2880, Section 6).
+//
+// One Bi-CGSTAB iteration is a fixed sequence of kernels whose scalars stay
+// in device memory; the host only reads back a small status record once per
+// iteration, one iteration behind the device, so the device never waits for
+// the host.  Kernels queued after convergence see the device-side stop flag
+// and return at once.  With opts.use_graph the sequence of one iteration is
+// captured once per right-hand side and replayed as a hipGraph.
+
+#include "hmg_host.h"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+using namespace hmgk;
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return hmg_fail(HMG_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Request;
+struct ServerState {
+    std::mutex              mu;
+    std::condition_variable cv;
+    std::thread             worker;
+    bool                    running = false;
+    bool                    quit = false;
+    uint64_t                next_ticket = 1;
+    size_t                  used = 0;
+    int                     max_active = 0;
+    std::deque<Request *>   queue;
+    std::vector<Request *>  active;
+    std::map<uint64_t, Request *> all;
+};
+
+static void server_stop(hmg_ctx *ctx);
+
+extern "C" hmg_status hmg_ctx_create(int device, size_t hbm_budget_bytes, hmg_ctx **out) {
+    if (!out) return hmg_fail(HMG_ERR_INVALID, "null output handle");
+    *out = nullptr;
+    int count = 0;
+    HIPCHK(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return hmg_fail(HMG_ERR_INVALID, "device %d not present", device);
+    HIPCHK(hipSetDevice(device));
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    hmg_ctx *c = new hmg_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    c->t0 = hmg_now();
+    c->server.reset(new ServerState());
+    *out = c;
+    return HMG_OK;
+}
+
+extern "C" void hmg_ctx_destroy(hmg_ctx *ctx) {
+    if (!ctx) return;
+    server_stop(ctx);
+    delete ctx;
+}
+
+extern "C" double hmg_ctx_clock(const hmg_ctx *ctx) { return ctx ? hmg_now() - ctx->t0 : 0.0; }
+
+// ---------------------------------------------------------------------------
+// one Bi-CGSTAB iteration
+// ---------------------------------------------------------------------------
+static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
+    const Geo &g0 = g->lev[0].geo;
+    const int *stop = &S.K.st->stop;
+    kry_update_p(s, g0, S.K);
+    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop);
+    kry_matvec_alpha(s, g0, g->k0, S.K);
+    kry_update_s(s, g0, S.K);
+    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop);
+    kry_matvec_omega(s, g0, g->k0, S.K);
+    kry_update_xr(s, g0, S.K);
+}
+
+static hmg_status iteration_graph(hmg_grid *g, Slot &S) {
+    if (S.iter_graph) return HMG_OK;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+    enqueue_iteration(g, S, g->stream);
+    hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    if (e != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&S.iter_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        S.iter_graph = nullptr;
+        return hmg_fail(HMG_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    return HMG_OK;
+}
+
+static hmg_status launch_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
+    if (g->opts.use_graph) {
+        hmg_status st = iteration_graph(g, S);
+        if (st != HMG_OK) return st;
+        HIPCHK(hipGraphLaunch(S.iter_graph, s));
+    } else {
+        enqueue_iteration(g, S, s);
+        HIPCHK(hipGetLastError());
+    }
+    return HMG_OK;
+}
+
+static hmg_status ensure_hist(Slot &S, int maxit) {
+    int cap = 2 * maxit + 2;
+    if (S.hist_cap >= cap) return HMG_OK;
+    if (S.K.hist) (void)hipFree(S.K.hist);
+    S.K.hist = nullptr;
+    S.hist_cap = 0;
+    HIPCHK(hipMalloc((void **)&S.K.hist, (size_t)cap * 8));
+    S.hist_cap = cap;
+    if (S.iter_graph) {  // the graph captured the old pointer
+        (void)hipGraphExecDestroy(S.iter_graph);
+        S.iter_graph = nullptr;
+    }
+    return HMG_OK;
+}
+
+// Solve state machine of one slot, usable both blocking (run_solve) and
+// stepped by the request server.
+struct SolveRun {
+    hmg_grid   *g = nullptr;
+    Slot       *S = nullptr;
+    hipStream_t s = nullptr;
+    double      rtol = 1e-6;
+    int         maxit = 100;
+    int         inflight = 0;      // iterations queued but not yet observed
+    int         issued = 0;
+    KState     *hs = nullptr;      // pinned, 2 records
+    hipEvent_t  ev[2] = {};
+    double      t_start = 0.0;
+};
+
+static hmg_status run_begin(SolveRun &R, int x0_given) {
+    hmg_grid *g = R.g;
+    hmg_status st = ensure_hist(*R.S, R.maxit);
+    if (st) return st;
+    kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit);
+    HIPCHK(hipGetLastError());
+    R.inflight = 0;
+    R.issued = 0;
+    R.t_start = hmg_now();
+    return HMG_OK;
+}
+
+// Queue one iteration plus its status readback.
+static hmg_status run_issue(SolveRun &R) {
+    hmg_status st = launch_iteration(R.g, *R.S, R.s);
+    if (st) return st;
+    int q = R.issued & 1;
+    HIPCHK(hipMemcpyAsync(&R.hs[q], R.S->K.st, sizeof(KState), hipMemcpyDeviceToHost, R.s));
+    HIPCHK(hipEventRecord(R.ev[q], R.s));
+    R.issued++;
+    R.inflight++;
+    return HMG_OK;
+}
+
+// Finish after the device reported done: confirm with the FP64 true
+// residual.  Returns HMG_PENDING if the iteration must go on (restart).
+static hmg_status run_finish(SolveRun &R, hmg_solve_info *info) {
+    HIPCHK(hipStreamSynchronize(R.s));
+    Slot &S = *R.S;
+    kry_true_residual(R.s, R.g->lev[0].geo, R.g->k0, S.K);
+    HIPCHK(hipMemcpyAsync(&R.hs[0], S.K.st, sizeof(KState), hipMemcpyDeviceToHost, R.s));
+    HIPCHK(hipStreamSynchronize(R.s));
+    const KState &k = R.hs[0];
+    hmg_status res;
+    if (k.done == 1 && k.true_rel <= R.rtol) {
+        res = HMG_OK;
+    } else if (k.done == 1 && k.halfsteps < 2 * R.maxit) {
+        kry_restart_from_true(R.s, S.K);
+        HIPCHK(hipGetLastError());
+        R.inflight = 0;
+        return HMG_PENDING;
+    } else {
+        res = HMG_ERR_NOT_CONVERGED;
+    }
+    if (info) {
+        info->halfsteps = k.halfsteps;
+        info->iters = 0.5 * k.halfsteps;
+        info->rel_res_true = k.true_rel;
+        info->status = res;
+        info->levels = R.g->nlev;
+        info->restarts = k.restarts;
+        info->seconds = hmg_now() - R.t_start;
+    }
+    return res;
+}
+
+static hmg_status run_solve(SolveRun &R, int x0_given, hmg_solve_info *info) {
+    hmg_status st = run_begin(R, x0_given);
+    if (st) return st;
+    for (;;) {
+        st = run_issue(R);
+        if (st) return st;
+        if (R.inflight < 2) continue;
+        int q = (R.issued - 2) & 1;   // the older of the two in flight
+        HIPCHK(hipEventSynchronize(R.ev[q]));
+        R.inflight--;
+        if (R.hs[q].done) {
+            st = run_finish(R, info);
+            if (st == HMG_PENDING) continue;
+            return st;
+        }
+        if (R.issued > R.maxit + 4) {   // the device stops at maxit; guard only
+            st = run_finish(R, info);
+            return st == HMG_PENDING ? HMG_ERR_NOT_CONVERGED : st;
+        }
+    }
+}
+
+static void run_init(SolveRun &R, hmg_grid *g, Slot *S, hipStream_t s, double rtol, int maxit) {
+    R.g = g;
+    R.S = S;
+    R.s = s;
+    R.rtol = rtol;
+    R.maxit = maxit;
+    R.hs = g->host_state;
+    R.ev[0] = g->ev[0];
+    R.ev[1] = g->ev[1];
+}
+
+static hmg_status check_solve_args(double rtol, int maxit) {
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return hmg_fail(HMG_ERR_INVALID, "rtol must be > 0");
+    if (maxit < 1 || maxit > 1000000) return hmg_fail(HMG_ERR_INVALID, "maxit must be in [1, 1e6]");
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_solve(hmg_grid *g, hmg_c64 *x, double rtol, int maxit, hmg_solve_info *info) {
+    if (!g || !x) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    hmg_status st = check_solve_args(rtol, maxit);
+    if (st) return st;
+    HIPCHK(hipSetDevice(g->ctx->device));
+    size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+    hmg_status worst = HMG_OK;
+    for (int r = 0; r < g->nrhs; ++r) {
+        SolveRun R;
+        run_init(R, g, &g->slot[r], g->stream, rtol, maxit);
+        hmg_status sr = run_solve(R, 0, info ? &info[r] : nullptr);
+        if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED) return sr;
+        HIPCHK(hipMemcpy(x + m0 * r, g->slot[r].K.x, m0 * 16, hipMemcpyDeviceToHost));
+        if (sr != HMG_OK) worst = sr;
+    }
+    return worst;
+}
+
+extern "C" hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void *d_x, int x0_given, double rtol,
+                                    int maxit, hmg_solve_info *info, void *stream) {
+    if (!g || !d_x || rhs < 0 || rhs >= g->nrhs) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    hmg_status st = check_solve_args(rtol, maxit);
+    if (st) return st;
+    HIPCHK(hipSetDevice(g->ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : g->stream;
+    Slot &S = g->slot[rhs];
+    size_t bytes = (size_t)g->lev[0].geo.M * g->lev[0].geo.M * 16;
+    if (d_b) HIPCHK(hipMemcpyAsync(S.K.b, d_b, bytes, hipMemcpyDeviceToDevice, s));
+    if (x0_given) HIPCHK(hipMemcpyAsync(S.K.x, d_x, bytes, hipMemcpyDeviceToDevice, s));
+    SolveRun R;
+    run_init(R, g, &S, s, rtol, maxit);
+    hmg_status sr = run_solve(R, x0_given, info);
+    if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED) return sr;
+    HIPCHK(hipMemcpyAsync(d_x, S.K.x, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return sr;
+}
+
+// ---------------------------------------------------------------------------
+// batched solves: every right-hand side of every grid advances one iteration
+// per round, each slot on the stream of its grid, so that the work of
+// different instances overlaps on the device.
+// ---------------------------------------------------------------------------
+extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *grids, hmg_c64 *const *x,
+                                      double rtol, int maxit, hmg_solve_info *const *info) {
+    if (!ctx || count < 0 || (count > 0 && (!grids || !x))) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    hmg_status st = check_solve_args(rtol, maxit);
+    if (st) return st;
+    for (int q = 0; q < count; ++q)
+        if (!grids[q] || !x[q] || grids[q]->ctx != ctx) return hmg_fail(HMG_ERR_INVALID, "bad grid %d", q);
+    HIPCHK(hipSetDevice(ctx->device));
+    // one pending solve per (grid, rhs); solves of one grid share its events,
+    // so right-hand sides of one grid run one after the other
+    struct Item {
+        int q, r;
+    };
+    std::vector<std::deque<Item>> per_grid(count);
+    for (int q = 0; q < count; ++q)
+        for (int r = 0; r < grids[q]->nrhs; ++r) per_grid[q].push_back(Item{q, r});
+    std::vector<SolveRun> runs(count);
+    std::vector<int> live(count, 0);
+    hmg_status worst = HMG_OK;
+    auto start_next = [&](int q) -> hmg_status {
+        if (per_grid[q].empty()) {
+            live[q] = 0;
+            return HMG_OK;
+        }
+        Item it = per_grid[q].front();
+        run_init(runs[q], grids[q], &grids[q]->slot[it.r], grids[q]->stream, rtol, maxit);
+        live[q] = 1;
+        return run_begin(runs[q], 0);
+    };
+    for (int q = 0; q < count; ++q) {
+        st = start_next(q);
+        if (st) return st;
+    }
+    for (;;) {
+        bool any = false;
+        for (int q = 0; q < count; ++q) {
+            if (!live[q]) continue;
+            any = true;
+            SolveRun &R = runs[q];
+            if (R.inflight < 2) {
+                st = run_issue(R);
+                if (st) return st;
+            }
+        }
+        if (!any) break;
+        for (int q = 0; q < count; ++q) {
+            if (!live[q]) continue;
+            SolveRun &R = runs[q];
+            if (R.inflight < 2) continue;
+            int e = (R.issued - 2) & 1;
+            HIPCHK(hipEventSynchronize(R.ev[e]));
+            R.inflight--;
+            bool over = R.issued > R.maxit + 4;
+            if (R.hs[e].done || over) {
+                Item it = per_grid[q].front();
+                hmg_solve_info *inf = (info && info[q]) ? &info[q][it.r] : nullptr;
+                hmg_status sr = run_finish(R, inf);
+                if (sr == HMG_PENDING && !over) continue;
+                if (sr == HMG_PENDING) sr = HMG_ERR_NOT_CONVERGED;
+                if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED) return sr;
+                if (sr != HMG_OK) worst = sr;
+                size_t m0 = (size_t)grids[q]->lev[0].geo.M * grids[q]->lev[0].geo.M;
+                HIPCHK(hipMemcpy(x[q] + m0 * it.r, R.S->K.x, m0 * 16, hipMemcpyDeviceToHost));
+                per_grid[q].pop_front();
+                st = start_next(q);
+                if (st) return st;
+            }
+        }
+    }
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
+// request server (continuous batching)
+// ---------------------------------------------------------------------------
+struct Request {
+    uint64_t            ticket = 0;
+    int                 n = 0;
+    double              h = 0.0;
+    std::vector<double> k;
+    std::vector<hmg_c64> f;
+    hmg_opts            opts{};
+    double              rtol = 1e-6;
+    int                 maxit = 100;
+    size_t              footprint = 0;
+    int                 state = 0;      // 0 queued, 1 active, 2 finished
+    bool                cancel = false;
+    hmg_grid           *grid = nullptr;
+    SolveRun            run;
+    hmg_result          result{};
+    std::vector<hmg_c64> x;
+};
+
+static void retire(hmg_ctx *ctx, Request *q, hmg_status status) {
+    ServerState &S = *ctx->server;
+    if (q->grid) {
+        if (status == HMG_OK || status == HMG_ERR_NOT_CONVERGED) {
+            size_t m0 = (size_t)(q->n + 2) * (q->n + 2);
+            q->x.resize(m0);
+            if (hipMemcpy(q->x.data(), q->grid->slot[0].K.x, m0 * 16, hipMemcpyDeviceToHost) != hipSuccess)
+                status = HMG_ERR_DEVICE;
+        }
+        hmg_grid_destroy(q->grid);
+        q->grid = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (q->state == 1) S.used -= q->footprint;
+    q->state = 2;
+    q->result.status = status;
+    q->result.t_done = hmg_now() - ctx->t0;
+    q->result.footprint_bytes = q->footprint;
+    S.active.erase(std::remove(S.active.begin(), S.active.end(), q), S.active.end());
+    S.cv.notify_all();
+}
+
+static void server_loop(hmg_ctx *ctx) {
+    ServerState &S = *ctx->server;
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        std::vector<Request *> admit;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            S.cv.wait(lk, [&] { return S.quit || !S.queue.empty() || !S.active.empty(); });
+            if (S.quit) return;
+            while (!S.queue.empty()) {
+                Request *q = S.queue.front();
+                if (q->cancel) {
+                    S.queue.pop_front();
+                    q->state = 2;
+                    q->result.status = HMG_ERR_CANCELLED;
+                    q->result.t_done = hmg_now() - ctx->t0;
+                    S.cv.notify_all();
+                    continue;
+                }
+                bool fits = S.used + q->footprint <= ctx->budget;
+                bool slot_ok = S.max_active <= 0 || (int)(S.active.size() + admit.size()) < S.max_active;
+                if (!fits || !slot_ok) break;
+                S.queue.pop_front();
+                S.used += q->footprint;
+                q->state = 1;
+                q->result.t_admit = hmg_now() - ctx->t0;
+                admit.push_back(q);
+            }
+        }
+        for (Request *q : admit) {
+            hmg_status st = hmg_grid_create(ctx, q->n, q->h, q->k.data(), q->f.data(), 1, &q->opts, &q->grid);
+            if (st == HMG_OK) {
+                run_init(q->run, q->grid, &q->grid->slot[0], q->grid->stream, q->rtol, q->maxit);
+                st = run_begin(q->run, 0);
+            }
+            std::lock_guard<std::mutex> lk(S.mu);
+            if (st != HMG_OK) {
+                S.used -= q->footprint;
+                q->state = 2;
+                q->result.status = st;
+                q->result.t_done = hmg_now() - ctx->t0;
+                if (q->grid) hmg_grid_destroy(q->grid);
+                q->grid = nullptr;
+                S.cv.notify_all();
+            } else {
+                S.active.push_back(q);
+            }
+        }
+        std::vector<Request *> act;
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            act = S.active;
+        }
+        // queue up to two iterations per active solve, then observe the
+        // oldest one of each; the streams of different requests overlap
+        for (Request *q : act)
+            while (q->run.inflight < 2 && !q->cancel) {
+                if (run_issue(q->run) != HMG_OK) break;
+            }
+        for (Request *q : act) {
+            SolveRun &R = q->run;
+            if (q->cancel) {
+                (void)hipStreamSynchronize(R.s);
+                retire(ctx, q, HMG_ERR_CANCELLED);
+                continue;
+            }
+            if (R.inflight == 0) continue;
+            int e = (R.issued - R.inflight) & 1;
+            if (hipEventSynchronize(R.ev[e]) != hipSuccess) {
+                retire(ctx, q, HMG_ERR_DEVICE);
+                continue;
+            }
+            R.inflight--;
+            bool over = R.issued > R.maxit + 4;
+            if (R.hs[e].done || over) {
+                hmg_solve_info inf{};
+                hmg_status st = run_finish(R, &inf);
+                if (st == HMG_PENDING && !over) continue;
+                if (st == HMG_PENDING) st = HMG_ERR_NOT_CONVERGED;
+                q->result.iters = inf.iters;
+                q->result.rel_res_true = inf.rel_res_true;
+                retire(ctx, q, st);
+            }
+        }
+    }
+}
+
+static void server_start(hmg_ctx *ctx) {
+    ServerState &S = *ctx->server;
+    if (S.running) return;
+    S.running = true;
+    S.quit = false;
+    S.worker = std::thread(server_loop, ctx);
+}
+
+static void server_stop(hmg_ctx *ctx) {
+    if (!ctx->server) return;
+    ServerState &S = *ctx->server;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.quit = true;
+        S.cv.notify_all();
+    }
+    if (S.worker.joinable()) S.worker.join();
+    S.running = false;
+    for (auto &kv : S.all) {
+        Request *q = kv.second;
+        if (q->grid) hmg_grid_destroy(q->grid);
+        delete q;
+    }
+    S.all.clear();
+    S.queue.clear();
+    S.active.clear();
+}
+
+extern "C" hmg_status hmg_submit(hmg_ctx *ctx, const hmg_request *req, uint64_t *ticket) {
+    if (!ctx || !req || !ticket || !req->k) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    hmg_status st = check_solve_args(req->rtol, req->maxit);
+    if (st) return st;
+    int nc = req->opts.coarsest_n;
+    unsigned v = (unsigned)req->n + 1;
+    if (req->n < 1 || (v & (v - 1)) != 0 || req->n < nc || !(req->h > 0.0))
+        return hmg_fail(HMG_ERR_INVALID, "bad grid size or spacing");
+    size_t m0 = (size_t)(req->n + 2) * (req->n + 2);
+    Request *q = new Request();
+    q->n = req->n;
+    q->h = req->h;
+    q->k.assign(req->k, req->k + m0);
+    if (req->f) q->f.assign(req->f, req->f + m0);
+    else q->f.assign(m0, hmg_c64{0.0, 0.0});
+    q->opts = req->opts;
+    q->rtol = req->rtol;
+    q->maxit = req->maxit;
+    q->footprint = estimate_footprint(req->n, req->opts) + (size_t)(2 * req->maxit + 2) * 8;
+    q->result.t_arrive = hmg_now() - ctx->t0;
+    if (q->footprint > ctx->budget) {
+        size_t need = q->footprint;
+        delete q;
+        return hmg_fail(HMG_ERR_TOO_LARGE, "request needs %zu bytes, budget is %zu", need, ctx->budget);
+    }
+    ServerState &S = *ctx->server;
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (!S.running) server_start(ctx);
+    q->ticket = S.next_ticket++;
+    S.all[q->ticket] = q;
+    S.queue.push_back(q);
+    *ticket = q->ticket;
+    S.cv.notify_all();
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_poll(hmg_ctx *ctx, uint64_t ticket, hmg_c64 *x_out, hmg_result *res) {
+    if (!ctx) return hmg_fail(HMG_ERR_INVALID, "null context");
+    ServerState &S = *ctx->server;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(ticket);
+    if (it == S.all.end()) return hmg_fail(HMG_ERR_UNKNOWN_TICKET, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *q = it->second;
+    if (q->state != 2) {
+        if (res) {
+            *res = q->result;
+            res->status = HMG_PENDING;
+        }
+        return HMG_PENDING;
+    }
+    if (res) *res = q->result;
+    if (x_out && !q->x.empty()) std::memcpy(x_out, q->x.data(), q->x.size() * sizeof(hmg_c64));
+    hmg_status st = (hmg_status)q->result.status;
+    S.all.erase(it);
+    delete q;
+    return st;
+}
+
+extern "C" hmg_status hmg_cancel(hmg_ctx *ctx, uint64_t ticket) {
+    if (!ctx) return hmg_fail(HMG_ERR_INVALID, "null context");
+    ServerState &S = *ctx->server;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto it = S.all.find(ticket);
+    if (it == S.all.end()) return hmg_fail(HMG_ERR_UNKNOWN_TICKET, "unknown ticket");
+    it->second->cancel = true;
+    S.cv.notify_all();
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_ctx_set_max_active(hmg_ctx *ctx, int max_active) {
+    if (!ctx || max_active < 0) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    std::lock_guard<std::mutex> lk(ctx->server->mu);
+    ctx->server->max_active = max_active;
+    return HMG_OK;
+}

@@ -1,0 +1,68 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+that include/hmg.h declares, and rejects bad arguments before touching a
+device.  No kernel runs here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(hmg_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary_calls():
+    names = declared_functions()
+    for required in ("hmg_grid_create", "hmg_vcycle", "hmg_solve", "hmg_solve_batch",
+                     "hmg_submit", "hmg_poll", "hmg_cancel"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1312_2880_amd import hmg
+    lib = ctypes.CDLL(hmg.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(hmg.EXPORTED)
+
+
+def test_oracle_is_not_linked_into_the_library():
+    from paper_1312_2880_amd import hmg
+    lib = ctypes.CDLL(hmg.LIB_PATH)
+    assert not hasattr(lib, "orc_vcycle")
+    src = os.path.join(ROOT, "paper_1312_2880_amd")
+    for dirpath, _, files in os.walk(src):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "hmg_oracle" not in text, fn
+
+
+def test_defaults_are_the_papers_constants():
+    from paper_1312_2880_amd import hmg
+    o = hmg.opts()
+    assert o.beta == 0.5                      # eq:mh, beta = 0.5
+    assert (o.nu_pre, o.nu_post) == (1, 1)    # V(1,1) smoothing
+    assert (o.kacz_pre, o.kacz_post) == (4, 4)
+    assert o.variant == hmg.HYB and o.coarsest_n == 7
+
+
+def test_null_arguments_are_rejected():
+    from paper_1312_2880_amd import hmg
+    lib = hmg._lib
+    out = ctypes.c_void_p()
+    k = np.ones((9, 9))
+    assert lib.hmg_grid_create(None, 7, 0.125, hmg._ptr(k), None, 1, None,
+                               ctypes.byref(out)) == hmg.ERR_INVALID
+    assert lib.hmg_vcycle(None, None, None) == hmg.ERR_INVALID
+    assert lib.hmg_solve(None, None, 1e-6, 10, None) == hmg.ERR_INVALID
+    assert lib.hmg_poll(None, 1, None, None) == hmg.ERR_INVALID
+    assert b"null" in lib.hmg_last_error()
