@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1312_2880_amd", "csrc", "hmg_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1312_2880_amd", "csrc", "hmg_fused.hip")
 
 
 def kernel_source_hash() -> str:
@@ -32,63 +32,63 @@ def kernel_source_hash() -> str:
 
 
 def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rbytes: int) -> float:
-    """Bytes the method must move per launch (each array touched once).
-    Per node: c = complex size, r = real size of the level precision.
-      gs_sweep        one red-black sweep: read f, k, u, write u   3c + r
-      kacz_sweep      one 5-colour sweep (minimum): 3c + r
-      residual_fw     read u, f, k; write coarse f                2c + r (+ c per coarse node)
-      prolong         read coarse e, u; write u                   2c (+ c per coarse node)
+    """Bytes the method must move per launch, every array touched once
+    (c = complex size, r = real size of the level precision; per fine node,
+    plus c per coarse node where a coarse field is read or written):
+      gs_down     read f, k; write coarse f                N (c + r) + Nc c
+      gs_up       read f, k, coarse e; write u              N (2c + r) + Nc c
+    (the pre-smoothed iterate is recomputed on chip, never stored)
     """
     c, r = cbytes, rbytes
-    if kind in ("gs_sweep", "kacz_sweep"):
-        return nodes * (3 * c + r)
-    if kind == "residual_fw":
+    if kind == "gs_down":
+        return nodes * (c + r) + coarse_nodes * c
+    if kind == "gs_up":
         return nodes * (2 * c + r) + coarse_nodes * c
-    if kind == "prolong":
-        return nodes * 2 * c + coarse_nodes * c
     raise KeyError(kind)
 
 
-def time_kernels(hmg, torch, g, plan, precision, reps=50):
-    """Average launch duration of each finest-level V-cycle kernel, timed with
-    torch events on torch's current stream, which the library launches on."""
-    import numpy as np
-    stream = torch.cuda.current_stream()
+def time_kernels(hmg, torch, g, plan, precision, reps=96, sets=24):
+    """Average launch duration of the finest-level V-cycle kernels, timed with
+    torch events on torch's current stream (the library launches on the
+    stream it is given).  Launches cycle through `sets` independent buffer
+    sets (about 1 GB in total) so that each one reads its inputs from HBM, not
+    from the Infinity Cache."""
+    # a dedicated stream: torch's default stream has the NULL handle, which the
+    # library reads as "the grid's own stream", and events on it would not
+    # bracket the kernels
+    stream = torch.cuda.Stream()
     cdt = torch.complex128 if precision == "fp64" else torch.complex64
     cb, rb = (16, 8) if precision == "fp64" else (8, 4)
-    out = {}
-    lev = 0
-    n0 = plan[lev]["n"]
-    nc = plan[lev + 1]["n"] if len(plan) > 1 else n0
+    n0, nc = plan[0]["n"], plan[1]["n"]
     nodes, cnodes = (n0 + 2) ** 2, (nc + 2) ** 2
     gen = torch.Generator(device="cuda").manual_seed(0)
-    f = torch.randn((n0 + 2, n0 + 2), dtype=cdt, device="cuda", generator=gen)
-    u = torch.randn((n0 + 2, n0 + 2), dtype=cdt, device="cuda", generator=gen)
-    fc = torch.zeros((nc + 2, nc + 2), dtype=cdt, device="cuda")
-    sig_a, sig_b = plan[lev]["sigma_relax"], plan[lev]["sigma_resid"]
-    sm = plan[lev]["smoother"]
+
+    def field(n):
+        return torch.randn((n + 2, n + 2), dtype=cdt, device="cuda", generator=gen)
+
+    bufs = [dict(f=field(n0), uo=field(n0), ec=field(nc), fc=field(nc))
+            for _ in range(sets)]
+    torch.cuda.synchronize()
+    sa, sb = plan[0]["sigma_relax"], plan[0]["sigma_resid"]
     cases = {
-        "gs_sweep": (lambda: g.op_smooth(lev, hmg.SM_GS, sig_a, 1, 0, f, u, stream), 2),
-        "residual_fw": (lambda: g.op_restrict(lev, sig_b, f, u, fc, stream), 1),
-        "prolong": (lambda: g.op_prolong(lev, fc, u, stream), 1),
+        "gs_down": lambda b: g.op_gs_down(0, sa, sb, b["f"], None, b["fc"], stream),
+        "gs_up": lambda b: g.op_gs_up(0, sa, b["f"], b["ec"], b["uo"], stream),
     }
-    if sm == "KACZ":
-        cases = {"kacz_sweep": (lambda: g.op_smooth(lev, hmg.SM_KACZ, sig_a, 1, 0, f, u, stream), 5),
-                 **{k: v for k, v in cases.items() if k != "gs_sweep"}}
-    for name, (fn, launches) in cases.items():
-        for _ in range(3):
-            fn()
+    out = {}
+    for name, fn in cases.items():
+        for q in range(sets):
+            fn(bufs[q])
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(reps):
-            fn()
+        for q in range(reps):
+            fn(bufs[q % sets])
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         b = algorithmic_bytes(name, nodes, cnodes, cb, rb)
-        out[name] = dict(ms_per_call=ms, launches_per_call=launches, bytes=b,
-                         gbs=b / (ms * 1e-3) / 1e9, level=lev, nodes=nodes)
+        out[name] = dict(ms_per_launch=ms, bytes=b, gbs=b / (ms * 1e-3) / 1e9, nodes=nodes)
+    del bufs
     return out
 
 
@@ -152,14 +152,10 @@ def main():
     ok = all(i["status"] == hmg.OK and i["rel_res_true"] <= 1e-6 for i in infos)
 
     kt = time_kernels(hmg, torch, g, plan, args.precision)
-    # dominant kernel: largest time per V-cycle at the finest level
-    per_v = {name: d["ms_per_call"] * (plan[0]["pre"] + plan[0]["post"] if "sweep" in name else 1)
-             for name, d in kt.items()}
-    dom = max(per_v, key=per_v.get)
+    # dominant V-cycle kernel: the finest-level kernel with the longest launch
+    dom = max(kt, key=lambda name: kt[name]["ms_per_launch"])
     d = kt[dom]
-    per_launch_ms = d["ms_per_call"] / d["launches_per_call"]
-    bytes_per_launch = d["bytes"] / d["launches_per_call"]
-    achieved = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    achieved = d["gbs"]
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -172,8 +168,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "level_nodes": d["nodes"],
-                "ms_per_launch": round(per_launch_ms, 5),
-                "bytes_per_launch": bytes_per_launch}
+                "ms_per_launch": round(d["ms_per_launch"], 5),
+                "bytes_per_launch": d["bytes"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -200,8 +196,7 @@ def main():
                    "all_converged": ok,
                    "levels": [(p["n"], p["smoother"]) for p in plan]},
         "roofline": roofline,
-        "kernels": {name: {"ms_per_call": round(v["ms_per_call"], 5),
-                           "launches_per_call": v["launches_per_call"],
+        "kernels": {name: {"ms_per_launch": round(v["ms_per_launch"], 5),
                            "gbs": round(v["gbs"], 1)} for name, v in kt.items()},
         "cpu_baseline": cpu,
     }

@@ -80,7 +80,13 @@ typedef struct {
     int    kacz_band;        /* 1: Kaczmarz on the kH ~ 1.25 levels (default)     */
     int    coarsest_n;       /* interior size of the dense-LU level, default 7    */
     int    use_graph;        /* 1: replay each Bi-CGSTAB iteration as a hipGraph  */
-    int    reserved[7];
+    int    one_pass_kernels; /* 1: one kernel launch per colour pass / transfer
+                                (reference schedule); 0: fused LDS-tiled kernels
+                                and the single-workgroup bottom solver (default) */
+    int    autotune;         /* 1: time the Kaczmarz tile configurations on the
+                                level's shape at grid creation (cached per
+                                process); 0: fixed default                      */
+    int    reserved[5];
 } hmg_opts;
 
 #define HMG_MAX_LEVELS 24
@@ -165,6 +171,12 @@ hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void *d_x,
                          int x0_given, double rtol, int maxit,
                          hmg_solve_info *info, void *stream);
 
+/* Relative residuals ||r|| / ||b|| of the last solve of right-hand side
+ * `rhs`, one per half iteration (entry 0 = the initial residual): copies up
+ * to cap values into out and returns how many the solve produced (-1 on
+ * error). */
+int        hmg_solve_history(hmg_grid *g, int rhs, double *out, int cap);
+
 /* ---- batching: many grids and right-hand sides in one launch plan ----------
  * Solves every right-hand side of every grid (zero initial guess); x[q] holds
  * grids[q]'s nrhs solutions, info[q] its nrhs infos (NULL allowed). */
@@ -230,6 +242,30 @@ hmg_status hmg_op_restrict_dev(hmg_grid *g, int level, double sigma, const void 
 hmg_status hmg_op_prolong_dev(hmg_grid *g, int level, const void *d_ec, void *d_u,
                               void *stream);
 hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_u, void *stream);
+
+/* Fused kernels of the default schedule (Section 5), same conventions:
+ *   gs_down:     u0 = one red-black sweep on A_{sigma_relax} u = f from u = 0,
+ *                fc = R (f - A_{sigma_resid} u0)        (pre-smoothing + restriction);
+ *                u0 is written to d_u only when d_u != NULL
+ *   gs_up:       uo = one red-black sweep on A_{sigma_relax} starting from
+ *                u0 + P ec, with u0 the iterate of gs_down recomputed from f
+ *                                                        (correction + post-smoothing)
+ *   kacz_tiled:  uo = S 5-colour Kaczmarz sweeps starting from ui (NULL: zero)
+ *                plus P ec (NULL: none); S and the tile side are those of tile
+ *                configuration `config` (hmg_kacz_tile_config).
+ * Outputs must not alias inputs (tiles read their neighbours' inputs). */
+hmg_status hmg_op_gs_down_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid,
+                              const void *d_f, void *d_u, void *d_fc, void *stream);
+hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_relax, const void *d_f,
+                            const void *d_ec, void *d_uo, void *stream);
+hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int config, const void *d_f,
+                                 const void *d_ui, const void *d_ec, void *d_uo, void *stream);
+/* Tile configuration chosen for a Kaczmarz level of the grid (-1: the level
+ * is not relaxed by the tiled kernel). */
+int        hmg_grid_kacz_config(const hmg_grid *g, int level);
+/* Tile side and sweeps per launch of Kaczmarz tile configuration `config`;
+ * returns the number of configurations, or -1 for an unknown one. */
+int        hmg_kacz_tile_config(int config, int *tile, int *sweeps);
 
 #ifdef __cplusplus
 }

@@ -62,6 +62,8 @@ extern "C" void hmg_opts_default(hmg_opts *o) {
     o->kacz_band = 1;
     o->coarsest_n = 7;
     o->use_graph = 1;
+    o->one_pass_kernels = 0;
+    o->autotune = 1;
 }
 
 // Level classification (Section 5).  The paper states its rules on grids
@@ -225,9 +227,9 @@ static void layout(hmg_grid *g, Carver &c) {
         Slot &S = g->slot[s];
         for (int l = 0; l < g->nlev; ++l) {
             size_t m = (size_t)g->lev[l].geo.M * g->lev[l].geo.M;
-            bool own = (l > 0) || (g->prec == P32);
-            S.f[l] = own ? c.take(m * csz) : nullptr;
-            S.u[l] = own ? c.take(m * csz) : nullptr;
+            S.f[l] = c.take(m * csz);
+            S.u[l] = c.take(m * csz);
+            S.u2[l] = c.take(m * csz);
         }
         Krylov &K = S.K;
         double **vecs[] = {&K.b, &K.x, &K.r, &K.rh, &K.p, &K.v, &K.s, &K.t, &K.ph, &K.sh};
@@ -238,6 +240,172 @@ static void layout(hmg_grid *g, Carver &c) {
         K.hist = nullptr;
         K.st = (KState *)c.take(sizeof(KState));
     }
+}
+
+// Kernel schedule per level.  The bottom solver takes the deepest levels
+// whose fields (u on every level, f below its first level) fit in the LDS of
+// one workgroup; above it, Gauss-Seidel levels with one pre- and one post-
+// sweep use the fused down/up kernels and Kaczmarz levels the tiled kernel.
+static void plan_paths(hmg_grid *g) {
+    g->lb = -1;
+    for (int l = 0; l < g->nlev; ++l) {
+        g->lev[l].mode = LM_SIMPLE;
+        g->lev[l].kacz_cfg = 0;
+    }
+    if (g->opts.one_pass_kernels) return;
+    // the bottom solver keeps u, f and k of each of its levels in LDS and is
+    // used for levels with n <= 31
+    for (int l = 0; l < g->nlev; ++l) {
+        if (g->nlev - l > BOT_MAXL || g->lev[l].geo.n > 31) continue;
+        int cs = 0, rs = 0;
+        for (int q = l; q < g->nlev; ++q) {
+            int m = g->lev[q].geo.M * g->lev[q].geo.M;
+            cs += 2 * m;
+            rs += 2 * m;   // k and a reciprocal per node
+        }
+        if (cs <= bottom_complex_slots() && rs <= bottom_real_slots()) {
+            g->lb = l;
+            break;
+        }
+    }
+    int top = (g->lb < 0) ? g->nlev - 1 : g->lb;
+    for (int l = 0; l < top; ++l) {
+        const hmg_plan &pl = g->plan;
+        if (pl.smoother[l] == HMG_SM_GS && pl.pre[l] == 1 && pl.post[l] == 1) {
+            g->lev[l].mode = LM_GS_FUSED;
+        } else if (pl.smoother[l] == HMG_SM_KACZ) {
+            g->lev[l].mode = LM_KACZ_TILED;
+            // default before tuning: the LDS-staged tile with 2 sweeps per
+            // launch if it divides both sweep counts, else one sweep per launch
+            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? 2 : 0;
+            g->lev[l].kacz_cfg = best;
+        }
+    }
+}
+
+static void bottom_desc(hmg_grid *g) {
+    if (g->lb < 0) return;
+    BottomDesc &d = g->bottom;
+    d.nlev = g->nlev - g->lb;
+    d.ainv_t = g->ainv_t;
+    int off = 0;
+    for (int q = 0; q < d.nlev; ++q) {
+        int l = g->lb + q;
+        BottomLevelDesc &D = d.L[q];
+        D.n = g->lev[l].geo.n;
+        D.H = g->lev[l].geo.H;
+        D.sa = g->plan.sigma_relax[l];
+        D.sb = g->plan.sigma_resid[l];
+        D.k = g->lev[l].k;
+        D.sm = (g->plan.smoother[l] == HMG_SM_KACZ) ? HMG_SM_KACZ_DEV : HMG_SM_GS_DEV;
+        D.pre = g->plan.pre[l];
+        D.post = g->plan.post[l];
+        D.uoff = off;
+        off += (D.n + 2) * (D.n + 2);
+    }
+    for (int q = 0; q < d.nlev; ++q) {
+        BottomLevelDesc &D = d.L[q];
+        D.foff = off;
+        off += (D.n + 2) * (D.n + 2);
+    }
+    int koff = 0;
+    for (int q = 0; q < d.nlev; ++q) {
+        BottomLevelDesc &D = d.L[q];
+        D.koff = koff;
+        koff += 2 * (D.n + 2) * (D.n + 2);   // k, then the reciprocals
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile-configuration tuner for the tiled Kaczmarz kernel: every feasible
+// configuration runs one relaxation leg (pre sweeps, ping-ponging between the
+// level's two buffers) on the level's own shape; the fastest is kept.  The
+// choice is cached per (device, n, precision, sweep counts) for the process.
+// ---------------------------------------------------------------------------
+#include <map>
+#include <mutex>
+#include <tuple>
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;
+
+static hmg_status tune_kacz_level(hmg_grid *g, int l) {
+    const hmg_plan &pl = g->plan;
+    auto key = std::make_tuple(g->ctx->device, g->lev[l].geo.n, (int)g->prec, pl.pre[l], pl.post[l]);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            g->lev[l].kacz_cfg = it->second;
+            return HMG_OK;
+        }
+    }
+    std::vector<int> cand;
+    for (int cfg = 0; cfg < KACZ_NCFG; ++cfg) {
+        int sw = kKaczCfgs[cfg].sweeps;
+        if (kacz_cfg_fits(g->prec, cfg) && pl.pre[l] % sw == 0 && pl.post[l] % sw == 0) cand.push_back(cfg);
+    }
+    if (cand.size() > 1 && pl.pre[l] > 0) {
+        const Level &L = g->lev[l];
+        Slot &S = g->slot[0];
+        size_t bytes = (size_t)L.geo.M * L.geo.M * (g->prec == P64 ? 16 : 8);
+        HIPCHK(hipMemsetAsync(S.f[l], 0, bytes, g->stream));
+        HIPCHK(hipMemsetAsync(S.u[l], 0, bytes, g->stream));
+        HIPCHK(hipMemsetAsync(S.u2[l], 0, bytes, g->stream));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        int best = g->lev[l].kacz_cfg;
+        for (int cfg : cand) {
+            int sw = kKaczCfgs[cfg].sweeps;
+            auto leg = [&]() {
+                const void *cur = nullptr;
+                void *bufs[2] = {S.u[l], S.u2[l]};
+                int w = 0;
+                for (int q = 0; q < pl.pre[l]; q += sw) {
+                    launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l], S.f[l], cur, nullptr,
+                                   bufs[w], nullptr);
+                    cur = bufs[w];
+                    w ^= 1;
+                }
+            };
+            leg();
+            HIPCHK(hipEventRecord(e0, g->stream));
+            for (int r = 0; r < 3; ++r) leg();
+            HIPCHK(hipEventRecord(e1, g->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cfg;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        g->lev[l].kacz_cfg = best;
+    } else if (cand.size() == 1) {
+        g->lev[l].kacz_cfg = cand[0];
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = g->lev[l].kacz_cfg;
+    return HMG_OK;
+}
+
+static hmg_status tune_levels(hmg_grid *g) {
+    if (!g->opts.autotune) return HMG_OK;
+    for (int l = 0; l < g->nlev; ++l)
+        if (g->lev[l].mode == LM_KACZ_TILED) {
+            hmg_status st = tune_kacz_level(g, l);
+            if (st) return st;
+        }
+    return HMG_OK;
+}
+
+extern "C" int hmg_grid_kacz_config(const hmg_grid *g, int level) {
+    if (!g || level < 0 || level >= g->nlev || g->lev[level].mode != LM_KACZ_TILED) return -1;
+    return g->lev[level].kacz_cfg;
 }
 
 // Device bytes of a grid of size n with options o (sizes do not depend on k).
@@ -329,6 +497,7 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
         return hmg_fail(HMG_ERR_INVALID, "coarsest operator is singular");
     }
 
+    plan_paths(g);
     g->slot.resize(nrhs);
     Carver sizer;
     layout(g, sizer);
@@ -342,7 +511,9 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     Carver c;
     c.base = g->mem;
     layout(g, c);
+    bottom_desc(g);
     hmg_status st = grid_init_device(g, kl, inv, f);
+    if (st == HMG_OK) st = tune_levels(g);
     if (st != HMG_OK) {
         hmg_grid_destroy(g);
         return st;
@@ -447,8 +618,83 @@ static void vcycle_level(hmg_grid *g, Slot &S, int l, const void *f, void *u, hi
     relax(g, l, f, u, g->plan.post[l], false, s, skip);
 }
 
+// Fused schedule of levels l.. on right-hand side f.  The result goes to
+// `out` when given (else to a level buffer, whose pointer is returned).  f64
+// marks the FP64 level-0 input / output of the mixed precision.
+static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64, void *out, hipStream_t s,
+                           const int *skip) {
+    const Level &L = g->lev[l];
+    const hmg_plan &pl = g->plan;
+    if (l == g->lb) {
+        void *dst = out ? out : S.u[l];
+        launch_bottom(g->prec, f64, s, g->bottom, f, dst, skip);
+        return dst;
+    }
+    if (L.mode == LM_GS_FUSED) {
+        launch_gs_down(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, nullptr,
+                       S.f[l + 1], skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+        void *dst = out ? out : S.u2[l];
+        launch_gs_up(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, e, dst, skip);
+        return dst;
+    }
+    size_t m = (size_t)L.geo.M * L.geo.M;
+    if (L.mode == LM_KACZ_TILED) {
+        int cfg = L.kacz_cfg, sw = kKaczCfgs[cfg].sweeps;
+        double sig = pl.sigma_relax[l];
+        void *bufs[2] = {S.u[l], S.u2[l]};
+        const void *cur = nullptr;
+        int w = 0;
+        for (int q = 0; q < pl.pre[l]; q += sw) {
+            launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, sig, f, cur, nullptr, bufs[w], skip);
+            cur = bufs[w];
+            w ^= 1;
+        }
+        if (!cur) {
+            launch_fill_zero(g->prec, s, bufs[w], m, skip);
+            cur = bufs[w];
+            w ^= 1;
+        }
+        launch_residual_fw(g->prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+        if (pl.post[l] == 0) {
+            launch_prolong_add(g->prec, s, L.geo, e, (void *)cur, skip);
+        }
+        for (int q = 0; q < pl.post[l]; q += sw) {
+            launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip);
+            cur = bufs[w];
+            w ^= 1;
+        }
+        if (out) {
+            (void)hipMemcpyAsync(out, cur, m * (g->prec == P64 ? 16 : 8), hipMemcpyDeviceToDevice, s);
+            return out;
+        }
+        return cur;
+    }
+    // one-pass kernels, in place
+    void *u = out ? out : S.u[l];
+    relax(g, l, f, u, pl.pre[l], true, s, skip);
+    launch_residual_fw(g->prec, s, L.geo, L.k, pl.sigma_resid[l], f, u, S.f[l + 1], skip);
+    const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+    launch_prolong_add(g->prec, s, L.geo, e, u, skip);
+    relax(g, l, f, u, pl.post[l], false, s, skip);
+    return u;
+}
+
 // z = B_V r on FP64 device fields r, z (finest level).
 void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip) {
+    if (!g->opts.one_pass_kernels) {
+        bool mixed = g->prec == P32;
+        if (!mixed || g->lb == 0 || g->lev[0].mode == LM_GS_FUSED) {
+            vc_fast(g, S, 0, r, mixed, z, s, skip);
+        } else {
+            size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+            launch_convert(s, 1, r, S.f[0], m0, skip);
+            const void *res = vc_fast(g, S, 0, S.f[0], false, nullptr, s, skip);
+            launch_convert(s, 0, res, z, m0, skip);
+        }
+        return;
+    }
     if (g->prec == P64) {
         vcycle_level(g, S, 0, r, z, s, skip);
     } else {
@@ -463,6 +709,7 @@ static hipStream_t pick_stream(hmg_grid *g, void *stream) { return stream ? (hip
 
 extern "C" hmg_status hmg_vcycle_dev(hmg_grid *g, const void *d_r, void *d_z, void *stream) {
     if (!g || !d_r || !d_z) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    if (d_r == d_z) return hmg_fail(HMG_ERR_INVALID, "r and z must not alias");
     HIPCHK(hipSetDevice(g->ctx->device));
     hipStream_t s = pick_stream(g, stream);
     enqueue_vcycle(g, g->slot[0], (const double *)d_r, (double *)d_z, s, nullptr);
@@ -555,4 +802,50 @@ extern "C" hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_
     launch_coarsest(g->prec, pick_stream(g, stream), L.geo.M * L.geo.M, g->ainv_t, d_f, d_u, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_gs_down_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid,
+                                         const void *d_f, void *d_u, void *d_fc, void *stream) {
+    hmg_status st = check_level(g, level, true);
+    if (st) return st;
+    if (!d_f || !d_fc || d_u == d_f || d_fc == d_f) return hmg_fail(HMG_ERR_INVALID, "bad fields");
+    const Level &L = g->lev[level];
+    launch_gs_down(g->prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, sigma_resid, d_f, d_u, d_fc,
+                   nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_relax, const void *d_f,
+                                       const void *d_ec, void *d_uo, void *stream) {
+    hmg_status st = check_level(g, level, true);
+    if (st) return st;
+    if (!d_f || !d_ec || !d_uo || d_uo == d_f || d_uo == d_ec)
+        return hmg_fail(HMG_ERR_INVALID, "bad fields (the output must not alias an input)");
+    const Level &L = g->lev[level];
+    launch_gs_up(g->prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, d_f, d_ec, d_uo, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int config, const void *d_f,
+                                            const void *d_ui, const void *d_ec, void *d_uo, void *stream) {
+    hmg_status st = check_level(g, level, false);
+    if (st) return st;
+    if (config < 0 || config >= KACZ_NCFG || !kacz_cfg_fits(g->prec, config))
+        return hmg_fail(HMG_ERR_INVALID, "tile configuration %d not available", config);
+    if (!d_f || !d_uo || d_uo == d_ui || d_uo == d_f || d_uo == d_ec)
+        return hmg_fail(HMG_ERR_INVALID, "bad fields (the output must not alias an input)");
+    if (d_ec && level >= g->nlev - 1) return hmg_fail(HMG_ERR_INVALID, "no coarser level");
+    const Level &L = g->lev[level];
+    launch_kacz_tb(g->prec, config, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_ui, d_ec, d_uo, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" int hmg_kacz_tile_config(int config, int *tile, int *sweeps) {
+    if (config < 0 || config >= KACZ_NCFG) return -1;
+    if (tile) *tile = kKaczCfgs[config].ts;
+    if (sweeps) *sweeps = kKaczCfgs[config].sweeps;
+    return KACZ_NCFG;
 }

@@ -1,0 +1,100 @@
+// hmg_device.h -- device-side helpers shared by the kernel translation units
+// of libhmg: complex arithmetic in the level precision and the rows of the
+// discrete operator.
+//
+// Discrete operator (Section 1, eq:diff / eq:disc / eq:mh), for node p =
+// (i, j) on a level with spacing H and N = n+1 intervals:
+//   a_pp = (-4 + 2 i k_p H b_p) / H^2 + k_p^2 (1 + i sigma)
+//   a_pq = w_pq / H^2,  w_pq = 2 for the inward neighbour across a boundary
+//                       face of p, 1 otherwise,
+// with b_p the number of boundary faces of p.  This is the 5-point stencil
+// with the Sommerfeld condition du/dn - i k u = 0 closed by central-
+// difference ghost points; sigma = 0 gives L, sigma = beta gives M.
+#pragma once
+
+#include "hmg_internal.h"
+
+namespace hmgk {
+
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) C {
+    T x, y;
+};
+
+template <typename T> __device__ __forceinline__ C<T> cmk(T a, T b) { C<T> z; z.x = a; z.y = b; return z; }
+template <typename T> __device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return cmk(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return cmk(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ C<T> cscale(T s, C<T> a) { return cmk(s * a.x, s * a.y); }
+template <typename T> __device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a / (dre + i dim)
+template <typename T> __device__ __forceinline__ C<T> cdiv(C<T> a, T dre, T dim) {
+    T inv = T(1) / (dre * dre + dim * dim);
+    return cmk((a.x * dre + a.y * dim) * inv, (a.y * dre - a.x * dim) * inv);
+}
+
+// a / (dre + i dim) with inv = 1 / (dre^2 + dim^2) computed by the caller
+template <typename T> __device__ __forceinline__ C<T> cdivr(C<T> a, T dre, T dim, T inv) {
+    return cmk((a.x * dre + a.y * dim) * inv, (a.y * dre - a.x * dim) * inv);
+}
+
+constexpr int BX = 64, BY = 4, NT = BX * BY;
+
+// Row p of A_sigma: diagonal (dre + i dim) and neighbour weights / H^2.
+template <typename T>
+struct Row {
+    T dre, dim, wl, wr, wd, wu;
+};
+
+template <typename T>
+__device__ __forceinline__ Row<T> row_at(int i, int j, int N, T H, T ih2, T kp, T sigma) {
+    Row<T> r;
+    int b = (i == 0) + (i == N) + (j == 0) + (j == N);
+    T k2 = kp * kp;
+    r.dre = T(-4) * ih2 + k2;
+    r.dim = T(2) * kp * H * T(b) * ih2 + k2 * sigma;
+    r.wl = (i > 0) ? ((i == N) ? T(2) : T(1)) * ih2 : T(0);
+    r.wr = (i < N) ? ((i == 0) ? T(2) : T(1)) * ih2 : T(0);
+    r.wd = (j > 0) ? ((j == N) ? T(2) : T(1)) * ih2 : T(0);
+    r.wu = (j < N) ? ((j == 0) ? T(2) : T(1)) * ih2 : T(0);
+    return r;
+}
+
+// Fields are stored in the level precision T (double or float); every
+// kernel computes in R = double and rounds only when it stores, so that the
+// stencil sums (terms of size |u| / H^2 that cancel) keep FP64 accuracy.
+template <typename R, typename T>
+__device__ __forceinline__ C<R> ldr(const C<T> *a, size_t p) {
+    C<T> v = a[p];
+    return cmk((R)v.x, (R)v.y);
+}
+template <typename T, typename R>
+__device__ __forceinline__ C<T> st_as(C<R> v) {
+    return cmk((T)v.x, (T)v.y);
+}
+
+// sum_{q != p} a_pq u_q, neighbours in the order left, right, down, up
+template <typename R, typename T>
+__device__ __forceinline__ C<R> offsum(const Row<R> &r, const C<T> *u, int i, int j, int N, int M) {
+    C<R> s = cmk(R(0), R(0));
+    size_t p = (size_t)j * M + i;
+    if (i > 0) s = cadd(s, cscale(r.wl, ldr<R>(u, p - 1)));
+    if (i < N) s = cadd(s, cscale(r.wr, ldr<R>(u, p + 1)));
+    if (j > 0) s = cadd(s, cscale(r.wd, ldr<R>(u, p - M)));
+    if (j < N) s = cadd(s, cscale(r.wu, ldr<R>(u, p + M)));
+    return s;
+}
+
+template <typename R, typename T>
+__device__ __forceinline__ C<R> row_apply(const Row<R> &r, const C<T> *u, int i, int j, int N, int M) {
+    C<R> up = ldr<R>(u, (size_t)j * M + i);
+    return cadd(cmul(cmk(r.dre, r.dim), up), offsum(r, u, i, j, N, M));
+}
+
+struct GeoT {
+    int n, M, N;
+};
+
+}  // namespace hmgk

@@ -23,9 +23,14 @@ struct hmg_ctx {
     std::unique_ptr<ServerState> server;
 };
 
+// How a level above the bottom solver runs its part of the V-cycle.
+enum LevelMode { LM_SIMPLE = 0, LM_GS_FUSED = 1, LM_KACZ_TILED = 2, LM_BOTTOM = 3 };
+
 struct Level {
     hmgk::Geo geo;
     void     *k = nullptr;  // wavenumber in the V-cycle precision
+    int       mode = LM_SIMPLE;
+    int       kacz_cfg = 1; // index into hmgk::kKaczCfgs
 };
 
 // Per right-hand side: level fields of one V-cycle in flight and the
@@ -33,8 +38,10 @@ struct Level {
 struct Slot {
     void        *f[HMG_MAX_LEVELS] = {};
     void        *u[HMG_MAX_LEVELS] = {};
+    void        *u2[HMG_MAX_LEVELS] = {};  // second buffer (tiled kernels never update in place)
     hmgk::Krylov K{};
     int          hist_cap = 0;
+    int          last_halfsteps = -1;   // of the last finished solve
     hipGraphExec_t iter_graph = nullptr;
 };
 
@@ -47,6 +54,8 @@ struct hmg_grid {
     hmg_plan   plan{};
     Level      lev[HMG_MAX_LEVELS];
     double    *k0 = nullptr;      // finest k in FP64 (outer operator)
+    int        lb = -1;           // first level of the bottom solver (-1: none)
+    hmgk::BottomDesc bottom{};    // per-level parameters of the bottom solver
     double    *ainv_t = nullptr;  // coarsest inverse, column-major complex FP64
     std::vector<Slot> slot;
     char      *mem = nullptr;

@@ -67,6 +67,45 @@ void launch_coarsest(Prec p, hipStream_t s, int m, const double *ainv_t, const v
 void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, size_t count,
                     const int *skip);
 
+// ---- fused LDS-tiled kernels (hmg_fused.hip) --------------------------------
+constexpr int HMG_SM_GS_DEV = 0, HMG_SM_KACZ_DEV = 1;
+constexpr int BOT_MAXL = 6;
+
+struct BottomLevelDesc {
+    int         n;
+    double      H, sa, sb;
+    const void *k;
+    int         sm, pre, post;
+    int         uoff, foff;     // complex-slot offsets of u and f in the LDS arena
+    int         koff;           // real-slot offset of k
+};
+struct BottomDesc {
+    int             nlev;
+    BottomLevelDesc L[BOT_MAXL];
+    const double   *ainv_t;
+};
+struct KaczCfg {
+    int ts, sweeps;             // tile side, sweeps per launch
+};
+constexpr int KACZ_NCFG = 4;
+extern const KaczCfg kKaczCfgs[KACZ_NCFG];
+bool   kacz_cfg_fits(Prec p, int cfg);
+int    bottom_complex_slots();   // LDS capacity of the bottom solver
+int    bottom_real_slots();
+
+// f64in / io64: the level-0 input (and output) are FP64 while the level
+// computes in float (mixed precision).
+void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void *k, double sa, double sb,
+                    const void *f, void *uo, void *fc, const int *skip);
+// uo may be null in launch_gs_down (the smoothed iterate is not stored);
+// launch_gs_up recomputes it from f.
+void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
+                  const void *ec, void *uo, const int *skip);
+void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
+                    const void *ui, const void *ec, void *uo, const int *skip);
+void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo,
+                   const int *skip);
+
 // ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
 int  krylov_nblocks(const Geo &g);
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given,

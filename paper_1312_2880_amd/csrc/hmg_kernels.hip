@@ -6,93 +6,25 @@
 // float).  Threads are laid out 64 x 4 per block so that each 64-wide wave
 // reads 64 consecutive nodes of one grid row.
 //
-// Discrete operator (Section 1, eq:diff / eq:disc / eq:mh), for node p =
-// (i, j) on a level with spacing H and N = n+1 intervals:
-//   a_pp = (-4 + 2 i k_p H b_p) / H^2 + k_p^2 (1 + i sigma)
-//   a_pq = w_pq / H^2,  w_pq = 2 for the inward neighbour across a boundary
-//                       face of p, 1 otherwise,
-// with b_p the number of boundary faces of p.  This is the 5-point stencil
-// with the Sommerfeld condition du/dn - i k u = 0 closed by central-
-// difference ghost points; sigma = 0 gives L, sigma = beta gives M.
+//
+// The discrete operator and complex helpers are in hmg_device.h.
 
-#include "hmg_internal.h"
+#include "hmg_device.h"
 
 namespace hmgk {
-
-template <typename T>
-struct __attribute__((aligned(2 * sizeof(T)))) C {
-    T x, y;
-};
-
-template <typename T> __device__ __forceinline__ C<T> cmk(T a, T b) { C<T> z; z.x = a; z.y = b; return z; }
-template <typename T> __device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return cmk(a.x + b.x, a.y + b.y); }
-template <typename T> __device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return cmk(a.x - b.x, a.y - b.y); }
-template <typename T> __device__ __forceinline__ C<T> cscale(T s, C<T> a) { return cmk(s * a.x, s * a.y); }
-template <typename T> __device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
-    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// a / (dre + i dim)
-template <typename T> __device__ __forceinline__ C<T> cdiv(C<T> a, T dre, T dim) {
-    T inv = T(1) / (dre * dre + dim * dim);
-    return cmk((a.x * dre + a.y * dim) * inv, (a.y * dre - a.x * dim) * inv);
-}
-
-constexpr int BX = 64, BY = 4, NT = BX * BY;
-
-// Row p of A_sigma: diagonal (dre + i dim) and neighbour weights / H^2.
-template <typename T>
-struct Row {
-    T dre, dim, wl, wr, wd, wu;
-};
-
-template <typename T>
-__device__ __forceinline__ Row<T> row_at(int i, int j, int N, T H, T ih2, T kp, T sigma) {
-    Row<T> r;
-    int b = (i == 0) + (i == N) + (j == 0) + (j == N);
-    T k2 = kp * kp;
-    r.dre = T(-4) * ih2 + k2;
-    r.dim = T(2) * kp * H * T(b) * ih2 + k2 * sigma;
-    r.wl = (i > 0) ? ((i == N) ? T(2) : T(1)) * ih2 : T(0);
-    r.wr = (i < N) ? ((i == 0) ? T(2) : T(1)) * ih2 : T(0);
-    r.wd = (j > 0) ? ((j == N) ? T(2) : T(1)) * ih2 : T(0);
-    r.wu = (j < N) ? ((j == 0) ? T(2) : T(1)) * ih2 : T(0);
-    return r;
-}
-
-// sum_{q != p} a_pq u_q, neighbours in the order left, right, down, up
-template <typename T>
-__device__ __forceinline__ C<T> offsum(const Row<T> &r, const C<T> *u, int i, int j, int N, int M) {
-    C<T> s = cmk(T(0), T(0));
-    size_t p = (size_t)j * M + i;
-    if (i > 0) s = cadd(s, cscale(r.wl, u[p - 1]));
-    if (i < N) s = cadd(s, cscale(r.wr, u[p + 1]));
-    if (j > 0) s = cadd(s, cscale(r.wd, u[p - M]));
-    if (j < N) s = cadd(s, cscale(r.wu, u[p + M]));
-    return s;
-}
-
-template <typename T>
-__device__ __forceinline__ C<T> row_apply(const Row<T> &r, const C<T> *u, int i, int j, int N, int M) {
-    C<T> up = u[(size_t)j * M + i];
-    return cadd(cmul(cmk(r.dre, r.dim), up), offsum(r, u, i, j, N, M));
-}
-
-struct GeoT {
-    int n, M, N;
-};
 
 // ---------------------------------------------------------------------------
 // Operator apply: out = A_sigma u
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_apply(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
+__global__ __launch_bounds__(NT) void k_apply(GeoT g, double H, double ih2, const T *__restrict__ k, double sigma,
                                               const C<T> *__restrict__ u, C<T> *__restrict__ out) {
     int i = blockIdx.x * BX + threadIdx.x;
     int j = blockIdx.y * BY + threadIdx.y;
     if (i > g.N || j > g.N) return;
     size_t p = (size_t)j * g.M + i;
-    Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
-    out[p] = row_apply(r, u, i, j, g.N, g.M);
+    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)k[p], sigma);
+    out[p] = st_as<T>(row_apply(r, u, i, j, g.N, g.M));
 }
 
 // ---------------------------------------------------------------------------
@@ -102,18 +34,18 @@ __global__ __launch_bounds__(NT) void k_apply(GeoT g, T H, T ih2, const T *__res
 // zero_guess (colour 0 of a first sweep): the other colour counts as zero.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_gs_colour(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
-                                                  const C<T> *__restrict__ f, C<T> *u, int colour,
+__global__ __launch_bounds__(NT) void k_gs_colour(GeoT g, double H, double ih2, const T *__restrict__ k,
+                                                  double sigma, const C<T> *__restrict__ f, C<T> *u, int colour,
                                                   int zero_guess, const int *skip) {
     if (skip && *skip) return;
     int j = blockIdx.y * BY + threadIdx.y;
     int i = 2 * (blockIdx.x * BX + threadIdx.x) + ((colour + j) & 1);
     if (i > g.N || j > g.N) return;
     size_t p = (size_t)j * g.M + i;
-    Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
-    C<T> num = f[p];
+    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)k[p], sigma);
+    C<double> num = ldr<double>(f, p);
     if (!zero_guess) num = csub(num, offsum(r, u, i, j, g.N, g.M));
-    u[p] = cdiv(num, r.dre, r.dim);
+    u[p] = st_as<T>(cdiv(num, r.dre, r.dim));
 }
 
 // ---------------------------------------------------------------------------
@@ -123,8 +55,8 @@ __global__ __launch_bounds__(NT) void k_gs_colour(GeoT g, T H, T ih2, const T *_
 // Rows of one colour are >= 3 apart, so their stencils are disjoint.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_kacz_colour(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
-                                                    const C<T> *__restrict__ f, C<T> *u, int colour,
+__global__ __launch_bounds__(NT) void k_kacz_colour(GeoT g, double H, double ih2, const T *__restrict__ k,
+                                                    double sigma, const C<T> *__restrict__ f, C<T> *u, int colour,
                                                     const int *skip) {
     if (skip && *skip) return;
     int j = blockIdx.y * BY + threadIdx.y;
@@ -132,16 +64,16 @@ __global__ __launch_bounds__(NT) void k_kacz_colour(GeoT g, T H, T ih2, const T 
     int i = i0 + 5 * (blockIdx.x * BX + threadIdx.x);
     if (i > g.N || j > g.N) return;
     size_t p = (size_t)j * g.M + i;
-    Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
-    C<T> res = csub(f[p], row_apply(r, u, i, j, g.N, g.M));
-    T nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
-    C<T> d = cmk(res.x / nrm, res.y / nrm);
-    C<T> up = u[p];
-    u[p] = cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x));
-    if (i > 0) u[p - 1] = cadd(u[p - 1], cscale(r.wl, d));
-    if (i < g.N) u[p + 1] = cadd(u[p + 1], cscale(r.wr, d));
-    if (j > 0) u[p - g.M] = cadd(u[p - g.M], cscale(r.wd, d));
-    if (j < g.N) u[p + g.M] = cadd(u[p + g.M], cscale(r.wu, d));
+    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)k[p], sigma);
+    C<double> res = csub(ldr<double>(f, p), row_apply(r, u, i, j, g.N, g.M));
+    double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+    C<double> d = cmk(res.x / nrm, res.y / nrm);
+    C<double> up = ldr<double>(u, p);
+    u[p] = st_as<T>(cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x)));
+    if (i > 0) u[p - 1] = st_as<T>(cadd(ldr<double>(u, p - 1), cscale(r.wl, d)));
+    if (i < g.N) u[p + 1] = st_as<T>(cadd(ldr<double>(u, p + 1), cscale(r.wr, d)));
+    if (j > 0) u[p - g.M] = st_as<T>(cadd(ldr<double>(u, p - g.M), cscale(r.wd, d)));
+    if (j < g.N) u[p + g.M] = st_as<T>(cadd(ldr<double>(u, p + g.M), cscale(r.wu, d)));
 }
 
 template <typename T>
@@ -157,15 +89,16 @@ __global__ __launch_bounds__(256) void k_fill_zero(C<T> *u, size_t count, const 
 // mirrored (r(-1) = r(1), r(N+1) = r(N-1)).  One thread per coarse node.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NT) void k_residual_fw(GeoT g, T H, T ih2, const T *__restrict__ k, T sigma,
-                                                    const C<T> *__restrict__ f, const C<T> *__restrict__ u,
-                                                    C<T> *__restrict__ fc, const int *skip) {
+__global__ __launch_bounds__(NT) void k_residual_fw(GeoT g, double H, double ih2, const T *__restrict__ k,
+                                                    double sigma, const C<T> *__restrict__ f,
+                                                    const C<T> *__restrict__ u, C<T> *__restrict__ fc,
+                                                    const int *skip) {
     if (skip && *skip) return;
     int Nc = g.N / 2, Mc = Nc + 1;
     int I = blockIdx.x * BX + threadIdx.x;
     int J = blockIdx.y * BY + threadIdx.y;
     if (I > Nc || J > Nc) return;
-    C<T> s = cmk(T(0), T(0));
+    C<double> s = cmk(0.0, 0.0);
     for (int e = -1; e <= 1; ++e) {
         int j = 2 * J + e;
         j = (j < 0) ? -j : ((j > g.N) ? 2 * g.N - j : j);
@@ -173,13 +106,13 @@ __global__ __launch_bounds__(NT) void k_residual_fw(GeoT g, T H, T ih2, const T 
             int i = 2 * I + d;
             i = (i < 0) ? -i : ((i > g.N) ? 2 * g.N - i : i);
             size_t p = (size_t)j * g.M + i;
-            Row<T> r = row_at<T>(i, j, g.N, H, ih2, k[p], sigma);
-            C<T> res = csub(f[p], row_apply(r, u, i, j, g.N, g.M));
-            T w = T((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
+            Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)k[p], sigma);
+            C<double> res = csub(ldr<double>(f, p), row_apply(r, u, i, j, g.N, g.M));
+            double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
             s = cadd(s, cscale(w, res));
         }
     }
-    fc[(size_t)J * Mc + I] = cscale(T(0.0625), s);
+    fc[(size_t)J * Mc + I] = st_as<T>(cscale(0.0625, s));
 }
 
 // ---------------------------------------------------------------------------
@@ -195,18 +128,19 @@ __global__ __launch_bounds__(NT) void k_prolong_add(GeoT g, const C<T> *__restri
     int Mc = g.N / 2 + 1;
     int I = i >> 1, J = j >> 1;
     size_t q = (size_t)J * Mc + I;
-    C<T> e;
+    C<double> e;
     if (!(i & 1) && !(j & 1)) {
-        e = ec[q];
+        e = ldr<double>(ec, q);
     } else if ((i & 1) && !(j & 1)) {
-        e = cscale(T(0.5), cadd(ec[q], ec[q + 1]));
+        e = cscale(0.5, cadd(ldr<double>(ec, q), ldr<double>(ec, q + 1)));
     } else if (!(i & 1) && (j & 1)) {
-        e = cscale(T(0.5), cadd(ec[q], ec[q + Mc]));
+        e = cscale(0.5, cadd(ldr<double>(ec, q), ldr<double>(ec, q + Mc)));
     } else {
-        e = cscale(T(0.25), cadd(cadd(cadd(ec[q], ec[q + 1]), ec[q + Mc]), ec[q + Mc + 1]));
+        e = cscale(0.25, cadd(cadd(cadd(ldr<double>(ec, q), ldr<double>(ec, q + 1)), ldr<double>(ec, q + Mc)),
+                              ldr<double>(ec, q + Mc + 1)));
     }
     size_t p = (size_t)j * g.M + i;
-    u[p] = cadd(u[p], e);
+    u[p] = st_as<T>(cadd(ldr<double>(u, p), e));
 }
 
 // ---------------------------------------------------------------------------
@@ -222,12 +156,12 @@ __global__ __launch_bounds__(256) void k_coarsest(int m, const C<double> *__rest
                                                   const int *skip) {
     if (skip && *skip) return;
     __shared__ C<double> fs[MAX_COARSE];
-    for (int q = threadIdx.x; q < m; q += 256) fs[q] = cmk((double)f[q].x, (double)f[q].y);
+    for (int q = threadIdx.x; q < m; q += 256) fs[q] = ldr<double>(f, q);
     __syncthreads();
     for (int r = threadIdx.x; r < m; r += 256) {
         C<double> acc = cmk(0.0, 0.0);
         for (int c = 0; c < m; ++c) acc = cadd(acc, cmul(ainv_t[(size_t)c * m + r], fs[c]));
-        u[r] = cmk((T)acc.x, (T)acc.y);
+        u[r] = st_as<T>(acc);
     }
 }
 
@@ -253,8 +187,8 @@ static inline dim3 grid2(int nx, int ny) { return dim3((nx + BX - 1) / BX, (ny +
 
 template <typename T>
 static void apply_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *u, void *out) {
-    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
-    k_apply<T><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, (T)sigma,
+    double H = g.H, ih2 = 1.0 / (g.H * g.H);
+    k_apply<T><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, sigma,
                                                          (const C<T> *)u, (C<T> *)out);
 }
 void launch_apply(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *u, void *out) {
@@ -265,9 +199,9 @@ void launch_apply(Prec p, hipStream_t s, const Geo &g, const void *k, double sig
 template <typename T>
 static void gs_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u, int colour,
                  int zero_guess, const int *skip) {
-    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    double H = g.H, ih2 = 1.0 / (g.H * g.H);
     k_gs_colour<T><<<grid2((g.M + 1) / 2, g.M), dim3(BX, BY), 0, s>>>(
-        geot(g), H, ih2, (const T *)k, (T)sigma, (const C<T> *)f, (C<T> *)u, colour, zero_guess, skip);
+        geot(g), H, ih2, (const T *)k, sigma, (const C<T> *)f, (C<T> *)u, colour, zero_guess, skip);
 }
 void launch_gs_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u,
                       int colour, int zero_guess, const int *skip) {
@@ -278,9 +212,9 @@ void launch_gs_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double
 template <typename T>
 static void kacz_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u, int colour,
                    const int *skip) {
-    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    double H = g.H, ih2 = 1.0 / (g.H * g.H);
     k_kacz_colour<T><<<grid2((g.M + 4) / 5, g.M), dim3(BX, BY), 0, s>>>(
-        geot(g), H, ih2, (const T *)k, (T)sigma, (const C<T> *)f, (C<T> *)u, colour, skip);
+        geot(g), H, ih2, (const T *)k, sigma, (const C<T> *)f, (C<T> *)u, colour, skip);
 }
 void launch_kacz_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u,
                         int colour, const int *skip) {
@@ -297,9 +231,9 @@ void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *s
 template <typename T>
 static void rfw_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, const void *u, void *fc,
                   const int *skip) {
-    T H = (T)g.H, ih2 = (T)(1.0 / (g.H * g.H));
+    double H = g.H, ih2 = 1.0 / (g.H * g.H);
     int Mc = g.N / 2 + 1;
-    k_residual_fw<T><<<grid2(Mc, Mc), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, (T)sigma,
+    k_residual_fw<T><<<grid2(Mc, Mc), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, sigma,
                                                              (const C<T> *)f, (const C<T> *)u, (C<T> *)fc, skip);
 }
 void launch_residual_fw(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f,
@@ -380,17 +314,27 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
     }
 }
 
-// Single 256-thread block: total of each of NV partial rows (fixed order:
-// thread t sums t, t+256, ... sequentially, then a fixed tree).
+// Single 256-thread block: total of each of NV partial rows.  Thread t sums
+// entries t, t + 256, ... in eight interleaved accumulators (independent
+// loads in flight instead of one dependent chain), combined in a fixed
+// order, then a fixed tree across the block: the result depends only on nb.
 template <int NV>
 __device__ __forceinline__ void finalize_sums(const double *partials, int nb, double *tot) {
     double v[NV];
     int tid = threadIdx.y * BX + threadIdx.x;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
-        double x = 0.0;
-        for (int b = tid; b < nb; b += NT) x += partials[(size_t)q * nb + b];
-        v[q] = x;
+        const double *P = partials + (size_t)q * nb;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = tid;
+        for (; b + 7 * NT < nb; b += 8 * NT) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += P[b + u * NT];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b + u * NT < nb) a[u] += P[b + u * NT];
+        v[q] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     __shared__ double out[NV];
     block_sum<NV>(v, out);

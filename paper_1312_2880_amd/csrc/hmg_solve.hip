@@ -188,6 +188,7 @@ static hmg_status run_finish(SolveRun &R, hmg_solve_info *info) {
     } else {
         res = HMG_ERR_NOT_CONVERGED;
     }
+    S.last_halfsteps = k.halfsteps;
     if (info) {
         info->halfsteps = k.halfsteps;
         info->iters = 0.5 * k.halfsteps;
@@ -586,4 +587,20 @@ extern "C" hmg_status hmg_ctx_set_max_active(hmg_ctx *ctx, int max_active) {
     std::lock_guard<std::mutex> lk(ctx->server->mu);
     ctx->server->max_active = max_active;
     return HMG_OK;
+}
+
+extern "C" int hmg_solve_history(hmg_grid *g, int rhs, double *out, int cap) {
+    if (!g || rhs < 0 || rhs >= g->nrhs || (!out && cap > 0)) {
+        hmg_fail(HMG_ERR_INVALID, "bad argument");
+        return -1;
+    }
+    Slot &S = g->slot[rhs];
+    if (!S.K.hist || S.last_halfsteps < 0) return 0;
+    int n = std::min(S.last_halfsteps + 1, S.hist_cap);
+    int m = std::min(n, cap);
+    if (m > 0 && hipMemcpy(out, S.K.hist, (size_t)m * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+        hmg_fail(HMG_ERR_DEVICE, "history copy failed");
+        return -1;
+    }
+    return n;
 }

@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                 ("nu_post", ctypes.c_int), ("kacz_pre", ctypes.c_int),
                 ("kacz_post", ctypes.c_int), ("kacz_band", ctypes.c_int),
                 ("coarsest_n", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("reserved", ctypes.c_int * 7)]
+                ("one_pass_kernels", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class Plan(ctypes.Structure):
@@ -106,6 +107,12 @@ _SIGS = {
     "hmg_op_restrict_dev": (_i, [P, _i, _d, P, P, P, P]),
     "hmg_op_prolong_dev": (_i, [P, _i, P, P, P]),
     "hmg_op_coarsest_dev": (_i, [P, P, P, P]),
+    "hmg_op_gs_down_dev": (_i, [P, _i, _d, _d, P, P, P, P]),
+    "hmg_op_gs_up_dev": (_i, [P, _i, _d, P, P, P, P]),
+    "hmg_op_kacz_tiled_dev": (_i, [P, _i, _d, _i, P, P, P, P, P]),
+    "hmg_kacz_tile_config": (_i, [_i, P, P]),
+    "hmg_solve_history": (_i, [P, _i, P, _i]),
+    "hmg_grid_kacz_config": (_i, [P, _i]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -113,6 +120,17 @@ for _name, (_res, _args) in _SIGS.items():
     _fn.argtypes = _args
 
 EXPORTED = tuple(_SIGS)
+
+
+def kacz_tile_configs():
+    """[(tile side, sweeps per launch)] of the tiled Kaczmarz kernel."""
+    t, s = ctypes.c_int(), ctypes.c_int()
+    n = _lib.hmg_kacz_tile_config(0, ctypes.byref(t), ctypes.byref(s))
+    out = []
+    for c in range(n):
+        _lib.hmg_kacz_tile_config(c, ctypes.byref(t), ctypes.byref(s))
+        out.append((t.value, s.value))
+    return out
 
 
 def _check(status, allow=(OK,)):
@@ -260,6 +278,10 @@ class Grid:
                      sigma_resid=p.sigma_resid[l], pre=p.pre[l], post=p.post[l])
                 for l in range(p.nlev)]
 
+    def kacz_config(self, level: int) -> int:
+        """Index of the tiled-Kaczmarz configuration used on `level` (-1: none)."""
+        return _lib.hmg_grid_kacz_config(self._h, level)
+
     def set_rhs(self, rhs: int, f):
         f = np.ascontiguousarray(f, np.complex128)
         _check(_lib.hmg_grid_set_rhs(self._h, rhs, _ptr(f)))
@@ -279,6 +301,15 @@ class Grid:
         st = _lib.hmg_solve(self._h, _ptr(x), rtol, maxit, infos)
         _check(st, (OK, ERR_NOT_CONVERGED))
         return x, [_info_dict(i) for i in infos]
+
+    def history(self, rhs=0):
+        """Relative residual per half iteration of the last solve of `rhs`."""
+        n = _lib.hmg_solve_history(self._h, rhs, None, 0)
+        if n < 0:
+            _check(ERR_INVALID)
+        out = np.zeros(n, np.float64)
+        _lib.hmg_solve_history(self._h, rhs, _ptr(out), n)
+        return out
 
     def solve_dev(self, d_x, d_b=None, rhs=0, x0=False, rtol=1e-6, maxit=500, stream=None):
         info = SolveInfo()
@@ -303,6 +334,18 @@ class Grid:
     def op_prolong(self, level, d_ec, d_u, stream=None):
         _check(_lib.hmg_op_prolong_dev(self._h, level, _dptr(d_ec), _dptr(d_u),
                                        _stream(stream)))
+
+    def op_gs_down(self, level, sigma_relax, sigma_resid, d_f, d_u, d_fc, stream=None):
+        _check(_lib.hmg_op_gs_down_dev(self._h, level, sigma_relax, sigma_resid, _dptr(d_f),
+                                       _dptr(d_u), _dptr(d_fc), _stream(stream)))
+
+    def op_gs_up(self, level, sigma_relax, d_f, d_ec, d_uo, stream=None):
+        _check(_lib.hmg_op_gs_up_dev(self._h, level, sigma_relax, _dptr(d_f), _dptr(d_ec),
+                                     _dptr(d_uo), _stream(stream)))
+
+    def op_kacz_tiled(self, level, sigma, config, d_f, d_ui, d_ec, d_uo, stream=None):
+        _check(_lib.hmg_op_kacz_tiled_dev(self._h, level, sigma, config, _dptr(d_f), _dptr(d_ui),
+                                          _dptr(d_ec), _dptr(d_uo), _stream(stream)))
 
     def op_coarsest(self, d_f, d_u, stream=None):
         _check(_lib.hmg_op_coarsest_dev(self._h, _dptr(d_f), _dptr(d_u), _stream(stream)))

@@ -373,6 +373,8 @@ CASES_P4 = [
     dict(variant=oracle.HLM, kacz_band=1, coarsest_n=1, k=(6.0, 10.0)),
     dict(variant=oracle.HYB, kacz_band=1, coarsest_n=1, k=(3.0, 9.0),
          gs_order=oracle.ORDER_LEX, kacz_order=oracle.ORDER_LEX),
+    # HYB level with Gauss-Seidel on M and residuals on L (kH in [0.45, 0.875])
+    dict(variant=oracle.HYB, kacz_band=1, coarsest_n=3, k=(3.6, 7.0)),
 ]
 
 
@@ -404,11 +406,16 @@ def test_vcycle_equals_dense_matrix_vcycle(case):
 
 def test_vcycle_plans_cover_both_smoothers():
     kinds = set()
+    mixed_roles = False
     for case in CASES_P4:
         case = dict(case)
         lo, hi = case.pop("k")
-        kinds |= {p["smoother"] for p in oracle.Grid(1 / 8, rng_k(7, 21, lo, hi), **case).plan()}
+        for p in oracle.Grid(1 / 8, rng_k(7, 21, lo, hi), **case).plan():
+            kinds.add(p["smoother"])
+            if p["smoother"] == "GS" and p["sigma_relax"] != p["sigma_resid"]:
+                mixed_roles = True
     assert kinds == {"GS", "KACZ", "LU"}
+    assert mixed_roles
 
 
 # ---------------------------------------------------------------------------
