@@ -60,7 +60,7 @@ __device__ __forceinline__ int mirror(int x, int N) { return x < 0 ? -x : (x > N
 // all loads in flight together, and keeps them in registers across the
 // dependent phases, which then touch only LDS.
 // ===========================================================================
-constexpr int GDX = 64, GDY = 16, GNT = 256;
+constexpr int GDX = 64, GDY = 20, GNT = 256;
 constexpr int GRH = 3, GLW = GDX + 2 * GRH, GLH = GDY + 2 * GRH;
 constexpr int GHW = GLW / 2;                       // nodes of one colour per line
 constexpr int GNC = GHW * GLH;                     // nodes of one colour in the region
@@ -90,9 +90,7 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
                                                  double sb, const C<TF> *__restrict__ f, C<T> *uo,
                                                  C<T> *__restrict__ fc, const int *skip) {
     if (skip && *skip) return;
-    constexpr int RW = GDX + 2, RR = GDY + 2;
-    __shared__ C<double> U[GLW * GLH];
-    __shared__ C<double> Rs[RW * RR];
+    __shared__ C<double> U[GLW * GLH];      // the iterate, then the residual on tile + 1
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * GDX, y0 = blockIdx.y * GDY;
     const int ox = x0 - GRH, oy = y0 - GRH;
@@ -135,7 +133,21 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
         U[l] = cdiv(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim);
     }
     __syncthreads();
-    // residual with the role-(B) operator on tile + 1
+    // the smoothed iterate on the tile (only when asked for: the up kernel
+    // recomputes it)
+    if (uo) {
+#pragma unroll
+        for (int m = 0; m < GDX * GDY / GNT; ++m) {
+            const int q = tid + GNT * m;
+            int tx = q % GDX, ty = q / GDX;
+            int i = x0 + tx, j = y0 + ty;
+            if (i > N || j > N) continue;
+            uo[(size_t)j * M + i] = st_as<T>(U[(ty + GRH) * GLW + tx + GRH]);
+        }
+    }
+    // residual with the role-(B) operator on tile + 1, kept in registers
+    // until every thread has read the iterate, then stored over it
+    C<double> res[2][GNS];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -147,36 +159,40 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
             int l = ly * GLW + lx;
             Row<double> r = row_at<double>(i, j, N, H, ih2, kr[c][m], sb);
             C<double> au = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_l(r, U, l, GLW, i, j, N));
-            Rs[(ly - GRH + 1) * RW + (lx - GRH + 1)] = csub(fr[c][m], au);
+            res[c][m] = csub(fr[c][m], au);
         }
     __syncthreads();
-    // full weighting for the coarse nodes of this tile (one per thread)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < GNS; ++m) {
+            int lx, ly;
+            bool own = gs_owned(tid, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+            U[ly * GLW + lx] = res[c][m];
+        }
+    __syncthreads();
+    // full weighting for the coarse nodes of this tile
     {
         const int Nc = N / 2, Mc = Nc + 1;
-        int I = x0 / 2 + tid % (GDX / 2), J = y0 / 2 + tid / (GDX / 2);
-        if (I <= Nc && J <= Nc) {
+        constexpr int CX = GDX / 2, NCN = (GDX / 2) * (GDY / 2);
+#pragma unroll
+        for (int m = 0; m < (NCN + GNT - 1) / GNT; ++m) {
+            const int q = tid + GNT * m;
+            if (q >= NCN) break;
+            int I = x0 / 2 + q % CX, J = y0 / 2 + q / CX;
+            if (I > Nc || J > Nc) continue;
             C<double> s = cmk(0.0, 0.0);
             for (int e = -1; e <= 1; ++e) {
                 int j = mirror(2 * J + e, N);
                 for (int d = -1; d <= 1; ++d) {
                     int i = mirror(2 * I + d, N);
                     double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
-                    s = cadd(s, cscale(w, Rs[(j - (y0 - 1)) * RW + (i - (x0 - 1))]));
+                    s = cadd(s, cscale(w, U[(j - oy) * GLW + (i - ox)]));
                 }
             }
             fc[(size_t)J * Mc + I] = st_as<T>(cscale(0.0625, s));
-        }
-    }
-    // the smoothed iterate on the tile (only when asked for: the up kernel
-    // recomputes it)
-    if (uo) {
-#pragma unroll
-        for (int m = 0; m < GDX * GDY / GNT; ++m) {
-            const int q = tid + GNT * m;
-            int tx = q % GDX, ty = q / GDX;
-            int i = x0 + tx, j = y0 + ty;
-            if (i > N || j > N) continue;
-            uo[(size_t)j * M + i] = st_as<T>(U[(ty + GRH) * GLW + tx + GRH]);
         }
     }
 }
@@ -198,8 +214,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
     const int ox = x0 - GRH, oy = y0 - GRH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     C<double> fr[2][GNS];
-    double kr[2][GNS], ir[2][GNS];     // k and 1 / |a_pp|^2 of owned nodes
-    C<double> er[2][GNS];
+    double kr[2][GNS];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -211,9 +226,6 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
                 size_t p = (size_t)j * M + i;
                 fr[c][m] = ldr<double>(f, p);
                 kr[c][m] = (double)k[p];
-                er[c][m] = in_ring(lx, ly, 2) ? prolong_at(ec, i, j, Mc) : cmk(0.0, 0.0);
-                Row<double> r = row_at<double>(i, j, N, H, ih2, kr[c][m], sa);
-                ir[c][m] = 1.0 / (r.dre * r.dre + r.dim * r.dim);
             }
         }
     // red u0 on tile + 3
@@ -224,7 +236,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         int i = ox + lx, j = oy + ly;
         if (!own || i < 0 || j < 0 || i > N || j > N) continue;
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[ly * GLW + lx] = cdivr(fr[0][m], r.dre, r.dim, ir[0][m]);
+        U[ly * GLW + lx] = cdiv(fr[0][m], r.dre, r.dim);
     }
     __syncthreads();
     // black u0 on tile + 2, plus the correction on the black nodes
@@ -236,7 +248,8 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         if (!own || !in_ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
         int l = ly * GLW + lx;
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-        U[l] = cadd(cdivr(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim, ir[1][m]), er[1][m]);
+        U[l] = cadd(cdiv(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim),
+                    prolong_at(ec, i, j, Mc));
     }
     __syncthreads();
     // the correction on the red nodes of tile + 2 (after every black u0 has
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         int i = ox + lx, j = oy + ly;
         if (!own || !in_ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
         int l = ly * GLW + lx;
-        U[l] = cadd(U[l], er[0][m]);
+        U[l] = cadd(U[l], prolong_at(ec, i, j, Mc));
     }
     __syncthreads();
     // red on tile + 1
@@ -260,7 +273,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
         int l = ly * GLW + lx;
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[l] = cdivr(csub(fr[0][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim, ir[0][m]);
+        U[l] = cdiv(csub(fr[0][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim);
     }
     __syncthreads();
     // black on the tile -> output; red tile nodes -> output
@@ -276,17 +289,20 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
             C<double> v = U[l];
             if (c == 1) {
                 Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-                v = cdivr(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim, ir[1][m]);
+                v = cdiv(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim);
             }
             uo[(size_t)j * M + i] = st_as<TU>(v);
         }
 }
 
 // ===========================================================================
-// k_kacz_tb: S sweeps of 5-colour Kaczmarz on a TS x TS tile.  Pass q of
-// the 5 S passes (colour q mod 5) updates the rows within tile + (10 S - 2q
-// - 1); after it u is exact on tile + (10 S - 2q - 2); after the last pass
-// on the tile itself.  Initial u: 0 (ui == null) or ui (+ P ec).
+// k_kacz_tb: S sweeps of 5-colour Kaczmarz on a TS x TS tile held in LDS
+// with a halo of RH = 10 S (each colour pass moves information two nodes).
+// Pass q (colour q mod 5) updates the rows on tile + (RH - 2q - 1); after it
+// u is exact on tile + (RH - 2q - 2), and after the last pass on the tile
+// itself.  Each thread keeps the same row slots (line, column slot) in every
+// pass, so a pass needs no division to find its rows.  Initial u: 0 (ui ==
+// null) or ui, plus P ec when ec != null.
 // ===========================================================================
 constexpr int KNT = 512;
 
@@ -297,11 +313,15 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
                                                  const int *skip) {
     if (skip && *skip) return;
     constexpr int RH = 10 * S, LW = TS + 2 * RH;
-    // f and k of the tile are staged in LDS when u, f and k fit together
+    // f and (k, 1/||a_p||^2) of the region are staged in LDS when they fit
+    // next to u
     constexpr bool STAGE = (size_t)LW * LW * (16 + 16 + 16) <= 160 * 1024;
+    constexpr int T5 = (LW - 2 + 4) / 5;              // row slots per line and colour
+    constexpr int NSLOT = (LW - 2) * T5;              // slots per colour
+    constexpr int NM = (NSLOT + KNT - 1) / KNT;       // slots per thread and colour
     __shared__ C<double> U[LW * LW];
     __shared__ C<double> FS[STAGE ? LW * LW : 1];
-    __shared__ C<double> KS[STAGE ? LW * LW : 1];    // (k, 1 / ||a_p||^2)
+    __shared__ C<double> KS[STAGE ? LW * LW : 1];
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS;
     const int ox = x0 - RH, oy = y0 - RH;
@@ -321,19 +341,29 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
             KS[q] = cmk(kp, 1.0 / nrm);
         }
     }
+    // row slots of this thread: line ly = 1 + s / T5, column slot t = s % T5;
+    // for colour c the row sits at lx = 1 + ((c - i1 - 2 j) mod 5) + 5 t
+    int sly[NM], sbase[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+        int sl = tid + KNT * m;
+        sly[m] = (sl < NSLOT) ? 1 + sl / T5 : -1;
+        sbase[m] = 5 * (sl % T5);
+    }
     __syncthreads();
     for (int pass = 0; pass < 5 * S; ++pass) {
         const int c = pass % 5;
-        const int hh = RH - 2 * pass - 1;       // rows processed on tile + hh
-        const int W = TS + 2 * hh;
-        const int W5 = (W + 4) / 5;
-        const int xs = x0 - hh, ys = y0 - hh;
-        for (int q = tid; q < W * W5; q += KNT) {
-            int j = ys + q / W5;
-            int i = xs + (((c - xs - 2 * j) % 5) + 5) % 5 + 5 * (q % W5);
-            if (i >= xs + W || i < 0 || j < 0 || i > N || j > N) continue;
+        const int lo = 2 * pass + 1, hi = LW - 2 - 2 * pass;   // rows on tile + (RH - 2 pass - 1)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const int ly = sly[m];
+            if (ly < lo || ly > hi) continue;
+            const int j = oy + ly;
+            const int lx = 1 + (((c - (ox + 1) - 2 * j) % 5) + 5) % 5 + sbase[m];
+            const int i = ox + lx;
+            if (lx < lo || lx > hi || i < 0 || j < 0 || i > N || j > N) continue;
+            const int l = ly * LW + lx;
             size_t p = (size_t)j * M + i;
-            int l = (j - oy) * LW + (i - ox);
             C<double> kc = STAGE ? KS[l] : cmk((double)k[p], 0.0);
             Row<double> r = row_at<double>(i, j, N, H, ih2, kc.x, sig);
             C<double> fp = STAGE ? FS[l] : ldr<double>(f, p);
@@ -416,11 +446,23 @@ __device__ void bot_relax(const BotLevel<T> &L, C<double> *SM, const double *KS,
             }
     } else {
         const int W5 = (M + 4) / 5;
+        // fixed row slots: q = tid + BNT m -> line j = q / W5, column slot
+        // 5 (q % W5); computed once, not per pass
+        constexpr int BM = 2;     // M * W5 <= 33 * 7 < BM * BNT on bottom levels
+        int qj[BM], q5[BM];
+#pragma unroll
+        for (int m = 0; m < BM; ++m) {
+            int q = tid + BNT * m;
+            qj[m] = (q < M * W5) ? q / W5 : -1;
+            q5[m] = 5 * (q % W5);
+        }
         for (int s = 0; s < sweeps; ++s)
             for (int c = 0; c < 5; ++c) {
-                for (int q = tid; q < M * W5; q += BNT) {
-                    int j = q / W5;
-                    int i = ((c - 2 * j) % 5 + 5) % 5 + 5 * (q % W5);
+#pragma unroll
+                for (int m = 0; m < BM; ++m) {
+                    const int j = qj[m];
+                    if (j < 0) continue;
+                    const int i = ((c - 2 * j) % 5 + 5) % 5 + q5[m];
                     if (i > N) continue;
                     int p = j * M + i;
                     Row<double> r = row_at<double>(i, j, N, L.H, L.ih2, K[p], L.sa);
@@ -494,17 +536,33 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
         }
         __syncthreads();
     }
-    // coarsest: u = A^{-1} f in FP64
+    // coarsest: u = A^{-1} f in FP64; row r is split over CPARTS threads
+    // (column ranges), partial sums combined in a fixed order
     {
+        constexpr int CPARTS = 3;
+        __shared__ C<double> part[CPARTS][BNT];
         const BotLevel<T> &L = PL[last];
         const int m = L.M * L.M;
+        const int chunk = (m + CPARTS - 1) / CPARTS;
         const C<double> *F = SM + L.foff;
-        for (int r = tid; r < m; r += BNT) {
-            C<double> acc = cmk(0.0, 0.0);
-            for (int c = 0; c < m; ++c) acc = cadd(acc, cmul(P.ainv[(size_t)c * m + r], F[c]));
-            SM[L.uoff + r] = acc;
+        for (int base = 0; base < m; base += BNT / CPARTS) {
+            const int r = base + tid % (BNT / CPARTS), part_id = tid / (BNT / CPARTS);
+            if (part_id < CPARTS) {
+                C<double> acc = cmk(0.0, 0.0);
+                if (r < m) {
+                    const int c0 = part_id * chunk, c1 = min(m, c0 + chunk);
+                    for (int c = c0; c < c1; ++c) acc = cadd(acc, cmul(P.ainv[(size_t)c * m + r], F[c]));
+                }
+                part[part_id][tid % (BNT / CPARTS)] = acc;
+            }
+            __syncthreads();
+            if (tid < BNT / CPARTS && base + tid < m) {
+                C<double> acc = part[0][tid];
+                for (int q = 1; q < CPARTS; ++q) acc = cadd(acc, part[q][tid]);
+                SM[L.uoff + base + tid] = acc;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     // up: bilinear correction, post-relaxation
     for (int l = last - 1; l >= 0; --l) {

@@ -343,6 +343,10 @@ __device__ __forceinline__ void finalize_sums(const double *partials, int nb, do
     for (int q = 0; q < NV; ++q) tot[q] = out[q];
 }
 
+// Each thread of a Bi-CGSTAB kernel covers KRY rows (fewer blocks, so fewer
+// partial sums for the single-block finalisation).
+constexpr int KRY = 4;
+
 struct KDev {
     C<double> *b, *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;
     double *partials, *hist;
@@ -363,9 +367,10 @@ __device__ __forceinline__ void st2(double *p, C<double> z) { p[0] = z.x; p[1] =
 __global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, const double *__restrict__ k,
                                                  KDev K, int x0_given) {
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
     double v[2] = {0.0, 0.0};
-    if (i <= g.N && j <= g.N) {
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
         C<double> bp = K.b[p], rp;
         if (x0_given) {
@@ -379,8 +384,8 @@ __global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, c
         K.rh[p] = rp;
         K.p[p] = cmk(0.0, 0.0);
         K.v[p] = cmk(0.0, 0.0);
-        v[0] = bp.x * bp.x + bp.y * bp.y;
-        v[1] = rp.x * rp.x + rp.y * rp.y;
+        v[0] += bp.x * bp.x + bp.y * bp.y;
+        v[1] += rp.x * rp.x + rp.y * rp.y;
     }
     block_partials<2>(v, K.partials);
 }
@@ -419,16 +424,19 @@ __global__ __launch_bounds__(NT) void k_kry_update_p(GeoT g, KDev K) {
     const KState *s = K.st;
     if (s->done) return;
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
-    if (i > g.N || j > g.N) return;
-    size_t p = (size_t)j * g.M + i;
-    C<double> r = K.r[p];
-    if (s->restart) {
-        K.rh[p] = r;
-        K.p[p] = r;
-    } else {
-        C<double> beta = ld2(s->beta), omega = ld2(s->omega);
-        K.p[p] = cadd(r, cmul(beta, csub(K.p[p], cmul(omega, K.v[p]))));
+    const int restart = s->restart;
+    C<double> beta = ld2(s->beta), omega = ld2(s->omega);
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
+        size_t p = (size_t)j * g.M + i;
+        C<double> r = K.r[p];
+        if (restart) {
+            K.rh[p] = r;
+            K.p[p] = r;
+        } else {
+            K.p[p] = cadd(r, cmul(beta, csub(K.p[p], cmul(omega, K.v[p]))));
+        }
     }
 }
 
@@ -437,16 +445,17 @@ __global__ __launch_bounds__(NT) void k_kry_matvec_alpha(GeoT g, double H, doubl
                                                          KDev K) {
     if (K.st->done) return;
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
     double v[2] = {0.0, 0.0};
-    if (i <= g.N && j <= g.N) {
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
         Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
         C<double> vp = row_apply(r, K.ph, i, j, g.N, g.M);
         K.v[p] = vp;
         C<double> a = K.rh[p];
-        v[0] = a.x * vp.x + a.y * vp.y;      // conj(a) * vp
-        v[1] = a.x * vp.y - a.y * vp.x;
+        v[0] += a.x * vp.x + a.y * vp.y;      // conj(a) * vp
+        v[1] += a.x * vp.y - a.y * vp.x;
     }
     block_partials<2>(v, K.partials);
 }
@@ -465,14 +474,15 @@ __global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K, int nb) {
 __global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K) {
     if (K.st->done) return;
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
     double v[1] = {0.0};
-    if (i <= g.N && j <= g.N) {
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
         C<double> alpha = ld2(K.st->alpha);
         C<double> sp = csub(K.r[p], cmul(alpha, K.v[p]));
         K.s[p] = sp;
-        v[0] = sp.x * sp.x + sp.y * sp.y;
+        v[0] += sp.x * sp.x + sp.y * sp.y;
     }
     block_partials<1>(v, K.partials);
 }
@@ -498,17 +508,18 @@ __global__ __launch_bounds__(NT) void k_kry_matvec_omega(GeoT g, double H, doubl
                                                          KDev K) {
     if (K.st->stop) return;
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
     double v[3] = {0.0, 0.0, 0.0};
-    if (i <= g.N && j <= g.N) {
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
         Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
         C<double> tp = row_apply(r, K.sh, i, j, g.N, g.M);
         K.t[p] = tp;
         C<double> sp = K.s[p];
-        v[0] = tp.x * sp.x + tp.y * sp.y;    // conj(t) s
-        v[1] = tp.x * sp.y - tp.y * sp.x;
-        v[2] = tp.x * tp.x + tp.y * tp.y;
+        v[0] += tp.x * sp.x + tp.y * sp.y;    // conj(t) s
+        v[1] += tp.x * sp.y - tp.y * sp.x;
+        v[2] += tp.x * tp.x + tp.y * tp.y;
     }
     block_partials<3>(v, K.partials);
 }
@@ -527,9 +538,10 @@ __global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
     if (s->done) return;
     int half = s->half_exit;
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
     double v[3] = {0.0, 0.0, 0.0};
-    if (i <= g.N && j <= g.N) {
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
         C<double> alpha = ld2(s->alpha);
         if (half) {
@@ -540,9 +552,9 @@ __global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
             C<double> rp = csub(K.s[p], cmul(omega, K.t[p]));
             K.r[p] = rp;
             C<double> a = K.rh[p];
-            v[0] = rp.x * rp.x + rp.y * rp.y;
-            v[1] = a.x * rp.x + a.y * rp.y;  // conj(rh) r
-            v[2] = a.x * rp.y - a.y * rp.x;
+            v[0] += rp.x * rp.x + rp.y * rp.y;
+            v[1] += a.x * rp.x + a.y * rp.y;  // conj(rh) r
+            v[2] += a.x * rp.y - a.y * rp.x;
         }
     }
     if (!half) block_partials<3>(v, K.partials);
@@ -600,14 +612,15 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
 __global__ __launch_bounds__(NT) void k_kry_true(GeoT g, double H, double ih2, const double *__restrict__ k,
                                                  KDev K) {
     int i = blockIdx.x * BX + threadIdx.x;
-    int j = blockIdx.y * BY + threadIdx.y;
     double v[1] = {0.0};
-    if (i <= g.N && j <= g.N) {
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
         Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
         C<double> rp = csub(K.b[p], row_apply(r, K.x, i, j, g.N, g.M));
         K.r[p] = rp;
-        v[0] = rp.x * rp.x + rp.y * rp.y;
+        v[0] += rp.x * rp.x + rp.y * rp.y;
     }
     block_partials<1>(v, K.partials);
 }
@@ -636,8 +649,10 @@ __global__ void k_kry_restart(KDev K) {
     s->stop = 0;
 }
 
+static inline dim3 kgrid(const Geo &g) { return dim3((g.M + BX - 1) / BX, (g.M + BY * KRY - 1) / (BY * KRY)); }
+
 int krylov_nblocks(const Geo &g) {
-    dim3 gr = grid2(g.M, g.M);
+    dim3 gr = kgrid(g);
     return (int)(gr.x * gr.y);
 }
 
@@ -648,42 +663,42 @@ void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_init<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, x0_given);
+    k_kry_init<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, x0_given);
     // the history buffer holds maxhalf + 2 entries (allocated by the caller)
     k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2);
 }
 void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K) {
-    k_kry_update_p<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));
+    k_kry_update_p<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));
 }
 void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_matvec_alpha<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_matvec_alpha<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
     k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
 void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K) {
     KDev d = kdev(K);
-    k_kry_update_s<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), d);
+    k_kry_update_s<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
     k_kry_s_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
 void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_matvec_omega<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_matvec_omega<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
     k_kry_omega_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
 void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K) {
     KDev d = kdev(K);
-    k_kry_update_xr<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), d);
+    k_kry_update_xr<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
     k_kry_iter_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
 void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_true<<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_true<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
     k_kry_true_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
 void kry_restart_from_true(hipStream_t s, const Krylov &K) { k_kry_restart<<<1, 1, 0, s>>>(kdev(K)); }
