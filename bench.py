@@ -31,81 +31,167 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, vendor figure
+KACZ_ROW_FLOPS = 50           # one Kaczmarz row update, real flops
+
+
 def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rbytes: int) -> float:
     """Bytes the method must move per launch, every array touched once
     (c = complex size, r = real size of the level precision; per fine node,
     plus c per coarse node where a coarse field is read or written):
       gs_down     read f, k; write coarse f                N (c + r) + Nc c
       gs_up       read f, k, coarse e; write u              N (2c + r) + Nc c
-    (the pre-smoothed iterate is recomputed on chip, never stored)
+      kacz_tb     read f, k, u; write u                     N (3c + r)
+    (the pre-smoothed iterate of gs_down is recomputed on chip, never stored)
     """
     c, r = cbytes, rbytes
     if kind == "gs_down":
         return nodes * (c + r) + coarse_nodes * c
     if kind == "gs_up":
         return nodes * (2 * c + r) + coarse_nodes * c
+    if kind == "kacz_tb":
+        return nodes * (3 * c + r)
     raise KeyError(kind)
 
 
-def time_kernels(hmg, torch, g, plan, precision, reps=96, sets=24):
-    """Average launch duration of the finest-level V-cycle kernels, timed with
-    torch events on torch's current stream (the library launches on the
-    stream it is given).  Launches cycle through `sets` independent buffer
-    sets (about 1 GB in total) so that each one reads its inputs from HBM, not
-    from the Infinity Cache."""
-    # a dedicated stream: torch's default stream has the NULL handle, which the
-    # library reads as "the grid's own stream", and events on it would not
-    # bracket the kernels
-    stream = torch.cuda.Stream()
+def graph_time(torch, stream, fn, count, reps=3):
+    """Average duration of one launch of fn: `count` launches are captured
+    into one HIP graph on `stream` and replayed, bracketed by HIP events on
+    that stream (so host launch gaps are not counted)."""
+    for q in range(count):
+        fn(q)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream, capture_error_mode="relaxed"):
+        for q in range(count):
+            fn(q)
+    with torch.cuda.stream(stream):
+        graph.replay()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            graph.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / count
+        best = ms if best is None else min(best, ms)
+    del graph
+    return best
+
+
+def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
+    """The V-cycle kernels timed by the benchmark, as closures over device
+    buffers shaped like the solve's: (name, level, launch(q), launches per
+    V-cycle, roofline model).  The finest-level Gauss-Seidel kernels cycle
+    through `sets` buffer sets (about 1 GB) so that they read from HBM."""
     cdt = torch.complex128 if precision == "fp64" else torch.complex64
     cb, rb = (16, 8) if precision == "fp64" else (8, 4)
-    n0, nc = plan[0]["n"], plan[1]["n"]
-    nodes, cnodes = (n0 + 2) ** 2, (nc + 2) ** 2
     gen = torch.Generator(device="cuda").manual_seed(0)
 
     def field(n):
         return torch.randn((n + 2, n + 2), dtype=cdt, device="cuda", generator=gen)
 
-    bufs = [dict(f=field(n0), uo=field(n0), ec=field(nc), fc=field(nc))
-            for _ in range(sets)]
-    torch.cuda.synchronize()
-    sa, sb = plan[0]["sigma_relax"], plan[0]["sigma_resid"]
-    cases = {
-        "gs_down": lambda b: g.op_gs_down(0, sa, sb, b["f"], None, b["fc"], stream),
-        "gs_up": lambda b: g.op_gs_up(0, sa, b["f"], b["ec"], b["uo"], stream),
-    }
-    out = {}
-    for name, fn in cases.items():
-        for q in range(sets):
-            fn(bufs[q])
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for q in range(reps):
-            fn(bufs[q % sets])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        b = algorithmic_bytes(name, nodes, cnodes, cb, rb)
-        out[name] = dict(ms_per_launch=ms, bytes=b, gbs=b / (ms * 1e-3) / 1e9, nodes=nodes)
-    del bufs
+    out = []
+    n0, nc = plan[0]["n"], plan[1]["n"]
+    nodes, cnodes = (n0 + 2) ** 2, (nc + 2) ** 2
+    if plan[0]["smoother"] == "GS" and plan[0]["pre"] == 1 and plan[0]["post"] == 1:
+        bufs = [dict(f=field(n0), uo=field(n0), ec=field(nc), fc=field(nc)) for _ in range(sets)]
+        sa, sb = plan[0]["sigma_relax"], plan[0]["sigma_resid"]
+        out.append(("gs_down", 0, lambda q, st: g.op_gs_down(0, sa, sb, bufs[q % sets]["f"], None,
+                                                             bufs[q % sets]["fc"], st), 1,
+                    ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb))))
+        out.append(("gs_up", 0, lambda q, st: g.op_gs_up(0, sa, bufs[q % sets]["f"], bufs[q % sets]["ec"],
+                                                         bufs[q % sets]["uo"], st), 1,
+                    ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb))))
+    for l, p in enumerate(plan):
+        cfg = g.kacz_config(l)
+        if cfg < 0:
+            continue
+        if fixed:
+            cfg = fixed[l]
+        tile, sweeps, _ = hmg_configs()[cfg]
+        n = p["n"]
+        kb = [dict(f=field(n), u=field(n), uo=field(n)) for _ in range(4)]
+        sig = p["sigma_relax"]
+        out.append(("kacz_tb", l,
+                    lambda q, st, l=l, sig=sig, cfg=cfg, kb=kb: g.op_kacz_tiled(
+                        l, sig, cfg, kb[q % 4]["f"], kb[q % 4]["u"], None, kb[q % 4]["uo"], st),
+                    (p["pre"] + p["post"]) // sweeps,
+                    ("alu", KACZ_ROW_FLOPS * sweeps * (n + 2) ** 2,
+                     algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb))))
     return out
 
 
-def cpu_baseline(h, k, f, variant, budget_s=30.0):
-    """The FP64 oracle on the host cores: one full solve of the same problem
-    (bounded: the solve is cut at the iteration count that fits the budget
-    and the rate extrapolated per full solve)."""
+def hmg_configs():
+    from paper_1312_2880_amd import hmg
+    return hmg.kacz_tile_configs()
+
+
+def roofline_of(model, ms):
+    if model[0] == "hbm":
+        achieved = model[1] / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    achieved = model[1] / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
+            "hbm_equiv_gbs": round(model[2] / (ms * 1e-3) / 1e9, 1)}
+
+
+def time_kernels(torch, g, plan, precision, only=None, fixed=None):
+    stream = torch.cuda.Stream()
+    res = []
+    for name, level, fn, per_vc, model in kernel_cases(torch, g, plan, precision, fixed=fixed):
+        key = f"{name}@{plan[level]['n']}"
+        if only and key != only:
+            continue
+        ms = graph_time(torch, stream, lambda q: fn(q, stream), 48)
+        res.append(dict(key=key, name=name, level=level, ms=ms, per_vcycle=per_vc, model=model))
+    torch.cuda.synchronize()
+    return res
+
+
+COPY_BYTES = 512 << 20
+
+
+def traffic_probe(torch, g, plan, precision, which, fixed):
+    """Launches kernel `which` (e.g. "kacz_tb@127") 48 times as the timing
+    does, then copies COPY_BYTES device to device three times (the counter
+    reference)."""
+    kt = time_kernels(torch, g, plan, precision, only=which, fixed=fixed)
+    if not kt:
+        raise SystemExit(f"no kernel {which}")
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_probe": which, "copy_bytes": COPY_BYTES,
+                      "kernel_ms": round(kt[0]["ms"], 5)}), flush=True)
+
+
+def cpu_baseline(h, k, f, variant, budget_s=10.0, max_solves=3):
+    """The FP64 oracle on the host cores, on the same problem: full solves
+    until about `budget_s` seconds have passed (at most `max_solves`); the
+    rate is solves per second of wall time."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     og = oracle.Grid(h, k, variant=variant)
     t0 = time.perf_counter()
-    _, info = og.bicgstab(f, rtol=1e-6, maxit=400)
+    done, iters = 0, []
+    while done < max_solves and (done == 0 or time.perf_counter() - t0 < budget_s):
+        _, info = og.bicgstab(f, rtol=1e-6, maxit=400)
+        iters.append(info["iters"])
+        done += 1
     dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"one full FP64 solve of the same problem on {threads} threads "
-                       f"({info['iters']} iterations, {dt:.1f} s)",
-                iters=info["iters"])
+    return dict(value=done / dt, unit="solves/s", cores=threads, kind="oracle",
+                sample=f"{done} full FP64 oracle solve(s) of the same 1023^2 problem on {threads} threads "
+                       f"({iters[-1]} iterations each, {dt:.1f} s in total)",
+                iters=iters[-1])
 
 
 def main():
@@ -116,6 +202,13 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maxit", type=int, default=400)
+    ap.add_argument("--traffic-probe", default=None, metavar="KERNEL@N",
+                    help="only launch this kernel (e.g. kacz_tb@127) as the timing does, then "
+                         "a plain copy of known size, for the FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--kacz-configs", default=None, metavar="C,C,...",
+                    help="tile configuration per level for the tiled Kaczmarz levels (-1 elsewhere) "
+                         "instead of tuning; counter runs pass the configurations the timed run "
+                         "reported, since counters distort the tuner's timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
@@ -132,8 +225,16 @@ def main():
     n = k.shape[0] - 2
     prec = hmg.FP64 if args.precision == "fp64" else hmg.MIXED
     ctx = hmg.Context(0)
-    g = hmg.Grid(ctx, h, k, f, variant=hmg.HYB, precision=prec)
+    fixed = None
+    if args.kacz_configs:
+        fixed = [int(c) for c in args.kacz_configs.split(",")]
+    g = hmg.Grid(ctx, h, k, f, variant=hmg.HYB, precision=prec, autotune=0 if fixed else 1)
     plan = g.plan()
+    if args.traffic_probe:
+        traffic_probe(torch, g, plan, args.precision, args.traffic_probe, fixed)
+        g.close()
+        ctx.close()
+        return
     stream = torch.cuda.current_stream()
     d_b = torch.from_numpy(f).to("cuda")
     d_x = torch.zeros_like(d_b)
@@ -151,25 +252,28 @@ def main():
     last = infos[-1]
     ok = all(i["status"] == hmg.OK and i["rel_res_true"] <= 1e-6 for i in infos)
 
-    kt = time_kernels(hmg, torch, g, plan, args.precision)
-    # dominant V-cycle kernel: the finest-level kernel with the longest launch
-    dom = max(kt, key=lambda name: kt[name]["ms_per_launch"])
-    d = kt[dom]
-    achieved = d["gbs"]
+    # the V-cycle kernels: per-launch time from graph replays, share of the
+    # solve from launches per iteration (two V-cycles per Bi-CGSTAB iteration)
+    kt = time_kernels(torch, g, plan, args.precision)
+    mean_iters = sum(i["iters"] for i in infos[args.warmup:]) / args.steps
+    it_ms = 1e3 * dt / args.steps / max(mean_iters, 0.5)
+    for k_ in kt:
+        k_["per_iter"] = 2 * k_["per_vcycle"]
+        k_["share"] = k_["ms"] * k_["per_iter"] / it_ms
+        k_["roofline"] = roofline_of(k_["model"], k_["ms"])
+    dom = max(kt, key=lambda k_: k_["share"])
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            ent = tr.get(f"{dom}:{args.precision}")
+            ent = tr.get(f"{dom['key']}:{args.precision}")
             if ent and ent.get("kernel_source_hash") == kernel_source_hash():
                 traffic = ent.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "level_nodes": d["nodes"],
-                "ms_per_launch": round(d["ms_per_launch"], 5),
-                "bytes_per_launch": d["bytes"]}
+    roofline = dict(dom["roofline"])
+    roofline.update({"traffic": traffic, "kernel": dom["key"], "ms_per_launch": round(dom["ms"], 5),
+                     "per_launch": dom["model"][1], "share_of_solve": round(dom["share"], 3)})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -192,12 +296,13 @@ def main():
         "config": {"workload": "layered-medium Helmholtz 1023x1023, omega = 2 pi 40, "
                                "HYB-V preconditioned Bi-CGSTAB to 1e-6, seed 2",
                    "n": n, "precision": args.precision,
-                   "iters": last["iters"], "rel_res_true": last["rel_res_true"],
+                   "iters": last["iters"], "mean_iters": mean_iters, "rel_res_true": last["rel_res_true"],
                    "all_converged": ok,
-                   "levels": [(p["n"], p["smoother"]) for p in plan]},
+                   "levels": [(p["n"], p["smoother"]) for p in plan],
+                   "kacz_configs": ",".join(str(g.kacz_config(l)) for l in range(len(plan)))},
         "roofline": roofline,
-        "kernels": {name: {"ms_per_launch": round(v["ms_per_launch"], 5),
-                           "gbs": round(v["gbs"], 1)} for name, v in kt.items()},
+        "kernels": {k_["key"]: {"ms_per_launch": round(k_["ms"], 5), "launches_per_iter": k_["per_iter"],
+                                "share_of_solve": round(k_["share"], 3), **k_["roofline"]} for k_ in kt},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -5,7 +5,7 @@ footprint), against the same stream served one request at a time in FP64.
     python bench_serve.py [--rates 5,20,50] [--count 30] [--warmup 4]
 
 Each request: n ~ U{255, 511, 1023, 2047}, a seeded layered medium with
-omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, SL-V
+omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, HYB-V
 preconditioner, relative residual 1e-6.  The served form runs the V-cycle in
 complex float under the FP64 Bi-CGSTAB; the baseline runs plain FP64 with at
 most one request in flight.  Latency = completion time - submission time on
@@ -49,7 +49,7 @@ def make_requests(rate, count, warmup, seed):
     return reqs
 
 
-def serve(hmg, reqs, precision, max_active, warmup):
+def serve(hmg, reqs, precision, max_active, warmup, maxit):
     ctx = hmg.Context(0)
     ctx.set_max_active(max_active)
     tickets = [None] * len(reqs)
@@ -62,7 +62,7 @@ def serve(hmg, reqs, precision, max_active, warmup):
             if delay > 0:
                 time.sleep(delay)
             tickets[q] = ctx.submit(n=r["n"], h=r["h"], k=r["k"], f=r["f"], rtol=1e-6,
-                                    maxit=800, variant=hmg.SL, precision=precision)
+                                    maxit=maxit, variant=hmg.HYB, precision=precision)
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -83,6 +83,7 @@ def serve(hmg, reqs, precision, max_active, warmup):
         solves=len(timed), value=len(timed) / span, p50_s=percentile(lat, 50),
         p99_s=percentile(lat, 99), mean_iters=sum(r["iters"] for r in timed) / len(timed),
         all_converged=all(r["status"] == hmg.OK and r["rel_res_true"] <= 1e-6 for r in timed),
+        max_iters=max(r["iters"] for r in timed),
         mean_queue_s=sum(r["t_admit"] - r["t_arrive"] for r in timed) / len(timed))
 
 
@@ -93,6 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--max-active", type=int, default=0)
+    ap.add_argument("--maxit", type=int, default=2000)
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -101,15 +103,16 @@ def main():
         reqs = make_requests(rate, args.count, args.warmup, args.seed)
         for form, prec, act in (("served-mixed", hmg.MIXED, args.max_active),
                                 ("serial-fp64", hmg.FP64, 1)):
-            out = serve(hmg, reqs, prec, act, args.warmup)
+            out = serve(hmg, reqs, prec, act, args.warmup, args.maxit)
             line = {"metric": "solves/s and p50/p99 latency, Poisson request stream",
                     "form": form, "rate_req_s": rate, "unit": "solves/s",
                     "value": round(out["value"], 3),
                     "p50_ms": round(1e3 * out["p50_s"], 2), "p99_ms": round(1e3 * out["p99_s"], 2),
                     "mean_queue_ms": round(1e3 * out["mean_queue_s"], 2),
-                    "mean_iters": round(out["mean_iters"], 2), "solves": out["solves"],
+                    "mean_iters": round(out["mean_iters"], 2), "max_iters": out["max_iters"],
+                    "solves": out["solves"],
                     "all_converged": out["all_converged"], "data": "synthetic",
-                    "config": {"sizes": [255, 511, 1023, 2047], "variant": "SL-V",
+                    "config": {"sizes": [255, 511, 1023, 2047], "variant": "HYB-V",
                                "seed": args.seed, "rtol": 1e-6}}
             print(json.dumps(line), flush=True)
 

@@ -86,7 +86,13 @@ typedef struct {
     int    autotune;         /* 1: time the Kaczmarz tile configurations on the
                                 level's shape at grid creation (cached per
                                 process); 0: fixed default                      */
-    int    reserved[5];
+    int    bottom_dense;     /* 1: the cycle on the bottom levels (n <= 31) is a
+                                fixed linear map of its right-hand side; form
+                                its matrix (complex FP64, m^2 entries for
+                                m = (n+2)^2 nodes) at grid creation and apply
+                                it as a matrix-vector product (default);
+                                0: run the bottom levels in one workgroup     */
+    int    reserved[4];
 } hmg_opts;
 
 #define HMG_MAX_LEVELS 24
@@ -263,9 +269,10 @@ hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int confi
 /* Tile configuration chosen for a Kaczmarz level of the grid (-1: the level
  * is not relaxed by the tiled kernel). */
 int        hmg_grid_kacz_config(const hmg_grid *g, int level);
-/* Tile side and sweeps per launch of Kaczmarz tile configuration `config`;
- * returns the number of configurations, or -1 for an unknown one. */
-int        hmg_kacz_tile_config(int config, int *tile, int *sweeps);
+/* Tile side, sweeps per launch and workgroup size of Kaczmarz tile
+ * configuration `config` (NULL outputs are skipped); returns the number of
+ * configurations, or -1 for an unknown one. */
+int        hmg_kacz_tile_config(int config, int *tile, int *sweeps, int *threads);
 
 #ifdef __cplusplus
 }

@@ -64,6 +64,7 @@ extern "C" void hmg_opts_default(hmg_opts *o) {
     o->use_graph = 1;
     o->one_pass_kernels = 0;
     o->autotune = 1;
+    o->bottom_dense = 1;
 }
 
 // Level classification (Section 5).  The paper states its rules on grids
@@ -221,6 +222,12 @@ static void layout(hmg_grid *g, Carver &c) {
     g->k0 = (double *)c.take((size_t)g->lev[0].geo.M * g->lev[0].geo.M * 8);
     int mc = g->lev[g->nlev - 1].geo.M;
     g->ainv_t = (double *)c.take((size_t)mc * mc * (size_t)mc * mc * 16);
+    g->bop = nullptr;
+    g->bop_m = 0;
+    if (g->lb >= 0 && g->opts.bottom_dense) {
+        g->bop_m = g->lev[g->lb].geo.M * g->lev[g->lb].geo.M;
+        g->bop = (double *)c.take((size_t)g->bop_m * g->bop_m * 16);
+    }
     size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
     int nb = krylov_nblocks(g->lev[0].geo);
     for (int s = 0; s < g->nrhs; ++s) {
@@ -246,28 +253,31 @@ static void layout(hmg_grid *g, Carver &c) {
 // whose fields (u on every level, f below its first level) fit in the LDS of
 // one workgroup; above it, Gauss-Seidel levels with one pre- and one post-
 // sweep use the fused down/up kernels and Kaczmarz levels the tiled kernel.
-static void plan_paths(hmg_grid *g) {
-    g->lb = -1;
-    for (int l = 0; l < g->nlev; ++l) {
-        g->lev[l].mode = LM_SIMPLE;
-        g->lev[l].kacz_cfg = 0;
-    }
-    if (g->opts.one_pass_kernels) return;
-    // the bottom solver keeps u, f and k of each of its levels in LDS and is
-    // used for levels with n <= 31
+// First level of the bottom solver (-1: none); depends on the level sizes
+// and the options only.  The bottom solver keeps u, f and k of each of its
+// levels in LDS and is used for levels with n <= 31.
+static int find_bottom(const hmg_grid *g) {
+    if (g->opts.one_pass_kernels) return -1;
     for (int l = 0; l < g->nlev; ++l) {
         if (g->nlev - l > BOT_MAXL || g->lev[l].geo.n > 31) continue;
         int cs = 0, rs = 0;
         for (int q = l; q < g->nlev; ++q) {
-            int m = g->lev[q].geo.M * g->lev[q].geo.M;
-            cs += 2 * m;
-            rs += 2 * m;   // k and a reciprocal per node
+            int M = g->lev[q].geo.M, m = M * M;
+            cs += (M + 2) * (M + 2) + m;   // u with a ring of zero cells, f
+            rs += 2 * m;                   // k and a reciprocal per node
         }
-        if (cs <= bottom_complex_slots() && rs <= bottom_real_slots()) {
-            g->lb = l;
-            break;
-        }
+        if (cs <= bottom_complex_slots() && rs <= bottom_real_slots()) return l;
     }
+    return -1;
+}
+
+static void plan_paths(hmg_grid *g) {
+    for (int l = 0; l < g->nlev; ++l) {
+        g->lev[l].mode = LM_SIMPLE;
+        g->lev[l].kacz_cfg = 0;
+    }
+    g->lb = find_bottom(g);
+    if (g->opts.one_pass_kernels) return;
     int top = (g->lb < 0) ? g->nlev - 1 : g->lb;
     for (int l = 0; l < top; ++l) {
         const hmg_plan &pl = g->plan;
@@ -301,7 +311,7 @@ static void bottom_desc(hmg_grid *g) {
         D.pre = g->plan.pre[l];
         D.post = g->plan.post[l];
         D.uoff = off;
-        off += (D.n + 2) * (D.n + 2);
+        off += (D.n + 4) * (D.n + 4);   // u is stored with a ring of zero cells
     }
     for (int q = 0; q < d.nlev; ++q) {
         BottomLevelDesc &D = d.L[q];
@@ -349,9 +359,11 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         const Level &L = g->lev[l];
         Slot &S = g->slot[0];
         size_t bytes = (size_t)L.geo.M * L.geo.M * (g->prec == P64 ? 16 : 8);
+        size_t cbytes = (size_t)g->lev[l + 1].geo.M * g->lev[l + 1].geo.M * (g->prec == P64 ? 16 : 8);
         HIPCHK(hipMemsetAsync(S.f[l], 0, bytes, g->stream));
         HIPCHK(hipMemsetAsync(S.u[l], 0, bytes, g->stream));
         HIPCHK(hipMemsetAsync(S.u2[l], 0, bytes, g->stream));
+        HIPCHK(hipMemsetAsync(S.u[l + 1], 0, cbytes, g->stream));
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
@@ -359,7 +371,9 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         int best = g->lev[l].kacz_cfg;
         for (int cfg : cand) {
             int sw = kKaczCfgs[cfg].sweeps;
-            auto leg = [&]() {
+            // the level's two legs as the V-cycle runs them: pre sweeps from
+            // zero, post sweeps from u + P e
+            auto legs = [&]() {
                 const void *cur = nullptr;
                 void *bufs[2] = {S.u[l], S.u2[l]};
                 int w = 0;
@@ -369,14 +383,38 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                     cur = bufs[w];
                     w ^= 1;
                 }
+                for (int q = 0; q < pl.post[l] && cur; q += sw) {
+                    launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l], S.f[l], cur,
+                                   q == 0 ? S.u[l + 1] : nullptr, bufs[w], nullptr);
+                    cur = bufs[w];
+                    w ^= 1;
+                }
             };
-            leg();
-            HIPCHK(hipEventRecord(e0, g->stream));
-            for (int r = 0; r < 3; ++r) leg();
-            HIPCHK(hipEventRecord(e1, g->stream));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            // timed as a graph replay, the way the solver launches them
+            hipGraph_t gr = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+            for (int r = 0; r < 3; ++r) legs();
+            HIPCHK(hipStreamEndCapture(g->stream, &gr));
+            hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(gr);
+                return hmg_fail(HMG_ERR_DEVICE, "tuner graph: %s", hipGetErrorString(ie));
+            }
+            float ms = 1e30f;
+            hipError_t le = hipGraphLaunch(ge, g->stream);   // warm-up
+            for (int r = 0; r < 2 && le == hipSuccess; ++r) {
+                le = hipEventRecord(e0, g->stream);
+                if (le == hipSuccess) le = hipGraphLaunch(ge, g->stream);
+                if (le == hipSuccess) le = hipEventRecord(e1, g->stream);
+                if (le == hipSuccess) le = hipEventSynchronize(e1);
+                float t = 0.f;
+                if (le == hipSuccess) le = hipEventElapsedTime(&t, e0, e1);
+                if (le == hipSuccess) ms = std::min(ms, t);
+            }
+            (void)hipGraphExecDestroy(ge);
+            (void)hipGraphDestroy(gr);
+            if (le != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "tuner: %s", hipGetErrorString(le));
             if (ms < best_ms) {
                 best_ms = ms;
                 best = cfg;
@@ -422,6 +460,8 @@ size_t estimate_footprint(int n, const hmg_opts &o) {
         H *= 2.0;
     }
     g.nlev = l + 1;
+    g.opts = o;
+    g.lb = find_bottom(&g);
     g.slot.resize(1);
     Carver c;
     layout(&g, c);
@@ -513,6 +553,13 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     layout(g, c);
     bottom_desc(g);
     hmg_status st = grid_init_device(g, kl, inv, f);
+    if (st == HMG_OK && g->bop) {
+        // the bottom cycle on every unit vector: its matrix, column by column
+        launch_bottom_basis(g->prec, g->stream, g->bottom, g->bop);
+        hipError_t le = hipGetLastError();
+        if (le == hipSuccess) le = hipStreamSynchronize(g->stream);
+        if (le != hipSuccess) st = hmg_fail(HMG_ERR_DEVICE, "bottom matrix: %s", hipGetErrorString(le));
+    }
     if (st == HMG_OK) st = tune_levels(g);
     if (st != HMG_OK) {
         hmg_grid_destroy(g);
@@ -627,7 +674,8 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
     const hmg_plan &pl = g->plan;
     if (l == g->lb) {
         void *dst = out ? out : S.u[l];
-        launch_bottom(g->prec, f64, s, g->bottom, f, dst, skip);
+        if (g->bop) launch_dense_apply(g->prec, f64, s, g->bop, g->bop_m, f, dst, skip);
+        else launch_bottom(g->prec, f64, s, g->bottom, f, dst, skip);
         return dst;
     }
     if (L.mode == LM_GS_FUSED) {
@@ -843,9 +891,10 @@ extern "C" hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma
     return HMG_OK;
 }
 
-extern "C" int hmg_kacz_tile_config(int config, int *tile, int *sweeps) {
+extern "C" int hmg_kacz_tile_config(int config, int *tile, int *sweeps, int *threads) {
     if (config < 0 || config >= KACZ_NCFG) return -1;
     if (tile) *tile = kKaczCfgs[config].ts;
     if (sweeps) *sweeps = kKaczCfgs[config].sweeps;
+    if (threads) *threads = kKaczCfgs[config].threads;
     return KACZ_NCFG;
 }

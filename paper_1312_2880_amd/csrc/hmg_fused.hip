@@ -27,27 +27,64 @@
 
 namespace hmgk {
 
-// sum_{q != p} a_pq U_q for an LDS array with row length LW (node p at l)
+// sum_{q != p} a_pq U_q for an LDS array with row length LW (node p at l),
+// neighbours in the order left, right, down, up.  The cells of a region
+// that lie outside the domain hold zero and the row gives a missing
+// neighbour weight zero, so all four cells are read without tests.
 template <typename T>
-__device__ __forceinline__ C<T> offsum_l(const Row<T> &r, const C<T> *U, int l, int LW, int i, int j, int N) {
+__device__ __forceinline__ C<T> offsum_z(const Row<T> &r, const C<T> *U, int l, int LW) {
+    const C<T> ul = U[l - 1], ur = U[l + 1], ud = U[l - LW], uu = U[l + LW];
     C<T> s = cmk(T(0), T(0));
-    if (i > 0) s = cadd(s, cscale(r.wl, U[l - 1]));
-    if (i < N) s = cadd(s, cscale(r.wr, U[l + 1]));
-    if (j > 0) s = cadd(s, cscale(r.wd, U[l - LW]));
-    if (j < N) s = cadd(s, cscale(r.wu, U[l + LW]));
+    s = cadd(s, cscale(r.wl, ul));
+    s = cadd(s, cscale(r.wr, ur));
+    s = cadd(s, cscale(r.wd, ud));
+    s = cadd(s, cscale(r.wu, uu));
     return s;
 }
 
-// bilinear interpolation of the coarse correction at fine node (i, j)
+// One Kaczmarz row update in LDS (Section 4): d = (f_p - a_p u) / ||a_p||^2,
+// u += conj(a_p) d on the five cells of the row.  Cells outside the domain
+// are zero with zero weight and stay zero.
+__device__ __forceinline__ void kacz_row_lds(C<double> *U, int l, int LW, const Row<double> &r, C<double> fp,
+                                             double invn) {
+    const C<double> uc = U[l], ul = U[l - 1], ur = U[l + 1], ud = U[l - LW], uu = U[l + LW];
+    C<double> s = cmk(0.0, 0.0);
+    s = cadd(s, cscale(r.wl, ul));
+    s = cadd(s, cscale(r.wr, ur));
+    s = cadd(s, cscale(r.wd, ud));
+    s = cadd(s, cscale(r.wu, uu));
+    const C<double> res = csub(fp, cadd(cmul(cmk(r.dre, r.dim), uc), s));
+    const C<double> d = cmk(res.x * invn, res.y * invn);
+    U[l] = cmk(uc.x + (r.dre * d.x + r.dim * d.y), uc.y + (r.dre * d.y - r.dim * d.x));
+    U[l - 1] = cadd(ul, cscale(r.wl, d));
+    U[l + 1] = cadd(ur, cscale(r.wr, d));
+    U[l - LW] = cadd(ud, cscale(r.wd, d));
+    U[l + LW] = cadd(uu, cscale(r.wu, d));
+}
+
+// Bilinear interpolation (Section 5) of the four coarse values around fine
+// node (i, j): e00 = e(I, J), e10 = e(I+1, J), e01 = e(I, J+1),
+// e11 = e(I+1, J+1) with I = i/2, J = j/2.  Selects, not branches; the sums
+// are those of the one-pass prolongation, in the same order.
+__device__ __forceinline__ C<double> bilinear(C<double> e00, C<double> e10, C<double> e01, C<double> e11, int i,
+                                              int j) {
+    const bool xo = i & 1, yo = j & 1;
+    const C<double> sx = xo ? cadd(e00, e10) : e00;
+    const C<double> s = yo ? (xo ? cadd(cadd(sx, e01), e11) : cadd(e00, e01)) : sx;
+    const double w = (xo ? 0.5 : 1.0) * (yo ? 0.5 : 1.0);
+    return cscale(w, s);
+}
+
+// bilinear interpolation of a coarse field in global memory at fine node
+// (i, j) of the domain; the four loads are unconditional (indices clamped
+// into the coarse grid; a clamped value gets weight zero)
 template <typename T>
 __device__ __forceinline__ C<double> prolong_at(const C<T> *ec, int i, int j, int Mc) {
-    int I = i >> 1, J = j >> 1;
-    size_t q = (size_t)J * Mc + I;
-    if (!(i & 1) && !(j & 1)) return ldr<double>(ec, q);
-    if ((i & 1) && !(j & 1)) return cscale(0.5, cadd(ldr<double>(ec, q), ldr<double>(ec, q + 1)));
-    if (!(i & 1) && (j & 1)) return cscale(0.5, cadd(ldr<double>(ec, q), ldr<double>(ec, q + Mc)));
-    return cscale(0.25, cadd(cadd(cadd(ldr<double>(ec, q), ldr<double>(ec, q + 1)), ldr<double>(ec, q + Mc)),
-                             ldr<double>(ec, q + Mc + 1)));
+    const int I = i >> 1, J = j >> 1;
+    const int I1 = min(I + 1, Mc - 1), J1 = min(J + 1, Mc - 1);
+    const C<double> e00 = ldr<double>(ec, (size_t)J * Mc + I), e10 = ldr<double>(ec, (size_t)J * Mc + I1);
+    const C<double> e01 = ldr<double>(ec, (size_t)J1 * Mc + I), e11 = ldr<double>(ec, (size_t)J1 * Mc + I1);
+    return bilinear(e00, e10, e01, e11, i, j);
 }
 
 __device__ __forceinline__ int mirror(int x, int N) { return x < 0 ? -x : (x > N ? 2 * N - x : x); }
@@ -110,13 +147,18 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
                 kr[c][m] = (double)k[p];
             }
         }
-    // red on tile + 3 (zero guess: u = f / a_pp)
+    // red on tile + 3 (zero guess: u = f / a_pp); cells outside the domain
+    // are set to zero (missing neighbours of the rows below)
 #pragma unroll
     for (int m = 0; m < GNS; ++m) {
         int lx, ly;
         bool own = gs_owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || i < 0 || j < 0 || i > N || j > N) continue;
+        if (!own) continue;
+        if (i < 0 || j < 0 || i > N || j > N) {
+            U[ly * GLW + lx] = cmk(0.0, 0.0);
+            continue;
+        }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
         U[ly * GLW + lx] = cdiv(fr[0][m], r.dre, r.dim);
     }
@@ -127,10 +169,14 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
         int lx, ly;
         bool own = gs_owned(tid, 1, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !in_ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
+        if (!own || !in_ring(lx, ly, 2)) continue;
         int l = ly * GLW + lx;
+        if (i < 0 || j < 0 || i > N || j > N) {
+            U[l] = cmk(0.0, 0.0);
+            continue;
+        }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-        U[l] = cdiv(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim);
+        U[l] = cdiv(csub(fr[1][m], offsum_z(r, U, l, GLW)), r.dre, r.dim);
     }
     __syncthreads();
     // the smoothed iterate on the tile (only when asked for: the up kernel
@@ -158,7 +204,7 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
             if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
             int l = ly * GLW + lx;
             Row<double> r = row_at<double>(i, j, N, H, ih2, kr[c][m], sb);
-            C<double> au = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_l(r, U, l, GLW, i, j, N));
+            C<double> au = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, GLW));
             res[c][m] = csub(fr[c][m], au);
         }
     __syncthreads();
@@ -228,13 +274,17 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
                 kr[c][m] = (double)k[p];
             }
         }
-    // red u0 on tile + 3
+    // red u0 on tile + 3 (zero outside the domain)
 #pragma unroll
     for (int m = 0; m < GNS; ++m) {
         int lx, ly;
         bool own = gs_owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || i < 0 || j < 0 || i > N || j > N) continue;
+        if (!own) continue;
+        if (i < 0 || j < 0 || i > N || j > N) {
+            U[ly * GLW + lx] = cmk(0.0, 0.0);
+            continue;
+        }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
         U[ly * GLW + lx] = cdiv(fr[0][m], r.dre, r.dim);
     }
@@ -245,11 +295,14 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         int lx, ly;
         bool own = gs_owned(tid, 1, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !in_ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
+        if (!own || !in_ring(lx, ly, 2)) continue;
         int l = ly * GLW + lx;
+        if (i < 0 || j < 0 || i > N || j > N) {
+            U[l] = cmk(0.0, 0.0);
+            continue;
+        }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-        U[l] = cadd(cdiv(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim),
-                    prolong_at(ec, i, j, Mc));
+        U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, GLW)), r.dre, r.dim), prolong_at(ec, i, j, Mc));
     }
     __syncthreads();
     // the correction on the red nodes of tile + 2 (after every black u0 has
@@ -273,7 +326,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
         int l = ly * GLW + lx;
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[l] = cdiv(csub(fr[0][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim);
+        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, GLW)), r.dre, r.dim);
     }
     __syncthreads();
     // black on the tile -> output; red tile nodes -> output
@@ -289,7 +342,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
             C<double> v = U[l];
             if (c == 1) {
                 Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-                v = cdiv(csub(fr[1][m], offsum_l(r, U, l, GLW, i, j, N)), r.dre, r.dim);
+                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, GLW)), r.dre, r.dim);
             }
             uo[(size_t)j * M + i] = st_as<TU>(v);
         }
@@ -301,16 +354,19 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
 // Pass q (colour q mod 5) updates the rows on tile + (RH - 2q - 1); after it
 // u is exact on tile + (RH - 2q - 2), and after the last pass on the tile
 // itself.  Each thread keeps the same row slots (line, column slot) in every
-// pass, so a pass needs no division to find its rows.  Initial u: 0 (ui ==
-// null) or ui, plus P ec when ec != null.
+// pass, so a pass needs no division to find its rows.  Cells of the region
+// outside the domain hold zero; two rows of one colour never share a cell
+// (the five-point stars of one colour tile the plane), so a row reads and
+// writes its five cells without tests and the padding stays zero.  Initial
+// u: 0 (ui == null) or ui, plus P ec when ec != null.  The region is loaded
+// CH cells per thread at a time with every global load of a batch issued
+// before the first is used (indices clamped into the domain).
 // ===========================================================================
-constexpr int KNT = 512;
-
-template <typename T, int TS, int S>
-__global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, const T *__restrict__ k, double sig,
-                                                 const C<T> *__restrict__ f, const C<T> *__restrict__ ui,
-                                                 const C<T> *__restrict__ ec, C<T> *__restrict__ uo,
-                                                 const int *skip) {
+template <typename T, int TS, int S, int NT>
+__global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, const T *__restrict__ k, double sig,
+                                                const C<T> *__restrict__ f, const C<T> *__restrict__ ui,
+                                                const C<T> *__restrict__ ec, C<T> *__restrict__ uo,
+                                                const int *skip) {
     if (skip && *skip) return;
     constexpr int RH = 10 * S, LW = TS + 2 * RH;
     // f and (k, 1/||a_p||^2) of the region are staged in LDS when they fit
@@ -318,7 +374,9 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
     constexpr bool STAGE = (size_t)LW * LW * (16 + 16 + 16) <= 160 * 1024;
     constexpr int T5 = (LW - 2 + 4) / 5;              // row slots per line and colour
     constexpr int NSLOT = (LW - 2) * T5;              // slots per colour
-    constexpr int NM = (NSLOT + KNT - 1) / KNT;       // slots per thread and colour
+    constexpr int NM = (NSLOT + NT - 1) / NT;         // slots per thread and colour
+    constexpr int NL = (LW * LW + NT - 1) / NT;       // region cells per thread
+    constexpr int CH = NL < 4 ? NL : 4;               // cells per load batch
     __shared__ C<double> U[LW * LW];
     __shared__ C<double> FS[STAGE ? LW * LW : 1];
     __shared__ C<double> KS[STAGE ? LW * LW : 1];
@@ -326,19 +384,42 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
     const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS;
     const int ox = x0 - RH, oy = y0 - RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
-    for (int q = tid; q < LW * LW; q += KNT) {
-        int i = ox + q % LW, j = oy + q / LW;
-        if (i < 0 || j < 0 || i > N || j > N) continue;
-        size_t p = (size_t)j * M + i;
-        C<double> v = ui ? ldr<double>(ui, p) : cmk(0.0, 0.0);
-        if (ec) v = cadd(v, prolong_at(ec, i, j, Mc));
-        U[q] = v;
-        if (STAGE) {
-            FS[q] = ldr<double>(f, p);
-            double kp = (double)k[p];
-            Row<double> r = row_at<double>(i, j, N, H, ih2, kp, sig);
-            double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
-            KS[q] = cmk(kp, 1.0 / nrm);
+    for (int b0 = 0; b0 < NL; b0 += CH) {
+        C<double> vu[CH], vf[CH], e[CH][4];
+        double vk[CH];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int q = tid + NT * (b0 + s);
+            const int i = min(max(ox + q % LW, 0), N), j = min(max(oy + q / LW, 0), N);
+            const size_t p = (size_t)j * M + i;
+            vu[s] = ui ? ldr<double>(ui, p) : cmk(0.0, 0.0);
+            if (ec) {
+                const int I = i >> 1, J = j >> 1, I1 = min(I + 1, Mc - 1), J1 = min(J + 1, Mc - 1);
+                e[s][0] = ldr<double>(ec, (size_t)J * Mc + I);
+                e[s][1] = ldr<double>(ec, (size_t)J * Mc + I1);
+                e[s][2] = ldr<double>(ec, (size_t)J1 * Mc + I);
+                e[s][3] = ldr<double>(ec, (size_t)J1 * Mc + I1);
+            }
+            if (STAGE) {
+                vf[s] = ldr<double>(f, p);
+                vk[s] = (double)k[p];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int q = tid + NT * (b0 + s);
+            if (q >= LW * LW) continue;
+            const int i = ox + q % LW, j = oy + q / LW;
+            const bool in = i >= 0 && j >= 0 && i <= N && j <= N;
+            C<double> v = vu[s];
+            if (ec) v = cadd(v, bilinear(e[s][0], e[s][1], e[s][2], e[s][3], i, j));
+            U[q] = in ? v : cmk(0.0, 0.0);
+            if (STAGE) {
+                Row<double> r = row_at<double>(min(max(i, 0), N), min(max(j, 0), N), N, H, ih2, vk[s], sig);
+                double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+                FS[q] = in ? vf[s] : cmk(0.0, 0.0);
+                KS[q] = in ? cmk(vk[s], 1.0 / nrm) : cmk(0.0, 0.0);
+            }
         }
     }
     // row slots of this thread: line ly = 1 + s / T5, column slot t = s % T5;
@@ -346,7 +427,7 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
     int sly[NM], sbase[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-        int sl = tid + KNT * m;
+        int sl = tid + NT * m;
         sly[m] = (sl < NSLOT) ? 1 + sl / T5 : -1;
         sbase[m] = 5 * (sl % T5);
     }
@@ -363,27 +444,20 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
             const int i = ox + lx;
             if (lx < lo || lx > hi || i < 0 || j < 0 || i > N || j > N) continue;
             const int l = ly * LW + lx;
-            size_t p = (size_t)j * M + i;
-            C<double> kc = STAGE ? KS[l] : cmk((double)k[p], 0.0);
-            Row<double> r = row_at<double>(i, j, N, H, ih2, kc.x, sig);
-            C<double> fp = STAGE ? FS[l] : ldr<double>(f, p);
-            C<double> res = csub(fp, cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_l(r, U, l, LW, i, j, N)));
-            double invn = kc.y;
-            if (!STAGE) {
+            if (STAGE) {
+                const C<double> kc = KS[l];
+                const C<double> fp = FS[l];
+                kacz_row_lds(U, l, LW, row_at<double>(i, j, N, H, ih2, kc.x, sig), fp, kc.y);
+            } else {
+                const size_t p = (size_t)j * M + i;
+                Row<double> r = row_at<double>(i, j, N, H, ih2, (double)k[p], sig);
                 double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
-                invn = 1.0 / nrm;
+                kacz_row_lds(U, l, LW, r, ldr<double>(f, p), 1.0 / nrm);
             }
-            C<double> d = cmk(res.x * invn, res.y * invn);
-            C<double> up = U[l];
-            U[l] = cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x));
-            if (i > 0) U[l - 1] = cadd(U[l - 1], cscale(r.wl, d));
-            if (i < N) U[l + 1] = cadd(U[l + 1], cscale(r.wr, d));
-            if (j > 0) U[l - LW] = cadd(U[l - LW], cscale(r.wd, d));
-            if (j < N) U[l + LW] = cadd(U[l + LW], cscale(r.wu, d));
         }
         __syncthreads();
     }
-    for (int q = tid; q < TS * TS; q += KNT) {
+    for (int q = tid; q < TS * TS; q += NT) {
         int i = x0 + q % TS, j = y0 + q / TS;
         if (i > N || j > N) continue;
         uo[(size_t)j * M + i] = st_as<T>(U[(j - oy) * LW + (i - ox)]);
@@ -394,11 +468,17 @@ __global__ __launch_bounds__(KNT) void k_kacz_tb(GeoT g, double H, double ih2, c
 // k_bottom: the V-cycle on levels lb..L-1 (n <= 31) in one workgroup of BNT
 // threads.  Every field of every bottom level (u, f and k) lives in LDS, so
 // the dependent colour passes never wait on global memory; only the first
-// level's f (input), the coarsest inverse and the output touch it.
+// level's f (input), the coarsest inverse and the output touch it.  The
+// iterates are stored with a ring of zero cells around the domain (row
+// length M + 2), so the stencil rows read and write their cells without
+// tests; the inverse's entries used by a thread are loaded into registers at
+// the start and arrive while the down leg runs.
 // ===========================================================================
 constexpr int BNT = 256;
 constexpr int BOT_C_ELEMS = 4096;     // complex slots (u and f of every level)
 constexpr int BOT_K_ELEMS = 4096;     // real slots (k and a reciprocal of every level)
+constexpr int CPARTS = 3;             // threads per row of the coarsest solve
+constexpr int CPRE = 27;              // inverse entries a thread keeps in registers
 
 template <typename T>
 struct BotLevel {
@@ -416,17 +496,20 @@ struct BotPlan {
     const C<double> *ainv;
 };
 
+// padded position of node (i, j) of a level with M nodes per line
+__device__ __forceinline__ int bpad(int i, int j, int M) { return (j + 1) * (M + 2) + i + 1; }
+
 // K holds k of the level followed by IV: 1 / |a_pp|^2 (Gauss-Seidel levels)
 // or 1 / ||a_p||^2 (Kaczmarz levels), computed once per launch.
 template <typename T>
 __device__ void bot_relax(const BotLevel<T> &L, C<double> *SM, const double *KS, int sweeps, bool zero) {
-    const int tid = threadIdx.x, M = L.M, N = L.N, MM = M * M;
+    const int tid = threadIdx.x, M = L.M, N = L.N, MM = M * M, PW = M + 2;
     C<double> *U = SM + L.uoff;
     const C<double> *F = SM + L.foff;
     const double *K = KS + L.koff;
     const double *IV = K + MM;
     if (zero && (L.sm != HMG_SM_GS_DEV || sweeps == 0)) {
-        for (int p = tid; p < MM; p += BNT) U[p] = cmk(0.0, 0.0);
+        for (int p = tid; p < PW * PW; p += BNT) U[p] = cmk(0.0, 0.0);
         __syncthreads();
     }
     if (L.sm == HMG_SM_GS_DEV) {
@@ -436,11 +519,12 @@ __device__ void bot_relax(const BotLevel<T> &L, C<double> *SM, const double *KS,
                 for (int p = tid; p < MM; p += BNT) {
                     int i = p % M, j = p / M;
                     if (((i + j) & 1) != colour) continue;
+                    const int l = bpad(i, j, M);
                     Row<double> r = row_at<double>(i, j, N, L.H, L.ih2, K[p], L.sa);
                     C<double> num = F[p];
-                    if (!zg) num = csub(num, offsum_l(r, U, p, M, i, j, N));
+                    if (!zg) num = csub(num, offsum_z(r, U, l, PW));
                     const double inv = IV[p];
-                    U[p] = cmk((num.x * r.dre + num.y * r.dim) * inv, (num.y * r.dre - num.x * r.dim) * inv);
+                    U[l] = cmk((num.x * r.dre + num.y * r.dim) * inv, (num.y * r.dre - num.x * r.dim) * inv);
                 }
                 __syncthreads();
             }
@@ -464,24 +548,20 @@ __device__ void bot_relax(const BotLevel<T> &L, C<double> *SM, const double *KS,
                     if (j < 0) continue;
                     const int i = ((c - 2 * j) % 5 + 5) % 5 + q5[m];
                     if (i > N) continue;
-                    int p = j * M + i;
-                    Row<double> r = row_at<double>(i, j, N, L.H, L.ih2, K[p], L.sa);
-                    C<double> res = csub(F[p], cadd(cmul(cmk(r.dre, r.dim), U[p]), offsum_l(r, U, p, M, i, j, N)));
-                    const double invn = IV[p];
-                    C<double> d = cmk(res.x * invn, res.y * invn);
-                    C<double> up = U[p];
-                    U[p] = cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x));
-                    if (i > 0) U[p - 1] = cadd(U[p - 1], cscale(r.wl, d));
-                    if (i < N) U[p + 1] = cadd(U[p + 1], cscale(r.wr, d));
-                    if (j > 0) U[p - M] = cadd(U[p - M], cscale(r.wd, d));
-                    if (j < N) U[p + M] = cadd(U[p + M], cscale(r.wu, d));
+                    const int p = j * M + i;
+                    kacz_row_lds(U, bpad(i, j, M), PW, row_at<double>(i, j, N, L.H, L.ih2, K[p], L.sa), F[p],
+                                 IV[p]);
                 }
                 __syncthreads();
             }
     }
 }
 
-template <typename T, typename TF, typename TU>
+// BASIS: workgroup b runs the cycle on the unit vector e_b and writes the
+// result as column b of the row-major matrix uo (m x m, m = M^2 of the first
+// bottom level): the cycle from a zero guess is linear in f, so these columns
+// form the matrix of the whole bottom cycle.
+template <typename T, typename TF, typename TU, bool BASIS>
 __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__restrict__ fg, C<TU> *__restrict__ uo,
                                                 const int *skip) {
     if (skip && *skip) return;
@@ -491,9 +571,25 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
     // (spilled) registers
     __shared__ BotLevel<T> PL[BOT_MAXL];
     const int tid = threadIdx.x;
-    if (tid < P.nlev) PL[tid] = P.L[tid];
-    __syncthreads();
     const int last = P.nlev - 1;
+    // this thread's share of the coarsest solve: row cr, columns
+    // [c0, c0 + CPRE) of the inverse (column-major), requested first
+    const int mco = P.L[last].M * P.L[last].M;
+    const int chunk = (mco + CPARTS - 1) / CPARTS;
+    const int cr = tid % (BNT / CPARTS), cpart = tid / (BNT / CPARTS);
+    const int cc0 = min(cpart, CPARTS - 1) * chunk;
+    const bool cpre = chunk <= CPRE;
+    C<double> ainv_r[CPRE];
+    if (cpre) {
+#pragma unroll
+        for (int t = 0; t < CPRE; ++t) {
+            const int c = min(cc0 + t, mco - 1), r = min(cr, mco - 1);
+            ainv_r[t] = P.ainv[(size_t)c * mco + r];
+        }
+    }
+    if (tid < P.nlev) PL[tid] = P.L[tid];
+    for (int q = tid; q < BOT_C_ELEMS; q += BNT) SM[q] = cmk(0.0, 0.0);
+    __syncthreads();
     // stage k of every level, the reciprocals of the relaxation rows and the
     // first level's f
     for (int l = 0; l <= last; ++l) {
@@ -508,7 +604,8 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
             KS[L.koff + MM + p] = 1.0 / d2;
         }
     }
-    for (int p = tid; p < PL[0].M * PL[0].M; p += BNT) SM[PL[0].foff + p] = ldr<double>(fg, p);
+    for (int p = tid; p < PL[0].M * PL[0].M; p += BNT)
+        SM[PL[0].foff + p] = BASIS ? cmk(p == (int)blockIdx.x ? 1.0 : 0.0, 0.0) : ldr<double>(fg, p);
     __syncthreads();
     // down: pre-relaxation, residual, full weighting into the next f
     for (int l = 0; l < last; ++l) {
@@ -518,6 +615,7 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
         const C<double> *U = SM + L.uoff;
         const C<double> *F = SM + L.foff;
         const double *K = KS + L.koff;
+        const int PW = L.M + 2;
         for (int qc = tid; qc < Cl.M * Cl.M; qc += BNT) {
             int I = qc % Cl.M, J = qc / Cl.M;
             C<double> s = cmk(0.0, 0.0);
@@ -525,9 +623,9 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
                 int j = mirror(2 * J + e, L.N);
                 for (int d = -1; d <= 1; ++d) {
                     int i = mirror(2 * I + d, L.N);
-                    int p = j * L.M + i;
+                    int p = j * L.M + i, l2 = bpad(i, j, L.M);
                     Row<double> r = row_at<double>(i, j, L.N, L.H, L.ih2, K[p], L.sb);
-                    C<double> res = csub(F[p], cadd(cmul(cmk(r.dre, r.dim), U[p]), offsum_l(r, U, p, L.M, i, j, L.N)));
+                    C<double> res = csub(F[p], cadd(cmul(cmk(r.dre, r.dim), U[l2]), offsum_z(r, U, l2, PW)));
                     double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
                     s = cadd(s, cscale(w, res));
                 }
@@ -539,27 +637,32 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
     // coarsest: u = A^{-1} f in FP64; row r is split over CPARTS threads
     // (column ranges), partial sums combined in a fixed order
     {
-        constexpr int CPARTS = 3;
-        __shared__ C<double> part[CPARTS][BNT];
+        __shared__ C<double> part[CPARTS][BNT / CPARTS];
         const BotLevel<T> &L = PL[last];
-        const int m = L.M * L.M;
-        const int chunk = (m + CPARTS - 1) / CPARTS;
+        const int m = mco;
         const C<double> *F = SM + L.foff;
         for (int base = 0; base < m; base += BNT / CPARTS) {
-            const int r = base + tid % (BNT / CPARTS), part_id = tid / (BNT / CPARTS);
-            if (part_id < CPARTS) {
+            const int r = base + cr;
+            if (cpart < CPARTS) {
                 C<double> acc = cmk(0.0, 0.0);
                 if (r < m) {
-                    const int c0 = part_id * chunk, c1 = min(m, c0 + chunk);
-                    for (int c = c0; c < c1; ++c) acc = cadd(acc, cmul(P.ainv[(size_t)c * m + r], F[c]));
+                    const int c1 = min(m, cc0 + chunk);
+                    if (cpre && base == 0) {
+#pragma unroll
+                        for (int t = 0; t < CPRE; ++t)
+                            if (cc0 + t < c1) acc = cadd(acc, cmul(ainv_r[t], F[cc0 + t]));
+                    } else {
+                        for (int c = cc0; c < c1; ++c) acc = cadd(acc, cmul(P.ainv[(size_t)c * m + r], F[c]));
+                    }
                 }
-                part[part_id][tid % (BNT / CPARTS)] = acc;
+                part[cpart][cr] = acc;
             }
             __syncthreads();
             if (tid < BNT / CPARTS && base + tid < m) {
                 C<double> acc = part[0][tid];
                 for (int q = 1; q < CPARTS; ++q) acc = cadd(acc, part[q][tid]);
-                SM[L.uoff + base + tid] = acc;
+                const int rr = base + tid;
+                SM[L.uoff + bpad(rr % L.M, rr / L.M, L.M)] = acc;
             }
             __syncthreads();
         }
@@ -570,15 +673,58 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
         const BotLevel<T> &Cl = PL[l + 1];
         C<double> *U = SM + L.uoff;
         const C<double> *E = SM + Cl.uoff;
+        const int PWc = Cl.M + 2;
         for (int p = tid; p < L.M * L.M; p += BNT) {
-            int i = p % L.M, j = p / L.M;
-            U[p] = cadd(U[p], prolong_at(E, i, j, Cl.M));
+            const int i = p % L.M, j = p / L.M;
+            const int qc = bpad(i >> 1, j >> 1, Cl.M);   // coarse (I, J); its right and upper
+                                                          // neighbours may be zero ring cells
+            const int l2 = bpad(i, j, L.M);
+            U[l2] = cadd(U[l2], bilinear(E[qc], E[qc + 1], E[qc + PWc], E[qc + PWc + 1], i, j));
         }
         __syncthreads();
         bot_relax<T>(L, SM, KS, L.post, false);
     }
     const BotLevel<T> &L0 = PL[0];
-    for (int p = tid; p < L0.M * L0.M; p += BNT) uo[p] = st_as<TU>(SM[L0.uoff + p]);
+    const int m0 = L0.M * L0.M;
+    for (int p = tid; p < m0; p += BNT) {
+        const C<double> v = SM[L0.uoff + bpad(p % L0.M, p / L0.M, L0.M)];
+        if (BASIS) uo[(size_t)p * m0 + blockIdx.x] = st_as<TU>(v);
+        else uo[p] = st_as<TU>(v);
+    }
+}
+
+// ===========================================================================
+// k_dense_apply: u = B f for the dense bottom-cycle matrix B (row-major,
+// complex FP64, m <= DMAX).  f is staged in LDS; each wave forms one row's
+// dot product (lanes stride the row, then a fixed-order butterfly sum).
+// ===========================================================================
+constexpr int DNT = 256, DROWS = DNT / 64, DMAX = 33 * 33;
+
+template <typename TF, typename TU>
+__global__ __launch_bounds__(DNT) void k_dense_apply(const C<double> *__restrict__ B, int m,
+                                                     const C<TF> *__restrict__ f, C<TU> *__restrict__ u,
+                                                     const int *skip) {
+    if (skip && *skip) return;
+    __shared__ C<double> X[DMAX];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < m; q += DNT) X[q] = ldr<double>(f, q);
+    __syncthreads();
+    const int lane = tid & 63, r = blockIdx.x * DROWS + (tid >> 6);
+    if (r >= m) return;
+    const C<double> *row = B + (size_t)r * m;
+    double ax = 0.0, ay = 0.0;
+#pragma unroll 9
+    for (int c = lane; c < m; c += 64) {
+        const C<double> b = row[c], x = X[c];
+        ax += b.x * x.x - b.y * x.y;
+        ay += b.x * x.y + b.y * x.x;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        ax += __shfl_xor(ax, off, 64);
+        ay += __shfl_xor(ay, off, 64);
+    }
+    if (lane == 0) u[r] = st_as<TU>(cmk(ax, ay));
 }
 
 // ===========================================================================
@@ -616,17 +762,19 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
     else gs_up_t<float, float, float>(s, g, k, sa, f, ec, uo, skip);
 }
 
-template <typename T, int TS, int S>
+template <typename T, int TS, int S, int NT>
 static void kacz_tb_t(hipStream_t s, const Geo &g, const void *k, double sig, const void *f, const void *ui,
                       const void *ec, void *uo, const int *skip) {
     dim3 grid((g.M + TS - 1) / TS, (g.M + TS - 1) / TS);
-    k_kacz_tb<T, TS, S><<<grid, KNT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig,
-                                             (const C<T> *)f, (const C<T> *)ui, (const C<T> *)ec, (C<T> *)uo,
-                                             skip);
+    k_kacz_tb<T, TS, S, NT><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig,
+                                                (const C<T> *)f, (const C<T> *)ui, (const C<T> *)ec, (C<T> *)uo,
+                                                skip);
 }
 
-// Tile configurations offered to the tuner: (tile side, sweeps per launch).
-const KaczCfg kKaczCfgs[KACZ_NCFG] = {{32, 1}, {32, 2}, {16, 2}, {16, 4}};
+// Tile configurations offered to the tuner: (tile side, sweeps per launch,
+// threads per workgroup).
+const KaczCfg kKaczCfgs[KACZ_NCFG] = {{32, 1, 512}, {32, 2, 1024}, {16, 2, 512}, {16, 4, 1024},
+                                      {16, 2, 1024}, {16, 1, 512}, {32, 1, 1024}};
 
 // The LDS tile holds FP64 values in either storage precision.
 bool kacz_cfg_fits(Prec, int cfg) {
@@ -635,30 +783,31 @@ bool kacz_cfg_fits(Prec, int cfg) {
     return (size_t)lw * lw * 16 <= 160 * 1024;
 }
 
+template <typename T>
+static void kacz_tb_any(int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
+                        const void *ui, const void *ec, void *uo, const int *skip) {
+    switch (cfg) {
+    case 0: kacz_tb_t<T, 32, 1, 512>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    case 1: kacz_tb_t<T, 32, 2, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    case 2: kacz_tb_t<T, 16, 2, 512>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    case 3: kacz_tb_t<T, 16, 4, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    case 4: kacz_tb_t<T, 16, 2, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    case 5: kacz_tb_t<T, 16, 1, 512>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    default: kacz_tb_t<T, 32, 1, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    }
+}
+
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
                     const void *ui, const void *ec, void *uo, const int *skip) {
-    if (p == P64) {
-        switch (cfg) {
-        case 0: kacz_tb_t<double, 32, 1>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        case 1: kacz_tb_t<double, 32, 2>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        case 2: kacz_tb_t<double, 16, 2>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        default: kacz_tb_t<double, 16, 4>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        }
-    } else {
-        switch (cfg) {
-        case 0: kacz_tb_t<float, 32, 1>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        case 1: kacz_tb_t<float, 32, 2>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        case 2: kacz_tb_t<float, 16, 2>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        default: kacz_tb_t<float, 16, 4>(s, g, k, sig, f, ui, ec, uo, skip); break;
-        }
-    }
+    if (p == P64) kacz_tb_any<double>(cfg, s, g, k, sig, f, ui, ec, uo, skip);
+    else kacz_tb_any<float>(cfg, s, g, k, sig, f, ui, ec, uo, skip);
 }
 
 int bottom_complex_slots() { return BOT_C_ELEMS; }
 int bottom_real_slots() { return BOT_K_ELEMS; }
 
-template <typename T, typename TF, typename TU>
-static void bottom_t(hipStream_t s, const BottomDesc &d, const void *f, void *uo, const int *skip) {
+template <typename T>
+static BotPlan<T> bot_plan(const BottomDesc &d) {
     BotPlan<T> P;
     P.nlev = d.nlev;
     P.ainv = (const C<double> *)d.ainv_t;
@@ -680,7 +829,34 @@ static void bottom_t(hipStream_t s, const BottomDesc &d, const void *f, void *uo
         L.foff = D.foff;
         L.koff = D.koff;
     }
-    k_bottom<T, TF, TU><<<1, BNT, 0, s>>>(P, (const C<TF> *)f, (C<TU> *)uo, skip);
+    return P;
+}
+
+template <typename T, typename TF, typename TU>
+static void bottom_t(hipStream_t s, const BottomDesc &d, const void *f, void *uo, const int *skip) {
+    k_bottom<T, TF, TU, false><<<1, BNT, 0, s>>>(bot_plan<T>(d), (const C<TF> *)f, (C<TU> *)uo, skip);
+}
+
+int bottom_matrix_size(const BottomDesc &d) { return (d.L[0].n + 2) * (d.L[0].n + 2); }
+
+// The matrix of the bottom cycle (row-major complex FP64, m x m), one
+// workgroup per column.
+void launch_bottom_basis(Prec p, hipStream_t s, const BottomDesc &d, double *B) {
+    const int m = bottom_matrix_size(d);
+    if (p == P64)
+        k_bottom<double, double, double, true><<<m, BNT, 0, s>>>(bot_plan<double>(d), nullptr, (C<double> *)B,
+                                                                 nullptr);
+    else
+        k_bottom<float, double, double, true><<<m, BNT, 0, s>>>(bot_plan<float>(d), nullptr, (C<double> *)B,
+                                                                nullptr);
+}
+
+void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m, const void *f, void *u,
+                        const int *skip) {
+    dim3 grid((m + DROWS - 1) / DROWS);
+    const C<double> *b = (const C<double> *)B;
+    if (p == P64 || io64) k_dense_apply<double, double><<<grid, DNT, 0, s>>>(b, m, (const C<double> *)f, (C<double> *)u, skip);
+    else k_dense_apply<float, float><<<grid, DNT, 0, s>>>(b, m, (const C<float> *)f, (C<float> *)u, skip);
 }
 
 void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo, const int *skip) {

@@ -57,6 +57,8 @@ struct hmg_grid {
     int        lb = -1;           // first level of the bottom solver (-1: none)
     hmgk::BottomDesc bottom{};    // per-level parameters of the bottom solver
     double    *ainv_t = nullptr;  // coarsest inverse, column-major complex FP64
+    double    *bop = nullptr;     // matrix of the bottom cycle, row-major complex FP64
+    int        bop_m = 0;         // its order (nodes of the first bottom level)
     std::vector<Slot> slot;
     char      *mem = nullptr;
     size_t     bytes = 0;

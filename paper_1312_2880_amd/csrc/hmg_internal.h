@@ -85,9 +85,9 @@ struct BottomDesc {
     const double   *ainv_t;
 };
 struct KaczCfg {
-    int ts, sweeps;             // tile side, sweeps per launch
+    int ts, sweeps, threads;    // tile side, sweeps per launch, workgroup size
 };
-constexpr int KACZ_NCFG = 4;
+constexpr int KACZ_NCFG = 7;
 extern const KaczCfg kKaczCfgs[KACZ_NCFG];
 bool   kacz_cfg_fits(Prec p, int cfg);
 int    bottom_complex_slots();   // LDS capacity of the bottom solver
@@ -105,6 +105,10 @@ void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k,
                     const void *ui, const void *ec, void *uo, const int *skip);
 void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo,
                    const int *skip);
+int  bottom_matrix_size(const BottomDesc &d);
+void launch_bottom_basis(Prec p, hipStream_t s, const BottomDesc &d, double *B);
+void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m, const void *f, void *u,
+                        const int *skip);
 
 // ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
 int  krylov_nblocks(const Geo &g);

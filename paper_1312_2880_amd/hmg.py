@@ -47,7 +47,7 @@ class Opts(ctypes.Structure):
                 ("kacz_post", ctypes.c_int), ("kacz_band", ctypes.c_int),
                 ("coarsest_n", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("one_pass_kernels", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("bottom_dense", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class Plan(ctypes.Structure):
@@ -110,7 +110,7 @@ _SIGS = {
     "hmg_op_gs_down_dev": (_i, [P, _i, _d, _d, P, P, P, P]),
     "hmg_op_gs_up_dev": (_i, [P, _i, _d, P, P, P, P]),
     "hmg_op_kacz_tiled_dev": (_i, [P, _i, _d, _i, P, P, P, P, P]),
-    "hmg_kacz_tile_config": (_i, [_i, P, P]),
+    "hmg_kacz_tile_config": (_i, [_i, P, P, P]),
     "hmg_solve_history": (_i, [P, _i, P, _i]),
     "hmg_grid_kacz_config": (_i, [P, _i]),
 }
@@ -123,13 +123,14 @@ EXPORTED = tuple(_SIGS)
 
 
 def kacz_tile_configs():
-    """[(tile side, sweeps per launch)] of the tiled Kaczmarz kernel."""
-    t, s = ctypes.c_int(), ctypes.c_int()
-    n = _lib.hmg_kacz_tile_config(0, ctypes.byref(t), ctypes.byref(s))
+    """[(tile side, sweeps per launch, workgroup size)] of the tiled
+    Kaczmarz kernel."""
+    t, s, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    n = _lib.hmg_kacz_tile_config(0, None, None, None)
     out = []
     for c in range(n):
-        _lib.hmg_kacz_tile_config(c, ctypes.byref(t), ctypes.byref(s))
-        out.append((t.value, s.value))
+        _lib.hmg_kacz_tile_config(c, ctypes.byref(t), ctypes.byref(s), ctypes.byref(w))
+        out.append((t.value, s.value, w.value))
     return out
 
 

@@ -1,10 +1,12 @@
 """Summaries of rocprofv3 output for the kernels of this library.
 
     python -m paper_1312_2880_amd.profiling stats  <kernel_stats.csv> [title]
+    python -m paper_1312_2880_amd.profiling trace  <kernel_trace.csv> [top]
     python -m paper_1312_2880_amd.profiling traffic <fetch_dir> <write_dir> <kernel> <bytes> <hash> [key]
 
 `stats` prints a short markdown table (kernel, calls, average and total
-time, share).  `traffic` combines two `--pmc` runs (FETCH_SIZE, then
+time, share).  `trace` splits the same time by kernel and launch shape
+(grid size: one row per level of the hierarchy), with the median duration.  `traffic` combines two `--pmc` runs (FETCH_SIZE, then
 WRITE_SIZE; KiB per dispatch) of `bench.py --traffic-probe`: the probe runs
 the dominant kernel on cold buffers and a plain device-to-device copy of a
 known size; each counter is scaled by (copy bytes / what the counter reads for
@@ -28,6 +30,25 @@ def kernel_stats(path: str, title: str = "", top: int = 14) -> str:
         name = r["Name"].split("(")[0].replace("void ", "")
         out.append(f"| {100 * float(r['TotalDurationNs']) / total:5.1f}% | {r['Calls']} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['TotalDurationNs']) / 1e6:.2f} | `{name}` |")
+    out.append(f"\nall kernels: {total / 1e6:.2f} ms")
+    return "\n".join(out)
+
+
+def kernel_trace(path: str, top: int = 20) -> str:
+    rows = list(csv.DictReader(open(path)))
+    groups = {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        wx, wy = int(r["Workgroup_Size_X"]), int(r.get("Workgroup_Size_Y", 1) or 1)
+        key = (name, int(r["Grid_Size_X"]) // max(wx, 1), int(r["Grid_Size_Y"]) // max(wy, 1), wx * wy)
+        groups.setdefault(key, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in groups.values())
+    out = ["| share | calls | median (us) | total (ms) | workgroups | threads | kernel |",
+           "|---:|---:|---:|---:|---:|---:|---|"]
+    for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        v.sort()
+        out.append(f"| {100 * sum(v) / total:5.1f}% | {len(v)} | {v[len(v) // 2] / 1e3:.2f} | "
+                   f"{sum(v) / 1e6:.2f} | {key[1]}x{key[2]} | {key[3]} | `{key[0]}` |")
     out.append(f"\nall kernels: {total / 1e6:.2f} ms")
     return "\n".join(out)
 
@@ -72,6 +93,8 @@ def traffic(fetch_dir, write_dir, kernel, copy_bytes, src_hash, key):
 if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "stats":
         print(kernel_stats(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ""))
+    elif len(sys.argv) >= 3 and sys.argv[1] == "trace":
+        print(kernel_trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 20))
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
         key = sys.argv[7] if len(sys.argv) > 7 else f"{sys.argv[4]}:fp64"
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),

@@ -228,12 +228,12 @@ def test_fused_gs_down_without_iterate_output(ctx, hmg):
     assert rel(host(d_fc), oracle.restrict_fw(oracle.residual(h, k, 0.0, f, u_ref))) <= 1e-13
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
+@pytest.mark.parametrize("cfg", range(7))
 @pytest.mark.parametrize("start", ["zero", "u", "u+Pe"])
 @pytest.mark.parametrize("n", [63, 127])
 def test_tiled_kaczmarz_matches_oracle(ctx, hmg, cfg, start, n):
-    tile, sweeps = hmg.kacz_tile_configs()[cfg]
-    say(f"case kacz_tiled cfg={cfg} ({tile},{sweeps}) start={start} n={n}")
+    tile, sweeps, threads = hmg.kacz_tile_configs()[cfg]
+    say(f"case kacz_tiled cfg={cfg} ({tile},{sweeps},{threads}) start={start} n={n}")
     h = 1.0 / (n + 1)
     k = rand_k(n, 7 * n + cfg, 60.0, 150.0)
     g = hmg.Grid(ctx, h, k)
@@ -288,12 +288,15 @@ def vcycle_cases():
     return out
 
 
-@pytest.mark.parametrize("one_pass", [0, 1], ids=["fused", "one_pass"])
+SCHEDULES = {"fused": dict(), "fused_wg_bottom": dict(bottom_dense=0), "one_pass": dict(one_pass_kernels=1)}
+
+
+@pytest.mark.parametrize("schedule", list(SCHEDULES))
 @pytest.mark.parametrize("case", vcycle_cases(), ids=lambda c: c[0])
-def test_vcycle_matches_oracle(ctx, hmg, case, one_pass):
+def test_vcycle_matches_oracle(ctx, hmg, case, schedule):
     name, h, k, kw = case
-    say(f"case vcycle {name} one_pass={one_pass}")
-    g = hmg.Grid(ctx, h, k, one_pass_kernels=one_pass, **kw)
+    say(f"case vcycle {name} schedule={schedule}")
+    g = hmg.Grid(ctx, h, k, **SCHEDULES[schedule], **kw)
     og = oracle.Grid(h, k, **kw)
     gp, op = g.plan(), og.plan()
     assert len(gp) == len(op)

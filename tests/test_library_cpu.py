@@ -53,6 +53,26 @@ def test_defaults_are_the_papers_constants():
     assert (o.nu_pre, o.nu_post) == (1, 1)    # V(1,1) smoothing
     assert (o.kacz_pre, o.kacz_post) == (4, 4)
     assert o.variant == hmg.HYB and o.coarsest_n == 7
+    # schedule defaults: fused kernels, tuned Kaczmarz tiles, dense bottom cycle
+    assert (o.one_pass_kernels, o.autotune, o.bottom_dense, o.use_graph) == (0, 1, 1, 1)
+
+
+def test_opts_struct_matches_the_header():
+    """The ctypes mirror of hmg_opts has the header's size and field order."""
+    import re
+    from paper_1312_2880_amd import hmg
+    hdr = open(os.path.join(ROOT, "include", "hmg.h")).read()
+    end = hdr.index("} hmg_opts;")
+    body = hdr[hdr.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(None, 1)[1].split(","):
+            names.append(part.strip().split("[")[0])
+    assert [f for f, _ in hmg.Opts._fields_] == names
 
 
 def test_null_arguments_are_rejected():
