@@ -266,6 +266,14 @@ hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_relax, const vo
                             const void *d_ec, void *d_uo, void *stream);
 hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int config, const void *d_f,
                                  const void *d_ui, const void *d_ec, void *d_uo, void *stream);
+/* Kaczmarz pre-smoothing with the restriction (Section 5): uo = S 5-colour
+ * Kaczmarz sweeps on A_{sigma_relax} from ui (NULL: zero), then
+ * fc = R (f - A_{sigma_resid} uo) on level + 1.  The configuration must be
+ * one whose region is staged in LDS (tile side and sweeps as listed by
+ * hmg_kacz_tile_config; the kernel works on tiles four nodes smaller with a
+ * halo two nodes wider).  Outputs must not alias inputs or each other. */
+hmg_status hmg_op_kacz_down_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid, int config,
+                                const void *d_f, const void *d_ui, void *d_uo, void *d_fc, void *stream);
 /* Tile configuration chosen for a Kaczmarz level of the grid (-1: the level
  * is not relaxed by the tiled kernel). */
 int        hmg_grid_kacz_config(const hmg_grid *g, int level);

@@ -378,8 +378,12 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                 void *bufs[2] = {S.u[l], S.u2[l]};
                 int w = 0;
                 for (int q = 0; q < pl.pre[l]; q += sw) {
-                    launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l], S.f[l], cur, nullptr,
-                                   bufs[w], nullptr);
+                    if (kacz_cfg_resid(cfg) && q + sw >= pl.pre[l])
+                        launch_kacz_tb_resid(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l],
+                                             pl.sigma_resid[l], S.f[l], cur, bufs[w], S.f[l + 1], nullptr);
+                    else
+                        launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l], S.f[l], cur,
+                                       nullptr, bufs[w], nullptr);
                     cur = bufs[w];
                     w ^= 1;
                 }
@@ -693,8 +697,14 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         void *bufs[2] = {S.u[l], S.u2[l]};
         const void *cur = nullptr;
         int w = 0;
+        // the last pre-smoothing launch also restricts the residual
+        const bool fuse = pl.pre[l] > 0 && kacz_cfg_resid(cfg);
         for (int q = 0; q < pl.pre[l]; q += sw) {
-            launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, sig, f, cur, nullptr, bufs[w], skip);
+            if (fuse && q + sw >= pl.pre[l])
+                launch_kacz_tb_resid(g->prec, cfg, s, L.geo, L.k, sig, pl.sigma_resid[l], f, cur, bufs[w],
+                                     S.f[l + 1], skip);
+            else
+                launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, sig, f, cur, nullptr, bufs[w], skip);
             cur = bufs[w];
             w ^= 1;
         }
@@ -703,7 +713,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
             cur = bufs[w];
             w ^= 1;
         }
-        launch_residual_fw(g->prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip);
+        if (!fuse) launch_residual_fw(g->prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip);
         const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
         if (pl.post[l] == 0) {
             launch_prolong_add(g->prec, s, L.geo, e, (void *)cur, skip);
@@ -887,6 +897,23 @@ extern "C" hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma
     if (d_ec && level >= g->nlev - 1) return hmg_fail(HMG_ERR_INVALID, "no coarser level");
     const Level &L = g->lev[level];
     launch_kacz_tb(g->prec, config, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_ui, d_ec, d_uo, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_kacz_down_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid,
+                                           int config, const void *d_f, const void *d_ui, void *d_uo, void *d_fc,
+                                           void *stream) {
+    hmg_status st = check_level(g, level, false);
+    if (st) return st;
+    if (level >= g->nlev - 1) return hmg_fail(HMG_ERR_INVALID, "no coarser level");
+    if (config < 0 || config >= KACZ_NCFG || !kacz_cfg_resid(config))
+        return hmg_fail(HMG_ERR_INVALID, "tile configuration %d has no fused residual form", config);
+    if (!d_f || !d_uo || !d_fc || d_uo == d_ui || d_uo == d_f || d_fc == d_f || d_fc == d_ui || d_fc == d_uo)
+        return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs or each other)");
+    const Level &L = g->lev[level];
+    launch_kacz_tb_resid(g->prec, config, pick_stream(g, stream), L.geo, L.k, sigma_relax, sigma_resid, d_f, d_ui,
+                         d_uo, d_fc, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }

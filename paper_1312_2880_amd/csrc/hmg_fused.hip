@@ -90,56 +90,65 @@ __device__ __forceinline__ C<double> prolong_at(const C<T> *ec, int i, int j, in
 __device__ __forceinline__ int mirror(int x, int N) { return x < 0 ? -x : (x > N ? 2 * N - x : x); }
 
 // ===========================================================================
-// Fused Gauss-Seidel kernels.  A tile of GDX x GDY fine nodes (x0, y0 even)
-// is processed with a halo of RH = 3 held in LDS.  Each thread owns fixed
+// Fused Gauss-Seidel kernels.  A tile of X x Y fine nodes (x0, y0 even) is
+// processed with a halo of RH = 3 held in LDS.  Each thread owns fixed
 // red and black nodes of the haloed region (colour-compressed: node q of a
 // colour maps to line q / HW, every other column), loads their f and k once,
 // all loads in flight together, and keeps them in registers across the
 // dependent phases, which then touch only LDS.
 // ===========================================================================
-constexpr int GDX = 64, GDY = 20, GNT = 256;
-constexpr int GRH = 3, GLW = GDX + 2 * GRH, GLH = GDY + 2 * GRH;
-constexpr int GHW = GLW / 2;                       // nodes of one colour per line
-constexpr int GNC = GHW * GLH;                     // nodes of one colour in the region
-constexpr int GNS = (GNC + GNT - 1) / GNT;         // owned nodes per colour per thread
+constexpr int GNT = 256;
 
-// local coordinates of owned node (colour c, slot m) of thread tid
-__device__ __forceinline__ bool gs_owned(int tid, int c, int m, int &lx, int &ly) {
-    int q = tid + GNT * m;
-    ly = q / GHW;
-    lx = 2 * (q % GHW) + ((ly + c) & 1);            // red: (lx + ly) even
-    return q < GNC;
-}
+template <int DX, int DY>
+struct GsTile {
+    static constexpr int X = DX, Y = DY;                // tile (even sides)
+    static constexpr int RH = 3, LW = DX + 2 * RH, LH = DY + 2 * RH;
+    static constexpr int HW = LW / 2;                   // nodes of one colour per line
+    static constexpr int NC = HW * LH;                  // nodes of one colour in the region
+    static constexpr int NS = (NC + GNT - 1) / GNT;     // owned nodes per colour per thread
 
-// ring distance from the region border: node (lx, ly) is in tile + h iff
-// lx >= GRH - h, lx < GLW - GRH + h, and the same for ly
-__device__ __forceinline__ bool in_ring(int lx, int ly, int h) {
-    return lx >= GRH - h && ly >= GRH - h && lx < GLW - GRH + h && ly < GLH - GRH + h;
-}
+    // local coordinates of owned node (colour c, slot m) of thread tid
+    static __device__ __forceinline__ bool owned(int tid, int c, int m, int &lx, int &ly) {
+        int q = tid + GNT * m;
+        ly = q / HW;
+        lx = 2 * (q % HW) + ((ly + c) & 1);             // red: (lx + ly) even
+        return q < NC;
+    }
+    // ring distance from the region border: node (lx, ly) is in tile + h iff
+    // lx >= RH - h, lx < LW - RH + h, and the same for ly
+    static __device__ __forceinline__ bool ring(int lx, int ly, int h) {
+        return lx >= RH - h && ly >= RH - h && lx < LW - RH + h && ly < LH - RH + h;
+    }
+};
+// the finest levels use the large tile (less halo per node, fewer HBM
+// re-reads); levels that would get fewer than two large tiles per CU use the
+// small one, so that more workgroups share the latency of the dependent phases
+using GsBig = GsTile<64, 20>;
+using GsSmall = GsTile<32, 12>;
 
 // ===========================================================================
 // k_gs_down: one zero-guess red-black sweep (sigma_A), residual (sigma_B) on
 // tile + 1, full weighting to the coarse nodes of the tile.  The smoothed
 // iterate stays on chip (written only when uo != null).
 // ===========================================================================
-template <typename T, typename TF>
+template <class TL, typename T, typename TF>
 __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                  double sb, const C<TF> *__restrict__ f, C<T> *uo,
                                                  C<T> *__restrict__ fc, const int *skip) {
     if (skip && *skip) return;
-    __shared__ C<double> U[GLW * GLH];      // the iterate, then the residual on tile + 1
+    __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * GDX, y0 = blockIdx.y * GDY;
-    const int ox = x0 - GRH, oy = y0 - GRH;
+    const int x0 = blockIdx.x * TL::X, y0 = blockIdx.y * TL::Y;
+    const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     const int N = g.N, M = g.M;
-    C<double> fr[2][GNS];
-    double kr[2][GNS];
+    C<double> fr[2][TL::NS];
+    double kr[2][TL::NS];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int m = 0; m < GNS; ++m) {
+        for (int m = 0; m < TL::NS; ++m) {
             int lx, ly;
-            bool own = gs_owned(tid, c, m, lx, ly);
+            bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
             if (own && i >= 0 && j >= 0 && i <= N && j <= N) {
                 size_t p = (size_t)j * M + i;
@@ -150,79 +159,79 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
     // red on tile + 3 (zero guess: u = f / a_pp); cells outside the domain
     // are set to zero (missing neighbours of the rows below)
 #pragma unroll
-    for (int m = 0; m < GNS; ++m) {
+    for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
-        bool own = gs_owned(tid, 0, m, lx, ly);
+        bool own = TL::owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
         if (!own) continue;
         if (i < 0 || j < 0 || i > N || j > N) {
-            U[ly * GLW + lx] = cmk(0.0, 0.0);
+            U[ly * TL::LW + lx] = cmk(0.0, 0.0);
             continue;
         }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[ly * GLW + lx] = cdiv(fr[0][m], r.dre, r.dim);
+        U[ly * TL::LW + lx] = cdiv(fr[0][m], r.dre, r.dim);
     }
     __syncthreads();
     // black on tile + 2
 #pragma unroll
-    for (int m = 0; m < GNS; ++m) {
+    for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
-        bool own = gs_owned(tid, 1, m, lx, ly);
+        bool own = TL::owned(tid, 1, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !in_ring(lx, ly, 2)) continue;
-        int l = ly * GLW + lx;
+        if (!own || !TL::ring(lx, ly, 2)) continue;
+        int l = ly * TL::LW + lx;
         if (i < 0 || j < 0 || i > N || j > N) {
             U[l] = cmk(0.0, 0.0);
             continue;
         }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-        U[l] = cdiv(csub(fr[1][m], offsum_z(r, U, l, GLW)), r.dre, r.dim);
+        U[l] = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
     }
     __syncthreads();
     // the smoothed iterate on the tile (only when asked for: the up kernel
     // recomputes it)
     if (uo) {
 #pragma unroll
-        for (int m = 0; m < GDX * GDY / GNT; ++m) {
+        for (int m = 0; m < (TL::X * TL::Y + GNT - 1) / GNT; ++m) {
             const int q = tid + GNT * m;
-            int tx = q % GDX, ty = q / GDX;
+            int tx = q % TL::X, ty = q / TL::X;
             int i = x0 + tx, j = y0 + ty;
-            if (i > N || j > N) continue;
-            uo[(size_t)j * M + i] = st_as<T>(U[(ty + GRH) * GLW + tx + GRH]);
+            if (q >= TL::X * TL::Y || i > N || j > N) continue;
+            uo[(size_t)j * M + i] = st_as<T>(U[(ty + TL::RH) * TL::LW + tx + TL::RH]);
         }
     }
     // residual with the role-(B) operator on tile + 1, kept in registers
     // until every thread has read the iterate, then stored over it
-    C<double> res[2][GNS];
+    C<double> res[2][TL::NS];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int m = 0; m < GNS; ++m) {
+        for (int m = 0; m < TL::NS; ++m) {
             int lx, ly;
-            bool own = gs_owned(tid, c, m, lx, ly);
+            bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
-            int l = ly * GLW + lx;
+            if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+            int l = ly * TL::LW + lx;
             Row<double> r = row_at<double>(i, j, N, H, ih2, kr[c][m], sb);
-            C<double> au = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, GLW));
+            C<double> au = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, TL::LW));
             res[c][m] = csub(fr[c][m], au);
         }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int m = 0; m < GNS; ++m) {
+        for (int m = 0; m < TL::NS; ++m) {
             int lx, ly;
-            bool own = gs_owned(tid, c, m, lx, ly);
+            bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
-            U[ly * GLW + lx] = res[c][m];
+            if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+            U[ly * TL::LW + lx] = res[c][m];
         }
     __syncthreads();
     // full weighting for the coarse nodes of this tile
     {
         const int Nc = N / 2, Mc = Nc + 1;
-        constexpr int CX = GDX / 2, NCN = (GDX / 2) * (GDY / 2);
+        constexpr int CX = TL::X / 2, NCN = (TL::X / 2) * (TL::Y / 2);
 #pragma unroll
         for (int m = 0; m < (NCN + GNT - 1) / GNT; ++m) {
             const int q = tid + GNT * m;
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
                 for (int d = -1; d <= 1; ++d) {
                     int i = mirror(2 * I + d, N);
                     double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
-                    s = cadd(s, cscale(w, U[(j - oy) * GLW + (i - ox)]));
+                    s = cadd(s, cscale(w, U[(j - oy) * TL::LW + (i - ox)]));
                 }
             }
             fc[(size_t)J * Mc + I] = st_as<T>(cscale(0.0625, s));
@@ -249,24 +258,24 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
 // by one per dependent step: red u0 on tile + 3, black u0 on tile + 2,
 // correction on tile + 2, red on tile + 1, black on the tile.
 // ===========================================================================
-template <typename T, typename TF, typename TU>
+template <class TL, typename T, typename TF, typename TU>
 __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                const C<TF> *__restrict__ f, const C<T> *__restrict__ ec,
                                                C<TU> *__restrict__ uo, const int *skip) {
     if (skip && *skip) return;
-    __shared__ C<double> U[GLW * GLH];
+    __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * GDX, y0 = blockIdx.y * GDY;
-    const int ox = x0 - GRH, oy = y0 - GRH;
+    const int x0 = blockIdx.x * TL::X, y0 = blockIdx.y * TL::Y;
+    const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
-    C<double> fr[2][GNS];
-    double kr[2][GNS];
+    C<double> fr[2][TL::NS];
+    double kr[2][TL::NS];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int m = 0; m < GNS; ++m) {
+        for (int m = 0; m < TL::NS; ++m) {
             int lx, ly;
-            bool own = gs_owned(tid, c, m, lx, ly);
+            bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
             if (own && i >= 0 && j >= 0 && i <= N && j <= N) {
                 size_t p = (size_t)j * M + i;
@@ -276,73 +285,73 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         }
     // red u0 on tile + 3 (zero outside the domain)
 #pragma unroll
-    for (int m = 0; m < GNS; ++m) {
+    for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
-        bool own = gs_owned(tid, 0, m, lx, ly);
+        bool own = TL::owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
         if (!own) continue;
         if (i < 0 || j < 0 || i > N || j > N) {
-            U[ly * GLW + lx] = cmk(0.0, 0.0);
+            U[ly * TL::LW + lx] = cmk(0.0, 0.0);
             continue;
         }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[ly * GLW + lx] = cdiv(fr[0][m], r.dre, r.dim);
+        U[ly * TL::LW + lx] = cdiv(fr[0][m], r.dre, r.dim);
     }
     __syncthreads();
     // black u0 on tile + 2, plus the correction on the black nodes
 #pragma unroll
-    for (int m = 0; m < GNS; ++m) {
+    for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
-        bool own = gs_owned(tid, 1, m, lx, ly);
+        bool own = TL::owned(tid, 1, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !in_ring(lx, ly, 2)) continue;
-        int l = ly * GLW + lx;
+        if (!own || !TL::ring(lx, ly, 2)) continue;
+        int l = ly * TL::LW + lx;
         if (i < 0 || j < 0 || i > N || j > N) {
             U[l] = cmk(0.0, 0.0);
             continue;
         }
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-        U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, GLW)), r.dre, r.dim), prolong_at(ec, i, j, Mc));
+        U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim), prolong_at(ec, i, j, Mc));
     }
     __syncthreads();
     // the correction on the red nodes of tile + 2 (after every black u0 has
     // read the uncorrected red values)
 #pragma unroll
-    for (int m = 0; m < GNS; ++m) {
+    for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
-        bool own = gs_owned(tid, 0, m, lx, ly);
+        bool own = TL::owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !in_ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
-        int l = ly * GLW + lx;
+        if (!own || !TL::ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
+        int l = ly * TL::LW + lx;
         U[l] = cadd(U[l], prolong_at(ec, i, j, Mc));
     }
     __syncthreads();
     // red on tile + 1
 #pragma unroll
-    for (int m = 0; m < GNS; ++m) {
+    for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
-        bool own = gs_owned(tid, 0, m, lx, ly);
+        bool own = TL::owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !in_ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
-        int l = ly * GLW + lx;
+        if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+        int l = ly * TL::LW + lx;
         Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, GLW)), r.dre, r.dim);
+        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
     }
     __syncthreads();
     // black on the tile -> output; red tile nodes -> output
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-        for (int m = 0; m < GNS; ++m) {
+        for (int m = 0; m < TL::NS; ++m) {
             int lx, ly;
-            bool own = gs_owned(tid, c, m, lx, ly);
+            bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !in_ring(lx, ly, 0) || i > N || j > N) continue;
-            int l = ly * GLW + lx;
+            if (!own || !TL::ring(lx, ly, 0) || i > N || j > N) continue;
+            int l = ly * TL::LW + lx;
             C<double> v = U[l];
             if (c == 1) {
                 Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, GLW)), r.dre, r.dim);
+                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
             }
             uo[(size_t)j * M + i] = st_as<TU>(v);
         }
@@ -361,17 +370,26 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
 // u: 0 (ui == null) or ui, plus P ec when ec != null.  The region is loaded
 // CH cells per thread at a time with every global load of a batch issued
 // before the first is used (indices clamped into the domain).
+//
+// RESID (the last pre-smoothing launch of a level, Section 5): the halo
+// grows by two and the tile shrinks by four (the same LDS region), so that
+// after the passes u is exact on tile + 2; the residual with sigma_b is
+// formed on tile + 1 and full-weighted to the coarse nodes of the tile (fc),
+// which replaces the separate residual and restriction kernel.
 // ===========================================================================
-template <typename T, int TS, int S, int NT>
+template <typename T, int TS0, int S, int NT, bool RESID>
 __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, const T *__restrict__ k, double sig,
-                                                const C<T> *__restrict__ f, const C<T> *__restrict__ ui,
-                                                const C<T> *__restrict__ ec, C<T> *__restrict__ uo,
-                                                const int *skip) {
+                                                double sigb, const C<T> *__restrict__ f,
+                                                const C<T> *__restrict__ ui, const C<T> *__restrict__ ec,
+                                                C<T> *__restrict__ uo, C<T> *__restrict__ fc, const int *skip) {
     if (skip && *skip) return;
-    constexpr int RH = 10 * S, LW = TS + 2 * RH;
+    constexpr int TS = RESID ? TS0 - 4 : TS0;
+    constexpr int RH = 10 * S + (RESID ? 2 : 0), LW = TS + 2 * RH;
     // f and (k, 1/||a_p||^2) of the region are staged in LDS when they fit
     // next to u
     constexpr bool STAGE = (size_t)LW * LW * (16 + 16 + 16) <= 160 * 1024;
+    static_assert(STAGE || !RESID, "the fused residual needs the staged region");
+    static_assert(TS % 2 == 0, "tiles start on coarse nodes");
     constexpr int T5 = (LW - 2 + 4) / 5;              // row slots per line and colour
     constexpr int NSLOT = (LW - 2) * T5;              // slots per colour
     constexpr int NM = (NSLOT + NT - 1) / NT;         // slots per thread and colour
@@ -461,6 +479,48 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         int i = x0 + q % TS, j = y0 + q / TS;
         if (i > N || j > N) continue;
         uo[(size_t)j * M + i] = st_as<T>(U[(j - oy) * LW + (i - ox)]);
+    }
+    if constexpr (RESID) {
+        // residual f - A_{sigma_b} u on tile + 1, kept in registers until
+        // every thread has read f, then stored over f
+        constexpr int W1 = TS + 2, NR = (W1 * W1 + NT - 1) / NT;
+        C<double> res[NR];
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int q = tid + NT * m;
+            const int lx = RH - 1 + q % W1, ly = RH - 1 + q / W1, i = ox + lx, j = oy + ly;
+            if (q >= W1 * W1 || i < 0 || j < 0 || i > N || j > N) continue;
+            const int l = ly * LW + lx;
+            Row<double> r = row_at<double>(i, j, N, H, ih2, KS[l].x, sigb);
+            res[m] = csub(FS[l], cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, LW)));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int q = tid + NT * m;
+            const int lx = RH - 1 + q % W1, ly = RH - 1 + q / W1, i = ox + lx, j = oy + ly;
+            if (q >= W1 * W1 || i < 0 || j < 0 || i > N || j > N) continue;
+            FS[ly * LW + lx] = res[m];
+        }
+        __syncthreads();
+        // full weighting (mirrored at the boundary) for the coarse nodes of
+        // the tile
+        const int Nc = N / 2, Mc = Nc + 1;
+        constexpr int CX = TS / 2;
+        for (int q = tid; q < CX * CX; q += NT) {
+            const int I = x0 / 2 + q % CX, J = y0 / 2 + q / CX;
+            if (I > Nc || J > Nc) continue;
+            C<double> sum = cmk(0.0, 0.0);
+            for (int e = -1; e <= 1; ++e) {
+                const int j = mirror(2 * J + e, N);
+                for (int d = -1; d <= 1; ++d) {
+                    const int i = mirror(2 * I + d, N);
+                    const double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
+                    sum = cadd(sum, cscale(w, FS[(j - oy) * LW + (i - ox)]));
+                }
+            }
+            fc[(size_t)J * Mc + I] = st_as<T>(cscale(0.0625, sum));
+        }
     }
 }
 
@@ -732,12 +792,23 @@ __global__ __launch_bounds__(DNT) void k_dense_apply(const C<double> *__restrict
 // ===========================================================================
 static inline GeoT geo_t(const Geo &g) { return GeoT{g.n, g.M, g.N}; }
 
+// the small tile when the large one would give fewer than two workgroups per CU
+static bool gs_small(const Geo &g) {
+    return (size_t)((g.M + GsBig::X - 1) / GsBig::X) * ((g.M + GsBig::Y - 1) / GsBig::Y) < 512;
+}
+
+template <class TL>
+static dim3 gs_grid(const Geo &g) { return dim3((g.M + TL::X - 1) / TL::X, (g.M + TL::Y - 1) / TL::Y); }
+
 template <typename T, typename TF>
 static void gs_down_t(hipStream_t s, const Geo &g, const void *k, double sa, double sb, const void *f, void *uo,
                       void *fc, const int *skip) {
-    dim3 grid((g.M + GDX - 1) / GDX, (g.M + GDY - 1) / GDY);
-    k_gs_down<T, TF><<<grid, GNT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb,
-                                          (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
+    if (gs_small(g))
+        k_gs_down<GsSmall, T, TF><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
+    else
+        k_gs_down<GsBig, T, TF><<<gs_grid<GsBig>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
 }
 
 void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void *k, double sa, double sb,
@@ -750,9 +821,12 @@ void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void 
 template <typename T, typename TF, typename TU>
 static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const void *f, const void *ec, void *uo,
                     const int *skip) {
-    dim3 grid((g.M + GDX - 1) / GDX, (g.M + GDY - 1) / GDY);
-    k_gs_up<T, TF, TU><<<grid, GNT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f,
-                                            (const C<T> *)ec, (C<TU> *)uo, skip);
+    if (gs_small(g))
+        k_gs_up<GsSmall, T, TF, TU><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
+    else
+        k_gs_up<GsBig, T, TF, TU><<<gs_grid<GsBig>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
 }
 
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
@@ -766,9 +840,20 @@ template <typename T, int TS, int S, int NT>
 static void kacz_tb_t(hipStream_t s, const Geo &g, const void *k, double sig, const void *f, const void *ui,
                       const void *ec, void *uo, const int *skip) {
     dim3 grid((g.M + TS - 1) / TS, (g.M + TS - 1) / TS);
-    k_kacz_tb<T, TS, S, NT><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig,
-                                                (const C<T> *)f, (const C<T> *)ui, (const C<T> *)ec, (C<T> *)uo,
-                                                skip);
+    k_kacz_tb<T, TS, S, NT, false><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig, 0.0,
+                                                       (const C<T> *)f, (const C<T> *)ui, (const C<T> *)ec,
+                                                       (C<T> *)uo, nullptr, skip);
+}
+
+// the RESID form of a configuration: tile TS - 4, halo 10 S + 2
+template <typename T, int TS, int S, int NT>
+static void kacz_tb_resid_t(hipStream_t s, const Geo &g, const void *k, double sig, double sigb, const void *f,
+                            const void *ui, void *uo, void *fc, const int *skip) {
+    constexpr int T4 = TS - 4;
+    dim3 grid((g.M + T4 - 1) / T4, (g.M + T4 - 1) / T4);
+    k_kacz_tb<T, TS, S, NT, true><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig, sigb,
+                                                      (const C<T> *)f, (const C<T> *)ui, nullptr, (C<T> *)uo,
+                                                      (C<T> *)fc, skip);
 }
 
 // Tile configurations offered to the tuner: (tile side, sweeps per launch,
@@ -801,6 +886,31 @@ void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k,
                     const void *ui, const void *ec, void *uo, const int *skip) {
     if (p == P64) kacz_tb_any<double>(cfg, s, g, k, sig, f, ui, ec, uo, skip);
     else kacz_tb_any<float>(cfg, s, g, k, sig, f, ui, ec, uo, skip);
+}
+
+// Configurations whose region is staged in LDS have a RESID form.
+bool kacz_cfg_resid(int cfg) {
+    const KaczCfg &c = kKaczCfgs[cfg];
+    int lw = c.ts + 20 * c.sweeps;
+    return (size_t)lw * lw * 48 <= 160 * 1024;
+}
+
+template <typename T>
+static void kacz_resid_any(int cfg, hipStream_t s, const Geo &g, const void *k, double sig, double sigb,
+                           const void *f, const void *ui, void *uo, void *fc, const int *skip) {
+    switch (cfg) {
+    case 0: kacz_tb_resid_t<T, 32, 1, 512>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
+    case 2: kacz_tb_resid_t<T, 16, 2, 512>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
+    case 4: kacz_tb_resid_t<T, 16, 2, 1024>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
+    case 5: kacz_tb_resid_t<T, 16, 1, 512>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
+    default: kacz_tb_resid_t<T, 32, 1, 1024>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
+    }
+}
+
+void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, double sigb,
+                          const void *f, const void *ui, void *uo, void *fc, const int *skip) {
+    if (p == P64) kacz_resid_any<double>(cfg, s, g, k, sig, sigb, f, ui, uo, fc, skip);
+    else kacz_resid_any<float>(cfg, s, g, k, sig, sigb, f, ui, uo, fc, skip);
 }
 
 int bottom_complex_slots() { return BOT_C_ELEMS; }

@@ -103,6 +103,10 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
                   const void *ec, void *uo, const int *skip);
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
                     const void *ui, const void *ec, void *uo, const int *skip);
+bool kacz_cfg_resid(int cfg);   // configuration has the fused residual form
+// S sweeps (configuration cfg) from ui (null: zero), then fc = R (f - A_{sigb} u)
+void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, double sigb,
+                          const void *f, const void *ui, void *uo, void *fc, const int *skip);
 void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo,
                    const int *skip);
 int  bottom_matrix_size(const BottomDesc &d);

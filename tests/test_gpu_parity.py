@@ -256,6 +256,46 @@ def test_tiled_kaczmarz_matches_oracle(ctx, hmg, cfg, start, n):
     assert rel(host(d_uo), want) <= 1e-12
 
 
+@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 6])
+@pytest.mark.parametrize("start", ["zero", "u"])
+@pytest.mark.parametrize("n", [63, 127])
+def test_kaczmarz_down_matches_oracle(ctx, hmg, cfg, start, n):
+    """Last pre-smoothing launch with the restriction fused (Section 5):
+    S sweeps on M, then R (f - L u) on the next level."""
+    tile, sweeps, threads = hmg.kacz_tile_configs()[cfg]
+    say(f"case kacz_down cfg={cfg} ({tile},{sweeps},{threads}) start={start} n={n}")
+    h = 1.0 / (n + 1)
+    k = rand_k(n, 5 * n + cfg, 60.0, 150.0)
+    g = hmg.Grid(ctx, h, k)
+    f = inputs.random_field(n, 81)
+    nc = (n - 1) // 2
+    u0 = np.zeros_like(f)
+    d_ui = None
+    if start == "u":
+        u0 = inputs.random_field(n, 82)
+        d_ui = dev(u0)
+    d_uo = dev(np.zeros_like(f))
+    d_fc = dev(np.zeros((nc + 2, nc + 2), np.complex128))
+    g.op_kacz_down(0, 0.5, 0.0, cfg, dev(f), d_ui, d_uo, d_fc)
+    want = u0
+    for _ in range(sweeps):
+        want = oracle.kacz_5c(h, k, 0.5, f, want)
+    assert rel(host(d_uo), want) <= 1e-12
+    want_fc = oracle.restrict_fw(oracle.residual(h, k, 0.0, f, want))
+    assert rel(host(d_fc), want_fc) <= 1e-11
+
+
+def test_kaczmarz_down_rejects_unstaged_config(ctx, hmg):
+    g = hmg.Grid(ctx, 1 / 64, np.full((65, 65), 30.0))
+    a = dev(np.zeros((65, 65), np.complex128))
+    b = dev(np.zeros((65, 65), np.complex128))
+    fc = dev(np.zeros((33, 33), np.complex128))
+    with pytest.raises(hmg.HmgError):
+        g.op_kacz_down(0, 0.5, 0.0, 1, a, None, b, fc)      # (32, 2): region not staged
+    with pytest.raises(hmg.HmgError):
+        g.op_kacz_down(0, 0.5, 0.0, 2, a, None, b, b)       # fc aliases uo
+
+
 def test_fused_ops_reject_aliasing(ctx, hmg):
     n = 63
     g = hmg.Grid(ctx, 1 / 64, np.full((65, 65), 30.0))
