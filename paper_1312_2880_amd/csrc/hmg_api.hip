@@ -218,6 +218,7 @@ static void layout(hmg_grid *g, Carver &c) {
         Level &L = g->lev[l];
         size_t m = (size_t)L.geo.M * L.geo.M;
         L.k = c.take(m * rsz);
+        L.ktab = (L.mode == LM_KACZ_TILED) ? (double *)c.take(m * 16) : nullptr;
     }
     g->k0 = (double *)c.take((size_t)g->lev[0].geo.M * g->lev[0].geo.M * 8);
     int mc = g->lev[g->nlev - 1].geo.M;
@@ -379,16 +380,16 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                 int w = 0;
                 for (int q = 0; q < pl.pre[l]; q += sw) {
                     if (kacz_cfg_resid(cfg) && q + sw >= pl.pre[l])
-                        launch_kacz_tb_resid(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l],
+                        launch_kacz_tb_resid(g->prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l],
                                              pl.sigma_resid[l], S.f[l], cur, bufs[w], S.f[l + 1], nullptr);
                     else
-                        launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l], S.f[l], cur,
-                                       nullptr, bufs[w], nullptr);
+                        launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l],
+                                       cur, nullptr, bufs[w], nullptr);
                     cur = bufs[w];
                     w ^= 1;
                 }
                 for (int q = 0; q < pl.post[l] && cur; q += sw) {
-                    launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, pl.sigma_relax[l], S.f[l], cur,
+                    launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l], cur,
                                    q == 0 ? S.u[l + 1] : nullptr, bufs[w], nullptr);
                     cur = bufs[w];
                     w ^= 1;
@@ -398,7 +399,7 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
             hipGraph_t gr = nullptr;
             hipGraphExec_t ge = nullptr;
             HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
-            for (int r = 0; r < 3; ++r) legs();
+            for (int r = 0; r < 4; ++r) legs();
             HIPCHK(hipStreamEndCapture(g->stream, &gr));
             hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
             if (ie != hipSuccess) {
@@ -407,7 +408,7 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
             }
             float ms = 1e30f;
             hipError_t le = hipGraphLaunch(ge, g->stream);   // warm-up
-            for (int r = 0; r < 2 && le == hipSuccess; ++r) {
+            for (int r = 0; r < 3 && le == hipSuccess; ++r) {
                 le = hipEventRecord(e0, g->stream);
                 if (le == hipSuccess) le = hipGraphLaunch(ge, g->stream);
                 if (le == hipSuccess) le = hipEventRecord(e1, g->stream);
@@ -466,6 +467,9 @@ size_t estimate_footprint(int n, const hmg_opts &o) {
     g.nlev = l + 1;
     g.opts = o;
     g.lb = find_bottom(&g);
+    // the Kaczmarz levels depend on k: count a row table on every level
+    // below the finest
+    for (int q = 1; q < g.nlev; ++q) g.lev[q].mode = LM_KACZ_TILED;
     g.slot.resize(1);
     Carver c;
     layout(&g, c);
@@ -557,6 +561,14 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     layout(g, c);
     bottom_desc(g);
     hmg_status st = grid_init_device(g, kl, inv, f);
+    if (st == HMG_OK) {
+        for (int l = 0; l < g->nlev; ++l)
+            if (g->lev[l].ktab)
+                launch_kacz_table(g->prec, g->stream, g->lev[l].geo, g->lev[l].k, g->plan.sigma_relax[l],
+                                  g->lev[l].ktab);
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess) st = hmg_fail(HMG_ERR_DEVICE, "Kaczmarz tables: %s", hipGetErrorString(le));
+    }
     if (st == HMG_OK && g->bop) {
         // the bottom cycle on every unit vector: its matrix, column by column
         launch_bottom_basis(g->prec, g->stream, g->bottom, g->bop);
@@ -701,10 +713,10 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         const bool fuse = pl.pre[l] > 0 && kacz_cfg_resid(cfg);
         for (int q = 0; q < pl.pre[l]; q += sw) {
             if (fuse && q + sw >= pl.pre[l])
-                launch_kacz_tb_resid(g->prec, cfg, s, L.geo, L.k, sig, pl.sigma_resid[l], f, cur, bufs[w],
+                launch_kacz_tb_resid(g->prec, cfg, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], f, cur, bufs[w],
                                      S.f[l + 1], skip);
             else
-                launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, sig, f, cur, nullptr, bufs[w], skip);
+                launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, nullptr, bufs[w], skip);
             cur = bufs[w];
             w ^= 1;
         }
@@ -719,7 +731,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
             launch_prolong_add(g->prec, s, L.geo, e, (void *)cur, skip);
         }
         for (int q = 0; q < pl.post[l]; q += sw) {
-            launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip);
+            launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip);
             cur = bufs[w];
             w ^= 1;
         }
@@ -896,7 +908,8 @@ extern "C" hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma
         return hmg_fail(HMG_ERR_INVALID, "bad fields (the output must not alias an input)");
     if (d_ec && level >= g->nlev - 1) return hmg_fail(HMG_ERR_INVALID, "no coarser level");
     const Level &L = g->lev[level];
-    launch_kacz_tb(g->prec, config, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_ui, d_ec, d_uo, nullptr);
+    launch_kacz_tb(g->prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma, d_f, d_ui, d_ec, d_uo,
+                   nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }
@@ -912,8 +925,8 @@ extern "C" hmg_status hmg_op_kacz_down_dev(hmg_grid *g, int level, double sigma_
     if (!d_f || !d_uo || !d_fc || d_uo == d_ui || d_uo == d_f || d_fc == d_f || d_fc == d_ui || d_fc == d_uo)
         return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs or each other)");
     const Level &L = g->lev[level];
-    launch_kacz_tb_resid(g->prec, config, pick_stream(g, stream), L.geo, L.k, sigma_relax, sigma_resid, d_f, d_ui,
-                         d_uo, d_fc, nullptr);
+    launch_kacz_tb_resid(g->prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid,
+                         d_f, d_ui, d_uo, d_fc, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }

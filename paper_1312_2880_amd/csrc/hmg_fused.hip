@@ -369,7 +369,9 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
 // writes its five cells without tests and the padding stays zero.  Initial
 // u: 0 (ui == null) or ui, plus P ec when ec != null.  The region is loaded
 // CH cells per thread at a time with every global load of a batch issued
-// before the first is used (indices clamped into the domain).
+// before the first is used (indices clamped into the domain).  ktab, when
+// given, holds (k_p, 1 / ||a_p||^2) for sigma (k_kacz_table); else both are
+// formed here.
 //
 // RESID (the last pre-smoothing launch of a level, Section 5): the halo
 // grows by two and the tile shrinks by four (the same LDS region), so that
@@ -378,7 +380,8 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
 // which replaces the separate residual and restriction kernel.
 // ===========================================================================
 template <typename T, int TS0, int S, int NT, bool RESID>
-__global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, const T *__restrict__ k, double sig,
+__global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, const T *__restrict__ k,
+                                                const C<double> *__restrict__ ktab, double sig,
                                                 double sigb, const C<T> *__restrict__ f,
                                                 const C<T> *__restrict__ ui, const C<T> *__restrict__ ec,
                                                 C<T> *__restrict__ uo, C<T> *__restrict__ fc, const int *skip) {
@@ -394,7 +397,10 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
     constexpr int NSLOT = (LW - 2) * T5;              // slots per colour
     constexpr int NM = (NSLOT + NT - 1) / NT;         // slots per thread and colour
     constexpr int NL = (LW * LW + NT - 1) / NT;       // region cells per thread
-    constexpr int CH = NL < 4 ? NL : 4;               // cells per load batch
+    // cells per load batch: about 28 registers each in flight, within the
+    // budget of NT threads per workgroup
+    constexpr int CHMAX = NT >= 1024 ? 2 : 4;
+    constexpr int CH = NL < CHMAX ? NL : CHMAX;
     __shared__ C<double> U[LW * LW];
     __shared__ C<double> FS[STAGE ? LW * LW : 1];
     __shared__ C<double> KS[STAGE ? LW * LW : 1];
@@ -403,8 +409,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
     const int ox = x0 - RH, oy = y0 - RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     for (int b0 = 0; b0 < NL; b0 += CH) {
-        C<double> vu[CH], vf[CH], e[CH][4];
-        double vk[CH];
+        C<double> vu[CH], vf[CH], e[CH][4], vkn[CH];   // vkn: (k, 1/||a_p||^2) or (k, -)
 #pragma unroll
         for (int s = 0; s < CH; ++s) {
             const int q = tid + NT * (b0 + s);
@@ -420,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
             }
             if (STAGE) {
                 vf[s] = ldr<double>(f, p);
-                vk[s] = (double)k[p];
+                vkn[s] = ktab ? ktab[p] : cmk((double)k[p], 0.0);
             }
         }
 #pragma unroll
@@ -433,10 +438,15 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
             if (ec) v = cadd(v, bilinear(e[s][0], e[s][1], e[s][2], e[s][3], i, j));
             U[q] = in ? v : cmk(0.0, 0.0);
             if (STAGE) {
-                Row<double> r = row_at<double>(min(max(i, 0), N), min(max(j, 0), N), N, H, ih2, vk[s], sig);
-                double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
                 FS[q] = in ? vf[s] : cmk(0.0, 0.0);
-                KS[q] = in ? cmk(vk[s], 1.0 / nrm) : cmk(0.0, 0.0);
+                C<double> kn = vkn[s];
+                if (!ktab) {
+                    Row<double> r = row_at<double>(min(max(i, 0), N), min(max(j, 0), N), N, H, ih2, kn.x, sig);
+                    double nrm =
+                        r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+                    kn.y = 1.0 / nrm;
+                }
+                KS[q] = in ? kn : cmk(0.0, 0.0);
             }
         }
     }
@@ -522,6 +532,20 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
             fc[(size_t)J * Mc + I] = st_as<T>(cscale(0.0625, sum));
         }
     }
+}
+
+// (k_p, 1 / ||a_p||^2) of the rows of A_sigma on a level: fixed for a grid,
+// formed once for each Kaczmarz level and read by k_kacz_tb.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_kacz_table(GeoT g, double H, double ih2, const T *__restrict__ k,
+                                                   double sig, C<double> *__restrict__ tab) {
+    const size_t p = (size_t)blockIdx.x * NT + threadIdx.x;
+    if (p >= (size_t)g.M * g.M) return;
+    const int i = (int)(p % g.M), j = (int)(p / g.M);
+    const double kp = (double)k[p];
+    Row<double> r = row_at<double>(i, j, g.N, H, ih2, kp, sig);
+    double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+    tab[p] = cmk(kp, 1.0 / nrm);
 }
 
 // ===========================================================================
@@ -837,23 +861,24 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
 }
 
 template <typename T, int TS, int S, int NT>
-static void kacz_tb_t(hipStream_t s, const Geo &g, const void *k, double sig, const void *f, const void *ui,
-                      const void *ec, void *uo, const int *skip) {
+static void kacz_tb_t(hipStream_t s, const Geo &g, const void *k, const double *tab, double sig, const void *f,
+                      const void *ui, const void *ec, void *uo, const int *skip) {
     dim3 grid((g.M + TS - 1) / TS, (g.M + TS - 1) / TS);
-    k_kacz_tb<T, TS, S, NT, false><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig, 0.0,
-                                                       (const C<T> *)f, (const C<T> *)ui, (const C<T> *)ec,
-                                                       (C<T> *)uo, nullptr, skip);
+    k_kacz_tb<T, TS, S, NT, false><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
+                                                       (const C<double> *)tab, sig, 0.0, (const C<T> *)f,
+                                                       (const C<T> *)ui, (const C<T> *)ec, (C<T> *)uo, nullptr,
+                                                       skip);
 }
 
 // the RESID form of a configuration: tile TS - 4, halo 10 S + 2
 template <typename T, int TS, int S, int NT>
-static void kacz_tb_resid_t(hipStream_t s, const Geo &g, const void *k, double sig, double sigb, const void *f,
-                            const void *ui, void *uo, void *fc, const int *skip) {
+static void kacz_tb_resid_t(hipStream_t s, const Geo &g, const void *k, const double *tab, double sig, double sigb,
+                            const void *f, const void *ui, void *uo, void *fc, const int *skip) {
     constexpr int T4 = TS - 4;
     dim3 grid((g.M + T4 - 1) / T4, (g.M + T4 - 1) / T4);
-    k_kacz_tb<T, TS, S, NT, true><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sig, sigb,
-                                                      (const C<T> *)f, (const C<T> *)ui, nullptr, (C<T> *)uo,
-                                                      (C<T> *)fc, skip);
+    k_kacz_tb<T, TS, S, NT, true><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
+                                                      (const C<double> *)tab, sig, sigb, (const C<T> *)f,
+                                                      (const C<T> *)ui, nullptr, (C<T> *)uo, (C<T> *)fc, skip);
 }
 
 // Tile configurations offered to the tuner: (tile side, sweeps per launch,
@@ -869,23 +894,33 @@ bool kacz_cfg_fits(Prec, int cfg) {
 }
 
 template <typename T>
-static void kacz_tb_any(int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
-                        const void *ui, const void *ec, void *uo, const int *skip) {
+static void kacz_tb_any(int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
+                        const void *f, const void *ui, const void *ec, void *uo, const int *skip) {
     switch (cfg) {
-    case 0: kacz_tb_t<T, 32, 1, 512>(s, g, k, sig, f, ui, ec, uo, skip); break;
-    case 1: kacz_tb_t<T, 32, 2, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
-    case 2: kacz_tb_t<T, 16, 2, 512>(s, g, k, sig, f, ui, ec, uo, skip); break;
-    case 3: kacz_tb_t<T, 16, 4, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
-    case 4: kacz_tb_t<T, 16, 2, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
-    case 5: kacz_tb_t<T, 16, 1, 512>(s, g, k, sig, f, ui, ec, uo, skip); break;
-    default: kacz_tb_t<T, 32, 1, 1024>(s, g, k, sig, f, ui, ec, uo, skip); break;
+    case 0: kacz_tb_t<T, 32, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 1: kacz_tb_t<T, 32, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 2: kacz_tb_t<T, 16, 2, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 3: kacz_tb_t<T, 16, 4, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 4: kacz_tb_t<T, 16, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 5: kacz_tb_t<T, 16, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    default: kacz_tb_t<T, 32, 1, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
     }
 }
 
-void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
-                    const void *ui, const void *ec, void *uo, const int *skip) {
-    if (p == P64) kacz_tb_any<double>(cfg, s, g, k, sig, f, ui, ec, uo, skip);
-    else kacz_tb_any<float>(cfg, s, g, k, sig, f, ui, ec, uo, skip);
+void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
+                    const void *f, const void *ui, const void *ec, void *uo, const int *skip) {
+    if (p == P64) kacz_tb_any<double>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip);
+    else kacz_tb_any<float>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip);
+}
+
+void launch_kacz_table(Prec p, hipStream_t s, const Geo &g, const void *k, double sig, double *tab) {
+    const unsigned nb = (unsigned)(((size_t)g.M * g.M + NT - 1) / NT);
+    if (p == P64)
+        k_kacz_table<double><<<nb, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const double *)k, sig,
+                                                (C<double> *)tab);
+    else
+        k_kacz_table<float><<<nb, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const float *)k, sig,
+                                               (C<double> *)tab);
 }
 
 // Configurations whose region is staged in LDS have a RESID form.
@@ -896,21 +931,22 @@ bool kacz_cfg_resid(int cfg) {
 }
 
 template <typename T>
-static void kacz_resid_any(int cfg, hipStream_t s, const Geo &g, const void *k, double sig, double sigb,
-                           const void *f, const void *ui, void *uo, void *fc, const int *skip) {
+static void kacz_resid_any(int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
+                           double sigb, const void *f, const void *ui, void *uo, void *fc, const int *skip) {
     switch (cfg) {
-    case 0: kacz_tb_resid_t<T, 32, 1, 512>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
-    case 2: kacz_tb_resid_t<T, 16, 2, 512>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
-    case 4: kacz_tb_resid_t<T, 16, 2, 1024>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
-    case 5: kacz_tb_resid_t<T, 16, 1, 512>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
-    default: kacz_tb_resid_t<T, 32, 1, 1024>(s, g, k, sig, sigb, f, ui, uo, fc, skip); break;
+    case 0: kacz_tb_resid_t<T, 32, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
+    case 2: kacz_tb_resid_t<T, 16, 2, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
+    case 4: kacz_tb_resid_t<T, 16, 2, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
+    case 5: kacz_tb_resid_t<T, 16, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
+    default: kacz_tb_resid_t<T, 32, 1, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
     }
 }
 
-void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, double sigb,
-                          const void *f, const void *ui, void *uo, void *fc, const int *skip) {
-    if (p == P64) kacz_resid_any<double>(cfg, s, g, k, sig, sigb, f, ui, uo, fc, skip);
-    else kacz_resid_any<float>(cfg, s, g, k, sig, sigb, f, ui, uo, fc, skip);
+void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab,
+                          double sig, double sigb, const void *f, const void *ui, void *uo, void *fc,
+                          const int *skip) {
+    if (p == P64) kacz_resid_any<double>(cfg, s, g, k, tab, sig, sigb, f, ui, uo, fc, skip);
+    else kacz_resid_any<float>(cfg, s, g, k, tab, sig, sigb, f, ui, uo, fc, skip);
 }
 
 int bottom_complex_slots() { return BOT_C_ELEMS; }

@@ -31,6 +31,7 @@ struct Level {
     void     *k = nullptr;  // wavenumber in the V-cycle precision
     int       mode = LM_SIMPLE;
     int       kacz_cfg = 1; // index into hmgk::kKaczCfgs
+    double   *ktab = nullptr;  // Kaczmarz levels: (k_p, 1 / ||a_p||^2), complex-interleaved FP64
 };
 
 // Per right-hand side: level fields of one V-cycle in flight and the

@@ -101,12 +101,16 @@ void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void 
 // launch_gs_up recomputes it from f.
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
                   const void *ec, void *uo, const int *skip);
-void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, const void *f,
-                    const void *ui, const void *ec, void *uo, const int *skip);
+// tab: (k_p, 1 / ||a_p||^2) for sigma from launch_kacz_table, or null (the
+// kernel forms them)
+void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
+                    const void *f, const void *ui, const void *ec, void *uo, const int *skip);
+void launch_kacz_table(Prec p, hipStream_t s, const Geo &g, const void *k, double sig, double *tab);
 bool kacz_cfg_resid(int cfg);   // configuration has the fused residual form
 // S sweeps (configuration cfg) from ui (null: zero), then fc = R (f - A_{sigb} u)
-void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, double sig, double sigb,
-                          const void *f, const void *ui, void *uo, void *fc, const int *skip);
+void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab,
+                          double sig, double sigb, const void *f, const void *ui, void *uo, void *fc,
+                          const int *skip);
 void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo,
                    const int *skip);
 int  bottom_matrix_size(const BottomDesc &d);
