@@ -103,10 +103,10 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
         sa, sb = plan[0]["sigma_relax"], plan[0]["sigma_resid"]
         out.append(("gs_down", 0, lambda q, st: g.op_gs_down(0, sa, sb, bufs[q % sets]["f"], None,
                                                              bufs[q % sets]["fc"], st), 1,
-                    ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb))))
+                    ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb)), None))
         out.append(("gs_up", 0, lambda q, st: g.op_gs_up(0, sa, bufs[q % sets]["f"], bufs[q % sets]["ec"],
                                                          bufs[q % sets]["uo"], st), 1,
-                    ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb))))
+                    ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb)), None))
     for l, p in enumerate(plan):
         cfg = g.kacz_config(l)
         if cfg < 0:
@@ -122,7 +122,7 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
                         l, sig, cfg, kb[q % 4]["f"], kb[q % 4]["u"], None, kb[q % 4]["uo"], st),
                     (p["pre"] + p["post"]) // sweeps,
                     ("alu", KACZ_ROW_FLOPS * sweeps * (n + 2) ** 2,
-                     algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb))))
+                     algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb)), cfg))
     return out
 
 
@@ -145,12 +145,12 @@ def roofline_of(model, ms):
 def time_kernels(torch, g, plan, precision, only=None, fixed=None):
     stream = torch.cuda.Stream()
     res = []
-    for name, level, fn, per_vc, model in kernel_cases(torch, g, plan, precision, fixed=fixed):
+    for name, level, fn, per_vc, model, cfg in kernel_cases(torch, g, plan, precision, fixed=fixed):
         key = f"{name}@{plan[level]['n']}"
         if only and key != only:
             continue
         ms = graph_time(torch, stream, lambda q: fn(q, stream), 48)
-        res.append(dict(key=key, name=name, level=level, ms=ms, per_vcycle=per_vc, model=model))
+        res.append(dict(key=key, name=name, level=level, ms=ms, per_vcycle=per_vc, model=model, cfg=cfg))
     torch.cuda.synchronize()
     return res
 
@@ -189,7 +189,7 @@ def cpu_baseline(h, k, f, variant, budget_s=10.0, max_solves=3):
         done += 1
     dt = time.perf_counter() - t0
     return dict(value=done / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"{done} full FP64 oracle solve(s) of the same 1023^2 problem on {threads} threads "
+                sample=f"{done} full FP64 oracle solve(s) of the same {k.shape[0] - 2}^2 problem on {threads} threads "
                        f"({iters[-1]} iterations each, {dt:.1f} s in total)",
                 iters=iters[-1])
 
@@ -202,6 +202,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--maxit", type=int, default=400)
+    ap.add_argument("--n", type=int, choices=[1023, 2047], default=1023,
+                    help="1023: the benchmark problem; 2047: the same medium at omega = 2 pi 80 "
+                         "(the precision-form problem)")
     ap.add_argument("--traffic-probe", default=None, metavar="KERNEL@N",
                     help="only launch this kernel (e.g. kacz_tb@127) as the timing does, then "
                          "a plain copy of known size, for the FETCH_SIZE / WRITE_SIZE runs")
@@ -221,7 +224,7 @@ def main():
     from paper_1312_2880_amd import hmg, inputs
 
     torch.cuda.set_device(0)
-    h, k, f = inputs.workload_layered_1023()
+    h, k, f = inputs.workload_layered_1023() if args.n == 1023 else inputs.workload_layered_2047()
     n = k.shape[0] - 2
     prec = hmg.FP64 if args.precision == "fp64" else hmg.MIXED
     ctx = hmg.Context(0)
@@ -266,13 +269,15 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            ent = tr.get(f"{dom['key']}:{args.precision}")
+            tkey = dom["key"] + (f"/cfg{dom['cfg']}" if dom["cfg"] is not None else "")
+            ent = tr.get(f"{tkey}:{args.precision}")
             if ent and ent.get("kernel_source_hash") == kernel_source_hash():
                 traffic = ent.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
     roofline = dict(dom["roofline"])
-    roofline.update({"traffic": traffic, "kernel": dom["key"], "ms_per_launch": round(dom["ms"], 5),
+    roofline.update({"traffic": traffic, "kernel": dom["key"], "config": dom["cfg"],
+                     "ms_per_launch": round(dom["ms"], 5),
                      "per_launch": dom["model"][1], "share_of_solve": round(dom["share"], 3)})
 
     cpu = None
@@ -293,8 +298,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c128" if args.precision == "fp64" else "c64/c128",
         "data": "synthetic",
-        "config": {"workload": "layered-medium Helmholtz 1023x1023, omega = 2 pi 40, "
-                               "HYB-V preconditioned Bi-CGSTAB to 1e-6, seed 2",
+        "config": {"workload": (f"layered-medium Helmholtz {n}x{n}, omega = 2 pi {40 * (n + 1) // 1024}, "
+                                "HYB-V preconditioned Bi-CGSTAB to 1e-6, seed 2"),
                    "n": n, "precision": args.precision,
                    "iters": last["iters"], "mean_iters": mean_iters, "rel_res_true": last["rel_res_true"],
                    "all_converged": ok,

@@ -2,10 +2,10 @@
 sizes through the request server (continuous batching, admission by device
 footprint), against the same stream served one request at a time in FP64.
 
-    python bench_serve.py [--rates 5,20,50] [--count 30] [--warmup 4]
+    python bench_serve.py [--rates 5,50] [--count 30] [--warmup 4]
 
 Each request: n ~ U{255, 511, 1023, 2047}, a seeded layered medium with
-omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, HYB-V
+omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, SL-V
 preconditioner, relative residual 1e-6.  The served form runs the V-cycle in
 complex float under the FP64 Bi-CGSTAB; the baseline runs plain FP64 with at
 most one request in flight.  Latency = completion time - submission time on
@@ -62,7 +62,7 @@ def serve(hmg, reqs, precision, max_active, warmup, maxit):
             if delay > 0:
                 time.sleep(delay)
             tickets[q] = ctx.submit(n=r["n"], h=r["h"], k=r["k"], f=r["f"], rtol=1e-6,
-                                    maxit=maxit, variant=hmg.HYB, precision=precision)
+                                    maxit=maxit, variant=hmg.SL, precision=precision)
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -73,6 +73,8 @@ def serve(hmg, reqs, precision, max_active, warmup, maxit):
             res = ctx.poll(t)
             if res is not None:
                 results[q] = res[1]
+                if len(results) % 8 == 0:
+                    print(f"# {len(results)}/{len(reqs)} requests done", flush=True)
         time.sleep(0.0005)
     th.join()
     ctx.close()
@@ -89,12 +91,12 @@ def serve(hmg, reqs, precision, max_active, warmup, maxit):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rates", default="5,20,50")
+    ap.add_argument("--rates", default="5,50")
     ap.add_argument("--count", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--max-active", type=int, default=0)
-    ap.add_argument("--maxit", type=int, default=2000)
+    ap.add_argument("--maxit", type=int, default=3000)
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -112,7 +114,7 @@ def main():
                     "mean_iters": round(out["mean_iters"], 2), "max_iters": out["max_iters"],
                     "solves": out["solves"],
                     "all_converged": out["all_converged"], "data": "synthetic",
-                    "config": {"sizes": [255, 511, 1023, 2047], "variant": "HYB-V",
+                    "config": {"sizes": [255, 511, 1023, 2047], "variant": "SL-V",
                                "seed": args.seed, "rtol": 1e-6}}
             print(json.dumps(line), flush=True)
 

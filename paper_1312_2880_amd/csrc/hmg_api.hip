@@ -286,9 +286,10 @@ static void plan_paths(hmg_grid *g) {
             g->lev[l].mode = LM_GS_FUSED;
         } else if (pl.smoother[l] == HMG_SM_KACZ) {
             g->lev[l].mode = LM_KACZ_TILED;
-            // default before tuning: the LDS-staged tile with 2 sweeps per
-            // launch if it divides both sweep counts, else one sweep per launch
-            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? 2 : 0;
+            // default before tuning: the LDS-staged 16 x 16 tile with 2
+            // sweeps per launch (1024 threads) if 2 divides both sweep
+            // counts, else one sweep per launch
+            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? 4 : 5;
             g->lev[l].kacz_cfg = best;
         }
     }
@@ -420,6 +421,9 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
             (void)hipGraphExecDestroy(ge);
             (void)hipGraphDestroy(gr);
             if (le != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "tuner: %s", hipGetErrorString(le));
+            // the default keeps its place unless another configuration is
+            // clearly faster (runs then agree on the choice)
+            if (cfg == g->lev[l].kacz_cfg) ms *= 0.95f;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = cfg;
