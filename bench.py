@@ -113,10 +113,19 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
             continue
         if fixed:
             cfg = fixed[l]
-        tile, sweeps, _ = hmg_configs()[cfg]
         n = p["n"]
         kb = [dict(f=field(n), u=field(n), uo=field(n)) for _ in range(4)]
         sig = p["sigma_relax"]
+        if cfg >= len(hmg_configs()):
+            # the whole level in one workgroup: one launch per leg
+            out.append(("kacz_level", l,
+                        lambda q, st, l=l, sig=sig, p=p, kb=kb: g.op_kacz_level(
+                            l, sig, 0.0, p["pre"], kb[q % 4]["f"], kb[q % 4]["u"], None, kb[q % 4]["uo"], None,
+                            st),
+                        2, ("alu", KACZ_ROW_FLOPS * p["pre"] * (n + 2) ** 2,
+                            algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb)), cfg))
+            continue
+        tile, sweeps, _ = hmg_configs()[cfg]
         out.append(("kacz_tb", l,
                     lambda q, st, l=l, sig=sig, cfg=cfg, kb=kb: g.op_kacz_tiled(
                         l, sig, cfg, kb[q % 4]["f"], kb[q % 4]["u"], None, kb[q % 4]["uo"], st),

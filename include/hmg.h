@@ -274,8 +274,18 @@ hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int confi
  * halo two nodes wider).  Outputs must not alias inputs or each other. */
 hmg_status hmg_op_kacz_down_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid, int config,
                                 const void *d_f, const void *d_ui, void *d_uo, void *d_fc, void *stream);
-/* Tile configuration chosen for a Kaczmarz level of the grid (-1: the level
- * is not relaxed by the tiled kernel). */
+/* A whole Kaczmarz level with n <= 63 in one workgroup (Sections 4-5):
+ * uo = `sweeps` 5-colour Kaczmarz sweeps on A_{sigma_relax} starting from
+ * ui (NULL: zero) plus P ec (NULL: none); then, when d_fc != NULL,
+ * fc = R (f - A_{sigma_resid} uo) on level + 1.  Outputs must not alias
+ * inputs or each other. */
+hmg_status hmg_op_kacz_level_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid, int sweeps,
+                                 const void *d_f, const void *d_ui, const void *d_ec, void *d_uo, void *d_fc,
+                                 void *stream);
+/* Tile configuration chosen for a Kaczmarz level of the grid: an index of
+ * hmg_kacz_tile_config, the number of configurations when the tuner chose
+ * the whole-level kernel (hmg_op_kacz_level_dev), or -1 when the level is
+ * not a Kaczmarz level of the fused schedule. */
 int        hmg_grid_kacz_config(const hmg_grid *g, int level);
 /* Tile side, sweeps per launch and workgroup size of Kaczmarz tile
  * configuration `config` (NULL outputs are skipped); returns the number of

@@ -218,7 +218,7 @@ static void layout(hmg_grid *g, Carver &c) {
         Level &L = g->lev[l];
         size_t m = (size_t)L.geo.M * L.geo.M;
         L.k = c.take(m * rsz);
-        L.ktab = (L.mode == LM_KACZ_TILED) ? (double *)c.take(m * 16) : nullptr;
+        L.ktab = (L.mode == LM_KACZ_TILED || L.mode == LM_KACZ_LEVEL) ? (double *)c.take(m * 16) : nullptr;
     }
     g->k0 = (double *)c.take((size_t)g->lev[0].geo.M * g->lev[0].geo.M * 8);
     int mc = g->lev[g->nlev - 1].geo.M;
@@ -339,7 +339,8 @@ static void bottom_desc(hmg_grid *g) {
 #include <tuple>
 
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int, int>, int> g_tune_cache;
+// (device, n, precision, pre, post) -> (configuration, level mode)
+static std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
 
 static hmg_status tune_kacz_level(hmg_grid *g, int l) {
     const hmg_plan &pl = g->plan;
@@ -348,7 +349,8 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            g->lev[l].kacz_cfg = it->second;
+            g->lev[l].kacz_cfg = it->second.first;
+            g->lev[l].mode = it->second.second;
             return HMG_OK;
         }
     }
@@ -429,14 +431,47 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                 best = cfg;
             }
         }
+        // a level small enough for one workgroup may run whole (no halo
+        // work, but one CU): same two legs, kept only if faster
+        bool whole = false;
+        if (kacz_level_fits(L.geo)) {
+            auto legs = [&]() {
+                launch_kacz_level(g->prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], pl.sigma_resid[l],
+                                  pl.pre[l], S.f[l], nullptr, nullptr, S.u[l], S.f[l + 1], nullptr);
+                launch_kacz_level(g->prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], 0.0, pl.post[l],
+                                  S.f[l], S.u[l], S.u[l + 1], S.u2[l], nullptr, nullptr);
+            };
+            hipGraph_t gr = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+            for (int r = 0; r < 4; ++r) legs();
+            HIPCHK(hipStreamEndCapture(g->stream, &gr));
+            hipError_t le = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+            float ms = 1e30f;
+            if (le == hipSuccess) le = hipGraphLaunch(ge, g->stream);
+            for (int r = 0; r < 3 && le == hipSuccess; ++r) {
+                le = hipEventRecord(e0, g->stream);
+                if (le == hipSuccess) le = hipGraphLaunch(ge, g->stream);
+                if (le == hipSuccess) le = hipEventRecord(e1, g->stream);
+                if (le == hipSuccess) le = hipEventSynchronize(e1);
+                float t = 0.f;
+                if (le == hipSuccess) le = hipEventElapsedTime(&t, e0, e1);
+                if (le == hipSuccess) ms = std::min(ms, t);
+            }
+            if (ge) (void)hipGraphExecDestroy(ge);
+            (void)hipGraphDestroy(gr);
+            if (le != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "tuner: %s", hipGetErrorString(le));
+            whole = ms < 0.95f * best_ms;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         g->lev[l].kacz_cfg = best;
+        if (whole) g->lev[l].mode = LM_KACZ_LEVEL;
     } else if (cand.size() == 1) {
         g->lev[l].kacz_cfg = cand[0];
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = g->lev[l].kacz_cfg;
+    g_tune_cache[key] = std::make_pair(g->lev[l].kacz_cfg, g->lev[l].mode);
     return HMG_OK;
 }
 
@@ -451,7 +486,9 @@ static hmg_status tune_levels(hmg_grid *g) {
 }
 
 extern "C" int hmg_grid_kacz_config(const hmg_grid *g, int level) {
-    if (!g || level < 0 || level >= g->nlev || g->lev[level].mode != LM_KACZ_TILED) return -1;
+    if (!g || level < 0 || level >= g->nlev) return -1;
+    if (g->lev[level].mode == LM_KACZ_LEVEL) return KACZ_NCFG;
+    if (g->lev[level].mode != LM_KACZ_TILED) return -1;
     return g->lev[level].kacz_cfg;
 }
 
@@ -707,6 +744,16 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         return dst;
     }
     size_t m = (size_t)L.geo.M * L.geo.M;
+    if (L.mode == LM_KACZ_LEVEL) {
+        // pre-smoothing + restriction, coarser levels, correction + post-smoothing
+        double sig = pl.sigma_relax[l];
+        launch_kacz_level(g->prec, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], pl.pre[l], f, nullptr, nullptr,
+                          S.u[l], S.f[l + 1], skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+        void *dst = out ? out : S.u2[l];
+        launch_kacz_level(g->prec, s, L.geo, L.k, L.ktab, sig, 0.0, pl.post[l], f, S.u[l], e, dst, nullptr, skip);
+        return dst;
+    }
     if (L.mode == LM_KACZ_TILED) {
         int cfg = L.kacz_cfg, sw = kKaczCfgs[cfg].sweeps;
         double sig = pl.sigma_relax[l];
@@ -931,6 +978,24 @@ extern "C" hmg_status hmg_op_kacz_down_dev(hmg_grid *g, int level, double sigma_
     const Level &L = g->lev[level];
     launch_kacz_tb_resid(g->prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid,
                          d_f, d_ui, d_uo, d_fc, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_kacz_level_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid,
+                                            int sweeps, const void *d_f, const void *d_ui, const void *d_ec,
+                                            void *d_uo, void *d_fc, void *stream) {
+    hmg_status st = check_level(g, level, false);
+    if (st) return st;
+    if (!kacz_level_fits(g->lev[level].geo))
+        return hmg_fail(HMG_ERR_INVALID, "level %d is larger than n = 63", level);
+    if (sweeps < 0 || sweeps > 64) return hmg_fail(HMG_ERR_INVALID, "sweeps must be in [0, 64]");
+    if ((d_ec || d_fc) && level >= g->nlev - 1) return hmg_fail(HMG_ERR_INVALID, "no coarser level");
+    if (!d_f || !d_uo || d_uo == d_f || d_uo == d_ui || d_uo == d_ec || (d_fc && (d_fc == d_f || d_fc == d_uo)))
+        return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs or each other)");
+    const Level &L = g->lev[level];
+    launch_kacz_level(g->prec, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid, sweeps, d_f,
+                      d_ui, d_ec, d_uo, d_fc, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }

@@ -89,6 +89,19 @@ __device__ __forceinline__ C<double> prolong_at(const C<T> *ec, int i, int j, in
 
 __device__ __forceinline__ int mirror(int x, int N) { return x < 0 ? -x : (x > N ? 2 * N - x : x); }
 
+// Tile of a workgroup.  Workgroups are dealt to the 8 XCDs of the chip in
+// launch order, round-robin; each XCD gets a contiguous run of tiles (in
+// row-major tile order) so that neighbouring tiles, which read each other's
+// halo cells, share one L2.  A bijection of [0, T) for any T.
+__device__ __forceinline__ void xcd_tile(int &tx, int &ty) {
+    constexpr int NX = 8;
+    const int T = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
+    const int x = bid % NX, base = T / NX, rem = T % NX;
+    const int t = x * base + min(x, rem) + bid / NX;
+    tx = t % gridDim.x;
+    ty = t / gridDim.x;
+}
+
 // ===========================================================================
 // Fused Gauss-Seidel kernels.  A tile of X x Y fine nodes (x0, y0 even) is
 // processed with a halo of RH = 3 held in LDS.  Each thread owns fixed
@@ -138,7 +151,9 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
     if (skip && *skip) return;
     __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TL::X, y0 = blockIdx.y * TL::Y;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * TL::X, y0 = ty * TL::Y;
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     const int N = g.N, M = g.M;
     C<double> fr[2][TL::NS];
@@ -265,7 +280,9 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
     if (skip && *skip) return;
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TL::X, y0 = blockIdx.y * TL::Y;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * TL::X, y0 = ty * TL::Y;
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     C<double> fr[2][TL::NS];
@@ -405,7 +422,9 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
     __shared__ C<double> FS[STAGE ? LW * LW : 1];
     __shared__ C<double> KS[STAGE ? LW * LW : 1];
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TS, y0 = blockIdx.y * TS;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * TS, y0 = ty * TS;
     const int ox = x0 - RH, oy = y0 - RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     for (int b0 = 0; b0 < NL; b0 += CH) {
@@ -451,15 +470,19 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         }
     }
     // row slots of this thread: line ly = 1 + s / T5, column slot t = s % T5;
-    // for colour c the row sits at lx = 1 + ((c - i1 - 2 j) mod 5) + 5 t
-    int sly[NM], sbase[NM];
+    // for colour c the row sits at lx = 1 + ((c + a) mod 5) + 5 t with
+    // a = (-(ox + 1) - 2 j) mod 5 fixed per line (lines outside the domain
+    // get no slot)
+    int sly[NM], sbase[NM], sa[NM];
 #pragma unroll
     for (int m = 0; m < NM; ++m) {
-        int sl = tid + NT * m;
-        sly[m] = (sl < NSLOT) ? 1 + sl / T5 : -1;
-        sbase[m] = 5 * (sl % T5);
+        const int sl = tid + NT * m, ly = 1 + sl / T5, j = oy + ly;
+        sly[m] = (sl < NSLOT && j >= 0 && j <= N) ? ly : -1;
+        sbase[m] = 1 + 5 * (sl % T5);
+        sa[m] = (((-(ox + 1) - 2 * j) % 5) + 5) % 5;
     }
     __syncthreads();
+#pragma unroll
     for (int pass = 0; pass < 5 * S; ++pass) {
         const int c = pass % 5;
         const int lo = 2 * pass + 1, hi = LW - 2 - 2 * pass;   // rows on tile + (RH - 2 pass - 1)
@@ -468,9 +491,10 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
             const int ly = sly[m];
             if (ly < lo || ly > hi) continue;
             const int j = oy + ly;
-            const int lx = 1 + (((c - (ox + 1) - 2 * j) % 5) + 5) % 5 + sbase[m];
+            const int ca = c + sa[m];
+            const int lx = (ca >= 5 ? ca - 5 : ca) + sbase[m];
             const int i = ox + lx;
-            if (lx < lo || lx > hi || i < 0 || j < 0 || i > N || j > N) continue;
+            if (lx < lo || lx > hi || i < 0 || i > N) continue;
             const int l = ly * LW + lx;
             if (STAGE) {
                 const C<double> kc = KS[l];
@@ -531,6 +555,118 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
             }
             fc[(size_t)J * Mc + I] = st_as<T>(cscale(0.0625, sum));
         }
+    }
+}
+
+// ===========================================================================
+// k_kacz_level: the whole level (n <= 63) in one workgroup of LNT threads.
+// u lives in LDS with a ring of zero cells; each thread owns one row slot
+// (line j, column block t) and keeps f and (k, 1/||a_p||^2) of the slot's
+// five cells, one per colour, in registers.  `sweeps` 5-colour sweeps from
+// ui (null: zero) plus P ec (null: none), then u to uo and, when fc != null,
+// fc = R (f - A_{sigb} u) (the restriction of the level's pre-smoothing).
+// No halo is recomputed: every pass updates exactly the rows of its colour.
+// ===========================================================================
+constexpr int LNT = 1024, LMAX = 65;          // threads; largest M = n + 2
+
+template <typename T>
+__global__ __launch_bounds__(LNT) void k_kacz_level(GeoT g, double H, double ih2, const T *__restrict__ k,
+                                                   const C<double> *__restrict__ ktab, double sig, double sigb,
+                                                   int sweeps, const C<T> *__restrict__ f,
+                                                   const C<T> *__restrict__ ui, const C<T> *__restrict__ ec,
+                                                   C<T> *__restrict__ uo, C<T> *__restrict__ fc,
+                                                   const int *skip) {
+    if (skip && *skip) return;
+    constexpr int PW = LMAX + 2;
+    __shared__ C<double> U[PW * PW];          // node (i, j) at (j + 1) * pw + i + 1
+    __shared__ C<double> KS[LMAX * LMAX];     // (k, 1/||a_p||^2); later the residual
+    const int tid = threadIdx.x;
+    const int N = g.N, M = g.M, pw = M + 2, Mc = N / 2 + 1;
+    const int W5 = (M + 4) / 5;
+    // slot of this thread: line j, cells i = 5 t + r (r = 0..4); the colour
+    // of cell r is (i + 2 j) mod 5
+    const int j = tid / W5, t = tid % W5;
+    const bool slot = tid < M * W5;
+    C<double> fr[5];
+#pragma unroll
+    for (int r = 0; r < 5; ++r) fr[r] = ldr<double>(f, (size_t)min(j, N) * M + min(5 * t + r, N));
+    // u: zero ring, ui + P ec inside; the row table
+    for (int q = tid; q < pw * pw; q += LNT) {
+        const int i = q % pw - 1, jq = q / pw - 1;
+        C<double> v = cmk(0.0, 0.0);
+        if (i >= 0 && jq >= 0 && i <= N && jq <= N) {
+            const size_t p = (size_t)jq * M + i;
+            if (ui) v = ldr<double>(ui, p);
+            if (ec) v = cadd(v, prolong_at(ec, i, jq, Mc));
+            C<double> kn;
+            if (ktab) {
+                kn = ktab[p];
+            } else {
+                kn.x = (double)k[p];
+                Row<double> rw = row_at<double>(i, jq, N, H, ih2, kn.x, sig);
+                kn.y = 1.0 / (rw.dre * rw.dre + rw.dim * rw.dim + rw.wl * rw.wl + rw.wr * rw.wr +
+                              rw.wd * rw.wd + rw.wu * rw.wu);
+            }
+            KS[p] = kn;
+        }
+        U[q] = v;
+    }
+    __syncthreads();
+    const int a5 = (((-2 * j) % 5) + 5) % 5;
+    for (int s = 0; s < sweeps; ++s) {
+#pragma unroll 1
+        for (int c = 0; c < 5; ++c) {
+            // the slot's cell of colour c: r = (c - 2 j) mod 5
+            const int r = c + a5 >= 5 ? c + a5 - 5 : c + a5;
+            const int i = 5 * t + r;
+            if (slot && i <= N) {
+                C<double> fp = fr[0];
+#pragma unroll
+                for (int q = 1; q < 5; ++q)
+                    if (q == r) fp = fr[q];
+                const C<double> kp = KS[j * M + i];
+                kacz_row_lds(U, (j + 1) * pw + i + 1, pw, row_at<double>(i, j, N, H, ih2, kp.x, sig), fp, kp.y);
+            }
+            __syncthreads();
+        }
+    }
+    for (int q = tid; q < M * M; q += LNT) {
+        const int i = q % M, jq = q / M;
+        uo[q] = st_as<T>(U[(jq + 1) * pw + i + 1]);
+    }
+    if (!fc) return;
+    // residual with sigma_b at the slot's cells (kept in registers until every
+    // thread has read the table), stored over the table, then full weighting
+    C<double> res[5];
+    if (slot) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int i = 5 * t + r;
+            if (i > N) continue;
+            const int l = (j + 1) * pw + i + 1;
+            Row<double> rw = row_at<double>(i, j, N, H, ih2, KS[j * M + i].x, sigb);
+            res[r] = csub(fr[r], cadd(cmul(cmk(rw.dre, rw.dim), U[l]), offsum_z(rw, U, l, pw)));
+        }
+    }
+    __syncthreads();
+    if (slot) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            if (5 * t + r <= N) KS[j * M + 5 * t + r] = res[r];
+    }
+    __syncthreads();
+    for (int q = tid; q < Mc * Mc; q += LNT) {
+        const int I = q % Mc, J = q / Mc;
+        C<double> sum = cmk(0.0, 0.0);
+        for (int e = -1; e <= 1; ++e) {
+            const int jj = mirror(2 * J + e, N);
+            for (int d = -1; d <= 1; ++d) {
+                const int ii = mirror(2 * I + d, N);
+                const double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
+                sum = cadd(sum, cscale(w, KS[jj * M + ii]));
+            }
+        }
+        fc[q] = st_as<T>(cscale(0.0625, sum));
     }
 }
 
@@ -911,6 +1047,22 @@ void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k,
                     const void *f, const void *ui, const void *ec, void *uo, const int *skip) {
     if (p == P64) kacz_tb_any<double>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip);
     else kacz_tb_any<float>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip);
+}
+
+bool kacz_level_fits(const Geo &g) { return g.M <= LMAX; }
+
+void launch_kacz_level(Prec p, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
+                       double sigb, int sweeps, const void *f, const void *ui, const void *ec, void *uo, void *fc,
+                       const int *skip) {
+    const double ih2 = 1.0 / (g.H * g.H);
+    if (p == P64)
+        k_kacz_level<double><<<1, LNT, 0, s>>>(geo_t(g), g.H, ih2, (const double *)k, (const C<double> *)tab, sig,
+                                               sigb, sweeps, (const C<double> *)f, (const C<double> *)ui,
+                                               (const C<double> *)ec, (C<double> *)uo, (C<double> *)fc, skip);
+    else
+        k_kacz_level<float><<<1, LNT, 0, s>>>(geo_t(g), g.H, ih2, (const float *)k, (const C<double> *)tab, sig,
+                                              sigb, sweeps, (const C<float> *)f, (const C<float> *)ui,
+                                              (const C<float> *)ec, (C<float> *)uo, (C<float> *)fc, skip);
 }
 
 void launch_kacz_table(Prec p, hipStream_t s, const Geo &g, const void *k, double sig, double *tab) {

@@ -24,7 +24,7 @@ struct hmg_ctx {
 };
 
 // How a level above the bottom solver runs its part of the V-cycle.
-enum LevelMode { LM_SIMPLE = 0, LM_GS_FUSED = 1, LM_KACZ_TILED = 2, LM_BOTTOM = 3 };
+enum LevelMode { LM_SIMPLE = 0, LM_GS_FUSED = 1, LM_KACZ_TILED = 2, LM_BOTTOM = 3, LM_KACZ_LEVEL = 4 };
 
 struct Level {
     hmgk::Geo geo;

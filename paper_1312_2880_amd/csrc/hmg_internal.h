@@ -106,6 +106,12 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
                     const void *f, const void *ui, const void *ec, void *uo, const int *skip);
 void launch_kacz_table(Prec p, hipStream_t s, const Geo &g, const void *k, double sig, double *tab);
+// a whole level (n <= 63) in one workgroup: `sweeps` sweeps from ui (null:
+// zero) + P ec (null: none) into uo, then fc = R (f - A_{sigb} uo) if fc
+bool kacz_level_fits(const Geo &g);
+void launch_kacz_level(Prec p, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
+                       double sigb, int sweeps, const void *f, const void *ui, const void *ec, void *uo, void *fc,
+                       const int *skip);
 bool kacz_cfg_resid(int cfg);   // configuration has the fused residual form
 // S sweeps (configuration cfg) from ui (null: zero), then fc = R (f - A_{sigb} u)
 void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab,

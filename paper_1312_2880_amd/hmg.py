@@ -112,6 +112,7 @@ _SIGS = {
     "hmg_op_kacz_tiled_dev": (_i, [P, _i, _d, _i, P, P, P, P, P]),
     "hmg_kacz_tile_config": (_i, [_i, P, P, P]),
     "hmg_op_kacz_down_dev": (_i, [P, _i, _d, _d, _i, P, P, P, P, P]),
+    "hmg_op_kacz_level_dev": (_i, [P, _i, _d, _d, _i, P, P, P, P, P, P]),
     "hmg_solve_history": (_i, [P, _i, P, _i]),
     "hmg_grid_kacz_config": (_i, [P, _i]),
 }
@@ -352,6 +353,12 @@ class Grid:
     def op_kacz_down(self, level, sigma_relax, sigma_resid, config, d_f, d_ui, d_uo, d_fc, stream=None):
         _check(_lib.hmg_op_kacz_down_dev(self._h, level, sigma_relax, sigma_resid, config, _dptr(d_f),
                                          _dptr(d_ui), _dptr(d_uo), _dptr(d_fc), _stream(stream)))
+
+    def op_kacz_level(self, level, sigma_relax, sigma_resid, sweeps, d_f, d_ui, d_ec, d_uo, d_fc,
+                      stream=None):
+        _check(_lib.hmg_op_kacz_level_dev(self._h, level, sigma_relax, sigma_resid, sweeps, _dptr(d_f),
+                                          _dptr(d_ui), _dptr(d_ec), _dptr(d_uo), _dptr(d_fc),
+                                          _stream(stream)))
 
     def op_coarsest(self, d_f, d_u, stream=None):
         _check(_lib.hmg_op_coarsest_dev(self._h, _dptr(d_f), _dptr(d_u), _stream(stream)))

@@ -285,6 +285,45 @@ def test_kaczmarz_down_matches_oracle(ctx, hmg, cfg, start, n):
     assert rel(host(d_fc), want_fc) <= 1e-11
 
 
+@pytest.mark.parametrize("sweeps", [0, 1, 4])
+@pytest.mark.parametrize("start", ["zero", "u", "u+Pe"])
+@pytest.mark.parametrize("n", [15, 31, 63])
+def test_kaczmarz_level_matches_oracle(ctx, hmg, sweeps, start, n):
+    """A whole level in one workgroup: sweeps from u (+ P e), then the
+    restriction of the residual (Sections 4-5)."""
+    say(f"case kacz_level sweeps={sweeps} start={start} n={n}")
+    h = 1.0 / (n + 1)
+    k = rand_k(n, 3 * n + sweeps, 60.0, 150.0)
+    g = hmg.Grid(ctx, h, k, coarsest_n=3)
+    f = inputs.random_field(n, 91)
+    nc = (n - 1) // 2
+    u0 = np.zeros_like(f)
+    d_ui = d_ec = None
+    if start != "zero":
+        u0 = inputs.random_field(n, 92)
+        d_ui = dev(u0)
+    if start == "u+Pe":
+        ec = inputs.random_field(nc, 93)
+        d_ec = dev(ec)
+        u0 = oracle.prolong_add(ec, u0)
+    d_uo = dev(np.zeros_like(f))
+    d_fc = dev(np.zeros((nc + 2, nc + 2), np.complex128))
+    g.op_kacz_level(0, 0.5, 0.0, sweeps, dev(f), d_ui, d_ec, d_uo, d_fc)
+    want = u0
+    for _ in range(sweeps):
+        want = oracle.kacz_5c(h, k, 0.5, f, want)
+    assert rel(host(d_uo), want) <= 1e-12
+    assert rel(host(d_fc), oracle.restrict_fw(oracle.residual(h, k, 0.0, f, want))) <= 1e-11
+
+
+def test_kaczmarz_level_rejects_large_level(ctx, hmg):
+    g = hmg.Grid(ctx, 1 / 128, np.full((129, 129), 30.0))
+    a = dev(np.zeros((129, 129), np.complex128))
+    b = dev(np.zeros((129, 129), np.complex128))
+    with pytest.raises(hmg.HmgError):
+        g.op_kacz_level(0, 0.5, 0.0, 1, a, None, None, b, None)
+
+
 def test_kaczmarz_down_rejects_unstaged_config(ctx, hmg):
     g = hmg.Grid(ctx, 1 / 64, np.full((65, 65), 30.0))
     a = dev(np.zeros((65, 65), np.complex128))
