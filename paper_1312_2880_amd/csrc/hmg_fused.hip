@@ -915,36 +915,53 @@ __global__ __launch_bounds__(BNT) void k_bottom(BotPlan<T> P, const C<TF> *__res
 
 // ===========================================================================
 // k_dense_apply: u = B f for the dense bottom-cycle matrix B (row-major,
-// complex FP64, m <= DMAX).  f is staged in LDS; each wave forms one row's
-// dot product (lanes stride the row, then a fixed-order butterfly sum).
+// complex FP64, m <= DMAX).  One workgroup per row: thread t takes columns
+// t, t + DNT, ... (all of its loads issued together), then a fixed-order
+// wave butterfly and a fixed-order sum over the waves.  f is read straight
+// from memory (every workgroup reads the same m values, which stay in L2).
 // ===========================================================================
-constexpr int DNT = 256, DROWS = DNT / 64, DMAX = 33 * 33;
+constexpr int DNT = 256, DMAX = 33 * 33, DPT = (DMAX + DNT - 1) / DNT;
 
 template <typename TF, typename TU>
 __global__ __launch_bounds__(DNT) void k_dense_apply(const C<double> *__restrict__ B, int m,
                                                      const C<TF> *__restrict__ f, C<TU> *__restrict__ u,
                                                      const int *skip) {
     if (skip && *skip) return;
-    __shared__ C<double> X[DMAX];
-    const int tid = threadIdx.x;
-    for (int q = tid; q < m; q += DNT) X[q] = ldr<double>(f, q);
-    __syncthreads();
-    const int lane = tid & 63, r = blockIdx.x * DROWS + (tid >> 6);
-    if (r >= m) return;
+    __shared__ double part[2][DNT / 64];
+    const int tid = threadIdx.x, r = blockIdx.x;
     const C<double> *row = B + (size_t)r * m;
+    C<double> b[DPT], x[DPT];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        const int c = min(tid + DNT * q, m - 1);
+        b[q] = row[c];
+        x[q] = ldr<double>(f, c);
+    }
     double ax = 0.0, ay = 0.0;
-#pragma unroll 9
-    for (int c = lane; c < m; c += 64) {
-        const C<double> b = row[c], x = X[c];
-        ax += b.x * x.x - b.y * x.y;
-        ay += b.x * x.y + b.y * x.x;
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+        if (tid + DNT * q >= m) continue;
+        ax += b[q].x * x[q].x - b[q].y * x[q].y;
+        ay += b[q].x * x[q].y + b[q].y * x[q].x;
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         ax += __shfl_xor(ax, off, 64);
         ay += __shfl_xor(ay, off, 64);
     }
-    if (lane == 0) u[r] = st_as<TU>(cmk(ax, ay));
+    if ((tid & 63) == 0) {
+        part[0][tid >> 6] = ax;
+        part[1][tid >> 6] = ay;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sx = part[0][0], sy = part[1][0];
+        for (int w = 1; w < DNT / 64; ++w) {
+            sx += part[0][w];
+            sy += part[1][w];
+        }
+        u[r] = st_as<TU>(cmk(sx, sy));
+    }
 }
 
 // ===========================================================================
@@ -1151,7 +1168,7 @@ void launch_bottom_basis(Prec p, hipStream_t s, const BottomDesc &d, double *B) 
 
 void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m, const void *f, void *u,
                         const int *skip) {
-    dim3 grid((m + DROWS - 1) / DROWS);
+    dim3 grid(m);
     const C<double> *b = (const C<double> *)B;
     if (p == P64 || io64) k_dense_apply<double, double><<<grid, DNT, 0, s>>>(b, m, (const C<double> *)f, (C<double> *)u, skip);
     else k_dense_apply<float, float><<<grid, DNT, 0, s>>>(b, m, (const C<float> *)f, (C<float> *)u, skip);
