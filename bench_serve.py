@@ -9,7 +9,8 @@ omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, SL-V
 preconditioner, relative residual 1e-6.  The served form runs the V-cycle in
 complex float under the FP64 Bi-CGSTAB; the baseline runs plain FP64 with at
 most one request in flight.  Latency = completion time - submission time on
-the library's clock.  Prints one JSON line per (form, rate).
+the library's clock.  Prints one JSON line per (form, rate); the served FP64
+form separates the scheduler's effect from the precision's.
 """
 from __future__ import annotations
 
@@ -103,7 +104,8 @@ def main():
     from paper_1312_2880_amd import hmg
     for rate in [float(x) for x in args.rates.split(",")]:
         reqs = make_requests(rate, args.count, args.warmup, args.seed)
-        for form, prec, act in (("served-mixed", hmg.MIXED, args.max_active),
+        for form, prec, act in (("served-fp64", hmg.FP64, args.max_active),
+                                ("served-mixed", hmg.MIXED, args.max_active),
                                 ("serial-fp64", hmg.FP64, 1)):
             out = serve(hmg, reqs, prec, act, args.warmup, args.maxit)
             line = {"metric": "solves/s and p50/p99 latency, Poisson request stream",

@@ -25,6 +25,8 @@
 
 #include "hmg_device.h"
 
+#include <type_traits>
+
 namespace hmgk {
 
 // sum_{q != p} a_pq U_q for an LDS array with row length LW (node p at l),
@@ -427,6 +429,27 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
     const int x0 = tx * TS, y0 = ty * TS;
     const int ox = x0 - RH, oy = y0 - RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
+    // FP64 fields with a row table: f and (k, 1/||a_p||^2) go straight from
+    // memory into LDS (16 B per lane, lane-contiguous destinations within a
+    // wave), bypassing registers.  Cells outside the domain get the clamped
+    // copies, which no row reads.
+    const bool dma = std::is_same<T, double>::value && STAGE && ktab != nullptr;
+    if (dma) {
+        const int wbase = tid & ~63;
+        for (int kk = 0; kk < NL; ++kk) {
+            const int q = tid + NT * kk;
+            if (q < LW * LW) {
+                const int i = min(max(ox + q % LW, 0), N), j = min(max(oy + q / LW, 0), N);
+                const size_t p = (size_t)j * M + i;
+                __builtin_amdgcn_global_load_lds((const void *)(f + p),
+                                                 (__attribute__((address_space(3))) void *)&FS[wbase + NT * kk],
+                                                 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void *)(ktab + p),
+                                                 (__attribute__((address_space(3))) void *)&KS[wbase + NT * kk],
+                                                 16, 0, 0);
+            }
+        }
+    }
     for (int b0 = 0; b0 < NL; b0 += CH) {
         C<double> vu[CH], vf[CH], e[CH][4], vkn[CH];   // vkn: (k, 1/||a_p||^2) or (k, -)
 #pragma unroll
@@ -442,7 +465,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
                 e[s][2] = ldr<double>(ec, (size_t)J1 * Mc + I);
                 e[s][3] = ldr<double>(ec, (size_t)J1 * Mc + I1);
             }
-            if (STAGE) {
+            if (STAGE && !dma) {
                 vf[s] = ldr<double>(f, p);
                 vkn[s] = ktab ? ktab[p] : cmk((double)k[p], 0.0);
             }
@@ -456,7 +479,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
             C<double> v = vu[s];
             if (ec) v = cadd(v, bilinear(e[s][0], e[s][1], e[s][2], e[s][3], i, j));
             U[q] = in ? v : cmk(0.0, 0.0);
-            if (STAGE) {
+            if (STAGE && !dma) {
                 FS[q] = in ? vf[s] : cmk(0.0, 0.0);
                 C<double> kn = vkn[s];
                 if (!ktab) {
@@ -481,6 +504,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         sbase[m] = 1 + 5 * (sl % T5);
         sa[m] = (((-(ox + 1) - 2 * j) % 5) + 5) % 5;
     }
+    if (dma) __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed in LDS
     __syncthreads();
 #pragma unroll
     for (int pass = 0; pass < 5 * S; ++pass) {

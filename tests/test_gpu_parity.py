@@ -13,6 +13,9 @@ GPU solution's residual.
 import math
 import sys
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -51,6 +54,8 @@ def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
 
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
@@ -494,6 +499,103 @@ def test_zero_rhs_and_maxit(ctx, hmg):
     x2, info2 = g2.solve(rtol=1e-6, maxit=1)
     assert info2[0]["status"] == hmg.ERR_NOT_CONVERGED
     assert info2[0]["halfsteps"] == 2
+
+
+def test_multi_rhs_solves_match_oracle(ctx, hmg):
+    """One grid, three right-hand sides (Section 6 per right-hand side):
+    each solve equals the oracle's in count and solution residual."""
+    say("case solve nrhs=3")
+    n, h = 63, 1 / 64
+    k = rand_k(n, 21, 20.0, 40.0)
+    fs = [inputs.random_field(n, 30 + q) for q in range(3)]
+    g = hmg.Grid(ctx, h, k, np.stack(fs), variant=0)
+    x, info = g.solve(rtol=1e-6, maxit=300)
+    og = oracle.Grid(h, k, variant=0)
+    for q in range(3):
+        _, ref = og.bicgstab(fs[q], rtol=1e-6, maxit=300)
+        assert info[q]["status"] == hmg.OK
+        assert abs(info[q]["iters"] - ref["iters"]) <= max(1.0, 0.05 * ref["iters"]), (q, info[q], ref)
+        r = oracle.residual(h, k, 0.0, fs[q], x[q])
+        assert np.linalg.norm(r) / np.linalg.norm(fs[q]) <= 1e-6
+
+
+def test_solve_from_given_x0_matches_oracle(ctx, hmg):
+    """x0 != 0 (Section 6 with r0 = f - L x0)."""
+    say("case solve x0")
+    h, k, f = inputs.workload_const_point(63)
+    x0 = 1e-3 * inputs.random_field(63, 44)
+    g = hmg.Grid(ctx, h, k, variant=0)
+    d_x = dev(x0)
+    info = g.solve_dev(d_x, d_b=dev(f), x0=True, rtol=1e-6, maxit=300, stream=torch.cuda.current_stream())
+    _, ref = oracle.Grid(h, k, variant=0).bicgstab(f, rtol=1e-6, maxit=300, x0=x0)
+    assert info["status"] == hmg.OK
+    assert abs(info["iters"] - ref["iters"]) <= max(1.0, 0.05 * ref["iters"]), (info, ref)
+    r = oracle.residual(h, k, 0.0, f, host(d_x))
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+
+
+def test_tight_tolerance_true_residual(ctx, hmg):
+    """At rtol = 1e-10 the recursive residual drifts from the true one; the
+    solve must still end with a true residual (recomputed by the oracle)
+    within the tolerance, restarting from it where needed."""
+    say("case solve rtol 1e-10")
+    h, k, f = inputs.workload_const_point(63)
+    g = hmg.Grid(ctx, h, k, f, variant=0)
+    x, info = g.solve(rtol=1e-10, maxit=600)
+    assert info[0]["status"] == hmg.OK and info[0]["rel_res_true"] <= 1e-10
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1.5e-10
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_tiny_grids_match_oracle(ctx, hmg, n):
+    """n = 1 and 3 with coarsest_n = 1: V-cycle and solve on the smallest
+    hierarchies (every node a boundary node for n = 1)."""
+    say(f"case tiny n={n}")
+    h = 1.0 / (n + 1)
+    k = rand_k(n, 50 + n, 2.0, 6.0)
+    f = inputs.random_field(n, 60 + n)
+    for variant in (0, 2):
+        g = hmg.Grid(ctx, h, k, f, variant=variant, coarsest_n=1)
+        og = oracle.Grid(h, k, variant=variant, coarsest_n=1)
+        assert rel(g.vcycle(f), og.vcycle(f)) <= 1e-12
+        x, info = g.solve(rtol=1e-10, maxit=50)
+        assert info[0]["status"] == hmg.OK
+        r = oracle.residual(h, k, 0.0, f, x[0])
+        assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-10
+
+
+def test_solve_layered_2047_hyb_fp64(ctx, hmg):
+    """The precision-form problem in FP64 (2047^2, omega = 2 pi 80): the
+    GPU solution's true residual, recomputed by the oracle, meets 1e-6 and
+    the count is within 10 % of the oracle's (tests/golden/oracle_counts.json,
+    written by tests/golden/make_oracle_counts.py)."""
+    say("case solve layered2047 HYB FP64")
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_counts.json")))["layered2047_hyb"]
+    h, k, f = inputs.workload_layered_2047()
+    g = hmg.Grid(ctx, h, k, f, variant=2)
+    x, info = g.solve(rtol=1e-6, maxit=3000)
+    i0 = info[0]
+    say(f"gpu iters {i0['iters']} oracle {ref['iters']}")
+    assert i0["status"] == hmg.OK and i0["rel_res_true"] <= 1e-6
+    assert abs(i0["iters"] - ref["iters"]) <= 0.1 * ref["iters"], (i0, ref)
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+
+
+def test_vcycle_full_size_layered_2047(ctx, hmg):
+    """One V-cycle on the 2047^2 hierarchy (FP64, and the mixed form against
+    the FP64 oracle at float accuracy)."""
+    say("case vcycle layered2047")
+    h, k, f = inputs.workload_layered_2047()
+    og = oracle.Grid(h, k, variant=2)
+    r = inputs.random_field(2047, 8)
+    want = og.vcycle(r)
+    g = hmg.Grid(ctx, h, k, f, variant=2)
+    assert rel(g.vcycle(r), want) <= 1e-11
+    g.close()
+    gm = hmg.Grid(ctx, h, k, f, variant=2, precision=hmg.MIXED)
+    assert rel(gm.vcycle(r), want) <= 1e-4
 
 
 def test_invalid_arguments(ctx, hmg):
