@@ -35,20 +35,23 @@ FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, vendor figure
 KACZ_ROW_FLOPS = 50           # one Kaczmarz row update, real flops
 
 
-def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rbytes: int) -> float:
+def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rbytes: int,
+                      stored_u0: bool = False) -> float:
     """Bytes the method must move per launch, every array touched once
     (c = complex size, r = real size of the level precision; per fine node,
     plus c per coarse node where a coarse field is read or written):
-      gs_down     read f, k; write coarse f                N (c + r) + Nc c
-      gs_up       read f, k, coarse e; write u              N (2c + r) + Nc c
-      kacz_tb     read f, k, u; write u                     N (3c + r)
-    (the pre-smoothed iterate of gs_down is recomputed on chip, never stored)
+      gs_down     read f, k; write coarse f (+ write u0)     N (c + r) + Nc c   (+ N c)
+      gs_up       read f, k, coarse e (+ read u0); write u   N (2c + r) + Nc c  (+ N c)
+      kacz_tb     read f, k, u; write u                      N (3c + r)
+    (FP64 levels store the pre-smoothed iterate u0 for the up kernel;
+    complex-float levels recompute it on chip)
     """
     c, r = cbytes, rbytes
+    extra = nodes * c if stored_u0 else 0
     if kind == "gs_down":
-        return nodes * (c + r) + coarse_nodes * c
+        return nodes * (c + r) + coarse_nodes * c + extra
     if kind == "gs_up":
-        return nodes * (2 * c + r) + coarse_nodes * c
+        return nodes * (2 * c + r) + coarse_nodes * c + extra
     if kind == "kacz_tb":
         return nodes * (3 * c + r)
     raise KeyError(kind)
@@ -99,14 +102,19 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
     n0, nc = plan[0]["n"], plan[1]["n"]
     nodes, cnodes = (n0 + 2) ** 2, (nc + 2) ** 2
     if plan[0]["smoother"] == "GS" and plan[0]["pre"] == 1 and plan[0]["post"] == 1:
-        bufs = [dict(f=field(n0), uo=field(n0), ec=field(nc), fc=field(nc)) for _ in range(sets)]
+        # the kernels as the solve runs them: FP64 levels with n <= 511 store
+        # u0 in the down kernel and read it in the up kernel
+        st_u0 = precision == "fp64" and n0 <= 511
+        bufs = [dict(f=field(n0), u0=field(n0), uo=field(n0), ec=field(nc), fc=field(nc)) for _ in range(sets)]
         sa, sb = plan[0]["sigma_relax"], plan[0]["sigma_resid"]
-        out.append(("gs_down", 0, lambda q, st: g.op_gs_down(0, sa, sb, bufs[q % sets]["f"], None,
+        out.append(("gs_down", 0, lambda q, st: g.op_gs_down(0, sa, sb, bufs[q % sets]["f"],
+                                                             bufs[q % sets]["u0"] if st_u0 else None,
                                                              bufs[q % sets]["fc"], st), 1,
-                    ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb)), None))
+                    ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb, st_u0)), None))
         out.append(("gs_up", 0, lambda q, st: g.op_gs_up(0, sa, bufs[q % sets]["f"], bufs[q % sets]["ec"],
-                                                         bufs[q % sets]["uo"], st), 1,
-                    ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb)), None))
+                                                         bufs[q % sets]["uo"], st,
+                                                         d_u0=bufs[q % sets]["u0"] if st_u0 else None), 1,
+                    ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb, st_u0)), None))
     for l, p in enumerate(plan):
         cfg = g.kacz_config(l)
         if cfg < 0:

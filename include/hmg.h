@@ -254,7 +254,8 @@ hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_u, void *st
  *                fc = R (f - A_{sigma_resid} u0)        (pre-smoothing + restriction);
  *                u0 is written to d_u only when d_u != NULL
  *   gs_up:       uo = one red-black sweep on A_{sigma_relax} starting from
- *                u0 + P ec, with u0 the iterate of gs_down recomputed from f
+ *                u0 + P ec, with u0 read from d_u0 (the field gs_down wrote)
+ *                or, when d_u0 == NULL, recomputed from f
  *                                                        (correction + post-smoothing)
  *   kacz_tiled:  uo = S 5-colour Kaczmarz sweeps starting from ui (NULL: zero)
  *                plus P ec (NULL: none); S and the tile side are those of tile
@@ -263,7 +264,7 @@ hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_u, void *st
 hmg_status hmg_op_gs_down_dev(hmg_grid *g, int level, double sigma_relax, double sigma_resid,
                               const void *d_f, void *d_u, void *d_fc, void *stream);
 hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_relax, const void *d_f,
-                            const void *d_ec, void *d_uo, void *stream);
+                            const void *d_u0, const void *d_ec, void *d_uo, void *stream);
 hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int config, const void *d_f,
                                  const void *d_ui, const void *d_ec, void *d_uo, void *stream);
 /* Kaczmarz pre-smoothing with the restriction (Section 5): uo = S 5-colour

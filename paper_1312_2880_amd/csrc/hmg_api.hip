@@ -736,11 +736,18 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         return dst;
     }
     if (L.mode == LM_GS_FUSED) {
-        launch_gs_down(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, nullptr,
-                       S.f[l + 1], skip);
+        // The up kernel needs the pre-smoothed iterate u0.  On FP64 levels
+        // small enough for their fields to stay in cache (n <= 511) the down
+        // kernel stores it and the up kernel reads it (two dependent phases
+        // fewer); on larger levels the extra HBM traffic costs more than the
+        // phases, and complex-float levels must not round it: both recompute
+        // it from f.
+        void *u0 = (g->prec == P64 && L.geo.n <= 511) ? S.u[l] : nullptr;
+        launch_gs_down(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, u0, S.f[l + 1],
+                       skip);
         const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
         void *dst = out ? out : S.u2[l];
-        launch_gs_up(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, e, dst, skip);
+        launch_gs_up(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip);
         return dst;
     }
     size_t m = (size_t)L.geo.M * L.geo.M;
@@ -938,13 +945,13 @@ extern "C" hmg_status hmg_op_gs_down_dev(hmg_grid *g, int level, double sigma_re
 }
 
 extern "C" hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_relax, const void *d_f,
-                                       const void *d_ec, void *d_uo, void *stream) {
+                                       const void *d_u0, const void *d_ec, void *d_uo, void *stream) {
     hmg_status st = check_level(g, level, true);
     if (st) return st;
-    if (!d_f || !d_ec || !d_uo || d_uo == d_f || d_uo == d_ec)
+    if (!d_f || !d_ec || !d_uo || d_uo == d_f || d_uo == d_ec || d_uo == d_u0)
         return hmg_fail(HMG_ERR_INVALID, "bad fields (the output must not alias an input)");
     const Level &L = g->lev[level];
-    launch_gs_up(g->prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, d_f, d_ec, d_uo, nullptr);
+    launch_gs_up(g->prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, d_f, d_u0, d_ec, d_uo, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }

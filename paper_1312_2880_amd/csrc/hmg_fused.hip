@@ -114,10 +114,10 @@ __device__ __forceinline__ void xcd_tile(int &tx, int &ty) {
 // ===========================================================================
 constexpr int GNT = 256;
 
-template <int DX, int DY>
+template <int DX, int DY, int H = 3>
 struct GsTile {
     static constexpr int X = DX, Y = DY;                // tile (even sides)
-    static constexpr int RH = 3, LW = DX + 2 * RH, LH = DY + 2 * RH;
+    static constexpr int RH = H, LW = DX + 2 * RH, LH = DY + 2 * RH;
     static constexpr int HW = LW / 2;                   // nodes of one colour per line
     static constexpr int NC = HW * LH;                  // nodes of one colour in the region
     static constexpr int NS = (NC + GNT - 1) / GNT;     // owned nodes per colour per thread
@@ -140,6 +140,9 @@ struct GsTile {
 // small one, so that more workgroups share the latency of the dependent phases
 using GsBig = GsTile<64, 20>;
 using GsSmall = GsTile<32, 12>;
+// the up kernel that reads the stored pre-smoothed iterate needs a halo of 2
+using GsBig2 = GsTile<64, 20, 2>;
+using GsSmall2 = GsTile<32, 12, 2>;
 
 // ===========================================================================
 // k_gs_down: one zero-guess red-black sweep (sigma_A), residual (sigma_B) on
@@ -344,6 +347,81 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
         int l = ly * TL::LW + lx;
         U[l] = cadd(U[l], prolong_at(ec, i, j, Mc));
     }
+    __syncthreads();
+    // red on tile + 1
+#pragma unroll
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 0, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+        int l = ly * TL::LW + lx;
+        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
+        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+    }
+    __syncthreads();
+    // black on the tile -> output; red tile nodes -> output
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < TL::NS; ++m) {
+            int lx, ly;
+            bool own = TL::owned(tid, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (!own || !TL::ring(lx, ly, 0) || i > N || j > N) continue;
+            int l = ly * TL::LW + lx;
+            C<double> v = U[l];
+            if (c == 1) {
+                Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
+                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+            }
+            uo[(size_t)j * M + i] = st_as<TU>(v);
+        }
+}
+
+// ===========================================================================
+// k_gs_up_u0: as k_gs_up, but the pre-smoothed iterate u0 is read from
+// memory (written by k_gs_down) instead of recomputed: u = u0 + P ec on
+// tile + 2, red on tile + 1, black on the tile -> uo.  Used where u0 is
+// stored without rounding (FP64 levels); three phases instead of five.
+// ===========================================================================
+template <class TL, typename T, typename TF, typename TU>
+__global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
+                                                  const C<TF> *__restrict__ f, const C<T> *__restrict__ u0,
+                                                  const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
+                                                  const int *skip) {
+    static_assert(TL::RH == 2, "halo of two");
+    if (skip && *skip) return;
+    __shared__ C<double> U[TL::LW * TL::LH];
+    const int tid = threadIdx.x;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * TL::X, y0 = ty * TL::Y;
+    const int ox = x0 - TL::RH, oy = y0 - TL::RH;
+    const int N = g.N, M = g.M, Mc = N / 2 + 1;
+    // f and k of the nodes relaxed here (tile + 1), and u0 + P ec on tile + 2
+    C<double> fr[2][TL::NS];
+    double kr[2][TL::NS];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < TL::NS; ++m) {
+            int lx, ly;
+            bool own = TL::owned(tid, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (!own) continue;
+            const int l = ly * TL::LW + lx;
+            if (i < 0 || j < 0 || i > N || j > N) {
+                U[l] = cmk(0.0, 0.0);
+                continue;
+            }
+            const size_t p = (size_t)j * M + i;
+            if (TL::ring(lx, ly, 1)) {
+                fr[c][m] = ldr<double>(f, p);
+                kr[c][m] = (double)k[p];
+            }
+            U[l] = cadd(ldr<double>(u0, p), prolong_at(ec, i, j, Mc));
+        }
     __syncthreads();
     // red on tile + 1
 #pragma unroll
@@ -1020,8 +1098,20 @@ void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void 
 }
 
 template <typename T, typename TF, typename TU>
-static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const void *f, const void *ec, void *uo,
-                    const int *skip) {
+static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const void *f, const void *u0,
+                    const void *ec, void *uo, const int *skip) {
+    const double ih2 = 1.0 / (g.H * g.H);
+    if (u0) {
+        if (gs_small(g))
+            k_gs_up_u0<GsSmall2, T, TF, TU><<<gs_grid<GsSmall2>(g), GNT, 0, s>>>(
+                geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
+                (C<TU> *)uo, skip);
+        else
+            k_gs_up_u0<GsBig2, T, TF, TU><<<gs_grid<GsBig2>(g), GNT, 0, s>>>(
+                geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
+                (C<TU> *)uo, skip);
+        return;
+    }
     if (gs_small(g))
         k_gs_up<GsSmall, T, TF, TU><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
@@ -1031,10 +1121,10 @@ static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const
 }
 
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
-                  const void *ec, void *uo, const int *skip) {
-    if (p == P64) gs_up_t<double, double, double>(s, g, k, sa, f, ec, uo, skip);
-    else if (io64) gs_up_t<float, double, double>(s, g, k, sa, f, ec, uo, skip);
-    else gs_up_t<float, float, float>(s, g, k, sa, f, ec, uo, skip);
+                  const void *u0, const void *ec, void *uo, const int *skip) {
+    if (p == P64) gs_up_t<double, double, double>(s, g, k, sa, f, u0, ec, uo, skip);
+    else if (io64) gs_up_t<float, double, double>(s, g, k, sa, f, u0, ec, uo, skip);
+    else gs_up_t<float, float, float>(s, g, k, sa, f, u0, ec, uo, skip);
 }
 
 template <typename T, int TS, int S, int NT>

@@ -99,8 +99,10 @@ void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void 
                     const void *f, void *uo, void *fc, const int *skip);
 // uo may be null in launch_gs_down (the smoothed iterate is not stored);
 // launch_gs_up recomputes it from f.
+// u0: the pre-smoothed iterate stored by launch_gs_down, or null (recomputed
+// from f)
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
-                  const void *ec, void *uo, const int *skip);
+                  const void *u0, const void *ec, void *uo, const int *skip);
 // tab: (k_p, 1 / ||a_p||^2) for sigma from launch_kacz_table, or null (the
 // kernel forms them)
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
