@@ -140,6 +140,9 @@ struct GsTile {
 // small one, so that more workgroups share the latency of the dependent phases
 using GsBig = GsTile<64, 20>;
 using GsSmall = GsTile<32, 12>;
+// the down kernel holds fewer values per node and prefers more, shorter
+// tiles on the finest levels
+using GsDownBig = GsTile<64, 12>;
 // the up kernel that reads the stored pre-smoothed iterate needs a halo of 2
 using GsBig2 = GsTile<64, 20, 2>;
 using GsSmall2 = GsTile<32, 12, 2>;
@@ -1086,7 +1089,7 @@ static void gs_down_t(hipStream_t s, const Geo &g, const void *k, double sa, dou
         k_gs_down<GsSmall, T, TF><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
     else
-        k_gs_down<GsBig, T, TF><<<gs_grid<GsBig>(g), GNT, 0, s>>>(
+        k_gs_down<GsDownBig, T, TF><<<gs_grid<GsDownBig>(g), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
 }
 
