@@ -82,7 +82,7 @@ typedef struct {
     int    use_graph;        /* 1: replay each Bi-CGSTAB iteration as a hipGraph  */
     int    one_pass_kernels; /* 1: one kernel launch per colour pass / transfer
                                 (reference schedule); 0: fused LDS-tiled kernels
-                                and the single-workgroup bottom solver (default) */
+                                and the bottom levels as one cycle (default) */
     int    autotune;         /* 1: time the Kaczmarz tile configurations on the
                                 level's shape at grid creation (cached per
                                 process); 0: fixed default                      */

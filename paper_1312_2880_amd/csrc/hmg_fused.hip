@@ -1,27 +1,34 @@
 // hmg_fused.hip -- fused, LDS-tiled V-cycle kernels for gfx950.
 //
 // Each kernel performs the same per-node arithmetic as the one-pass kernels
-// of hmg_kernels.hip, in the same order (FP64 arithmetic on fields stored in
-// the level precision; the LDS tiles hold FP64 values), but stages a tile of
-// the level plus a halo in LDS so that one launch does several dependent
-// steps and every field is read from and written to HBM once:
+// of hmg_kernels.hip (FP64 arithmetic on fields stored in the level
+// precision; the LDS tiles hold FP64 values), but stages a tile of the level
+// plus a halo in LDS so that one launch does several dependent steps and
+// every field is read from and written to HBM about once:
 //
-//   k_gs_down    zero-guess red-black Gauss-Seidel sweep (role A operator),
-//                residual (role B operator) and full weighting to the next
-//                coarser level (Section 5: pre-smoothing and restriction);
-//                the smoothed iterate stays on chip;
-//   k_gs_up      recomputes that iterate (it depends on f only), adds the
-//                bilinear correction from the coarser level and does one
-//                red-black sweep (Section 5: prolongation and post-smoothing);
-//   k_kacz_tb    S sweeps of 5-colour Kaczmarz relaxation on a tile with a
-//                halo of 10 S nodes (each colour pass moves information two
-//                nodes), optionally starting from zero or from u + P e;
-//   k_bottom     one workgroup runs the whole V-cycle on the small levels
-//                (relaxation, transfers and the dense coarsest solve) with
-//                the iterates resident in LDS.
+//   k_gs_down     zero-guess red-black Gauss-Seidel sweep (role A operator),
+//                 residual (role B operator) and full weighting to the next
+//                 coarser level (Section 5: pre-smoothing and restriction);
+//                 the smoothed iterate u0 is stored only when asked for;
+//   k_gs_up       recomputes u0 (it depends on f only), adds the bilinear
+//                 correction from the coarser level and does one red-black
+//                 sweep (Section 5: prolongation and post-smoothing);
+//   k_gs_up_u0    the same from a stored u0 (cache-resident FP64 levels);
+//   k_kacz_tb     S sweeps of 5-colour Kaczmarz relaxation on a tile with a
+//                 halo of 10 S nodes (each colour pass moves information two
+//                 nodes), from zero or from u + P e; its RESID form also
+//                 restricts the residual (the last pre-smoothing launch);
+//   k_kacz_level  a whole level with n <= 63 in one workgroup (a tuner
+//                 candidate);
+//   k_kacz_table  the per-level row table (k, 1/||a_p||^2);
+//   k_bottom      one workgroup runs the whole V-cycle on the small levels
+//                 (relaxation, transfers and the dense coarsest solve) with
+//                 the iterates resident in LDS; its BASIS form builds the
+//                 matrix of that cycle, which k_dense_apply applies.
 //
 // A tile's workgroup writes only its own nodes and reads its halo from the
-// input arrays, which no workgroup of the same launch writes.
+// input arrays, which no workgroup of the same launch writes.  Workgroups
+// take tiles in XCD-contiguous bands (xcd_tile).
 
 #include "hmg_device.h"
 
