@@ -71,12 +71,18 @@ typedef enum { HMG_FP64 = 0, HMG_MIXED = 1 } hmg_precision;
 
 typedef enum { HMG_SM_GS = 0, HMG_SM_KACZ = 1, HMG_SM_LU = 2 } hmg_smoother;
 
+/* Order of the relaxation sweeps.  COLOUR: red-black Gauss-Seidel and
+ * 5-colour Kaczmarz (parallel orders).  LEX: lexicographic order, x fastest,
+ * the order Section 4 analyses; each sweep equals the sequential sweep up to
+ * rounding and runs on the device as a wavefront. */
+typedef enum { HMG_ORDER_COLOUR = 0, HMG_ORDER_LEX = 1 } hmg_order;
+
 typedef struct {
     int    variant;          /* hmg_variant, default HMG_HYB                      */
     int    precision;        /* hmg_precision, default HMG_FP64                   */
     double beta;             /* shift of eq:mh, default 0.5                       */
-    int    nu_pre, nu_post;  /* red-black Gauss-Seidel sweeps, default 1 + 1      */
-    int    kacz_pre, kacz_post; /* 5-colour Kaczmarz sweeps, default 4 + 4        */
+    int    nu_pre, nu_post;  /* Gauss-Seidel sweeps, default 1 + 1               */
+    int    kacz_pre, kacz_post; /* Kaczmarz sweeps, default 4 + 4                 */
     int    kacz_band;        /* 1: Kaczmarz on the kH ~ 1.25 levels (default)     */
     int    coarsest_n;       /* interior size of the dense-LU level, default 7    */
     int    use_graph;        /* 1: replay each Bi-CGSTAB iteration as a hipGraph  */
@@ -92,7 +98,9 @@ typedef struct {
                                 m = (n+2)^2 nodes) at grid creation and apply
                                 it as a matrix-vector product (default);
                                 0: run the bottom levels in one workgroup     */
-    int    reserved[4];
+    int    relax_order;      /* hmg_order, default HMG_ORDER_COLOUR; HMG_ORDER_LEX
+                                runs every level with the one-pass schedule   */
+    int    reserved[3];
 } hmg_opts;
 
 #define HMG_MAX_LEVELS 24
@@ -243,6 +251,13 @@ hmg_status hmg_op_apply_dev(hmg_grid *g, int level, double sigma, const void *d_
 hmg_status hmg_op_smooth_dev(hmg_grid *g, int level, int smoother, double sigma,
                              int sweeps, int zero_guess, const void *d_f, void *d_u,
                              void *stream);
+/* The same sweeps in lexicographic order (hmg_order LEX; Section 4): Gauss-
+ * Seidel (HMG_SM_GS) or Kaczmarz (HMG_SM_KACZ), same arguments and
+ * conventions as hmg_op_smooth_dev.  A sweep is a wavefront over tiles of the
+ * skewed plane c = i + j, one launch per tile diagonal. */
+hmg_status hmg_op_smooth_lex_dev(hmg_grid *g, int level, int smoother, double sigma,
+                                 int sweeps, int zero_guess, const void *d_f, void *d_u,
+                                 void *stream);
 hmg_status hmg_op_restrict_dev(hmg_grid *g, int level, double sigma, const void *d_f,
                                const void *d_u, void *d_fc, void *stream);
 hmg_status hmg_op_prolong_dev(hmg_grid *g, int level, const void *d_ec, void *d_u,

@@ -257,8 +257,13 @@ static void layout(hmg_grid *g, Carver &c) {
 // First level of the bottom solver (-1: none); depends on the level sizes
 // and the options only.  The bottom solver keeps u, f and k of each of its
 // levels in LDS and is used for levels with n <= 31.
+static bool one_pass(const hmg_grid *g) {
+    // the lexicographic sweeps exist only as separate kernels
+    return g->opts.one_pass_kernels || g->opts.relax_order == HMG_ORDER_LEX;
+}
+
 static int find_bottom(const hmg_grid *g) {
-    if (g->opts.one_pass_kernels) return -1;
+    if (one_pass(g)) return -1;
     for (int l = 0; l < g->nlev; ++l) {
         if (g->nlev - l > BOT_MAXL || g->lev[l].geo.n > 31) continue;
         int cs = 0, rs = 0;
@@ -278,7 +283,7 @@ static void plan_paths(hmg_grid *g) {
         g->lev[l].kacz_cfg = 0;
     }
     g->lb = find_bottom(g);
-    if (g->opts.one_pass_kernels) return;
+    if (one_pass(g)) return;
     int top = (g->lb < 0) ? g->nlev - 1 : g->lb;
     for (int l = 0; l < top; ++l) {
         const hmg_plan &pl = g->plan;
@@ -533,6 +538,8 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     if (nrhs < 1 || nrhs > 4096) return hmg_fail(HMG_ERR_INVALID, "nrhs must be in [1, 4096]");
     if (o.variant < 0 || o.variant > 2) return hmg_fail(HMG_ERR_INVALID, "bad variant");
     if (o.precision != HMG_FP64 && o.precision != HMG_MIXED) return hmg_fail(HMG_ERR_INVALID, "bad precision");
+    if (o.relax_order != HMG_ORDER_COLOUR && o.relax_order != HMG_ORDER_LEX)
+        return hmg_fail(HMG_ERR_INVALID, "bad relax_order");
     if (!std::isfinite(o.beta) || o.nu_pre < 0 || o.nu_post < 0 || o.kacz_pre < 0 || o.kacz_post < 0 ||
         o.nu_pre > 64 || o.nu_post > 64 || o.kacz_pre > 64 || o.kacz_post > 64)
         return hmg_fail(HMG_ERR_INVALID, "bad sweep counts or beta");
@@ -691,22 +698,32 @@ extern "C" hmg_status hmg_grid_set_rhs(hmg_grid *g, int rhs, const hmg_c64 *f) {
 //   pre-relax (role A) -> residual (role B) + full weighting -> recurse ->
 //   bilinear correction -> post-relax (role A); dense solve on the coarsest.
 // ---------------------------------------------------------------------------
+// `sweeps` sweeps of smoother sm (HMG_SM_GS / HMG_SM_KACZ) in order `order` on
+// A_sig u = f, in place; zero_guess: the incoming u counts as zero.
+static void sweep(Prec p, int sm, int order, hipStream_t s, const Geo &geo, const void *k, double sig,
+                  const void *f, void *u, int sweeps, bool zero_guess, const int *skip) {
+    const size_t m = (size_t)geo.M * geo.M;
+    if (order == HMG_ORDER_LEX) {
+        if (zero_guess) launch_fill_zero(p, s, u, m, skip);
+        for (int q = 0; q < sweeps; ++q) launch_lex_sweep(p, sm == HMG_SM_KACZ, s, geo, k, sig, f, u, skip);
+    } else if (sm == HMG_SM_GS) {
+        if (sweeps == 0 && zero_guess) launch_fill_zero(p, s, u, m, skip);
+        for (int q = 0; q < sweeps; ++q) {
+            launch_gs_colour(p, s, geo, k, sig, f, u, 0, (zero_guess && q == 0) ? 1 : 0, skip);
+            launch_gs_colour(p, s, geo, k, sig, f, u, 1, 0, skip);
+        }
+    } else {
+        if (zero_guess) launch_fill_zero(p, s, u, m, skip);
+        for (int q = 0; q < sweeps; ++q)
+            for (int c = 0; c < 5; ++c) launch_kacz_colour(p, s, geo, k, sig, f, u, c, skip);
+    }
+}
+
 static void relax(hmg_grid *g, int l, const void *f, void *u, int sweeps, bool zero_guess, hipStream_t s,
                   const int *skip) {
     const Level &L = g->lev[l];
-    double sig = g->plan.sigma_relax[l];
-    if (g->plan.smoother[l] == HMG_SM_GS) {
-        if (sweeps == 0 && zero_guess)
-            launch_fill_zero(g->prec, s, u, (size_t)L.geo.M * L.geo.M, skip);
-        for (int q = 0; q < sweeps; ++q) {
-            launch_gs_colour(g->prec, s, L.geo, L.k, sig, f, u, 0, (zero_guess && q == 0) ? 1 : 0, skip);
-            launch_gs_colour(g->prec, s, L.geo, L.k, sig, f, u, 1, 0, skip);
-        }
-    } else {
-        if (zero_guess) launch_fill_zero(g->prec, s, u, (size_t)L.geo.M * L.geo.M, skip);
-        for (int q = 0; q < sweeps; ++q)
-            for (int c = 0; c < 5; ++c) launch_kacz_colour(g->prec, s, L.geo, L.k, sig, f, u, c, skip);
-    }
+    sweep(g->prec, g->plan.smoother[l], g->opts.relax_order, s, L.geo, L.k, g->plan.sigma_relax[l], f, u, sweeps,
+          zero_guess, skip);
 }
 
 static void vcycle_level(hmg_grid *g, Slot &S, int l, const void *f, void *u, hipStream_t s, const int *skip) {
@@ -811,7 +828,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
 
 // z = B_V r on FP64 device fields r, z (finest level).
 void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip) {
-    if (!g->opts.one_pass_kernels) {
+    if (!one_pass(g)) {
         bool mixed = g->prec == P32;
         if (!mixed || g->lb == 0 || g->lev[0].mode == LM_GS_FUSED) {
             vc_fast(g, S, 0, r, mixed, z, s, skip);
@@ -887,18 +904,21 @@ extern "C" hmg_status hmg_op_smooth_dev(hmg_grid *g, int level, int smoother, do
     if (!d_f || !d_u || sweeps < 0) return hmg_fail(HMG_ERR_INVALID, "bad argument");
     if (smoother != HMG_SM_GS && smoother != HMG_SM_KACZ) return hmg_fail(HMG_ERR_INVALID, "bad smoother");
     const Level &L = g->lev[level];
-    hipStream_t s = pick_stream(g, stream);
-    if (smoother == HMG_SM_GS) {
-        if (sweeps == 0 && zero_guess) launch_fill_zero(g->prec, s, d_u, (size_t)L.geo.M * L.geo.M, nullptr);
-        for (int q = 0; q < sweeps; ++q) {
-            launch_gs_colour(g->prec, s, L.geo, L.k, sigma, d_f, d_u, 0, (zero_guess && q == 0) ? 1 : 0, nullptr);
-            launch_gs_colour(g->prec, s, L.geo, L.k, sigma, d_f, d_u, 1, 0, nullptr);
-        }
-    } else {
-        if (zero_guess) launch_fill_zero(g->prec, s, d_u, (size_t)L.geo.M * L.geo.M, nullptr);
-        for (int q = 0; q < sweeps; ++q)
-            for (int c = 0; c < 5; ++c) launch_kacz_colour(g->prec, s, L.geo, L.k, sigma, d_f, d_u, c, nullptr);
-    }
+    sweep(g->prec, smoother, HMG_ORDER_COLOUR, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, sweeps,
+          zero_guess != 0, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_op_smooth_lex_dev(hmg_grid *g, int level, int smoother, double sigma, int sweeps,
+                                            int zero_guess, const void *d_f, void *d_u, void *stream) {
+    hmg_status st = check_level(g, level, false);
+    if (st) return st;
+    if (!d_f || !d_u || sweeps < 0) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    if (smoother != HMG_SM_GS && smoother != HMG_SM_KACZ) return hmg_fail(HMG_ERR_INVALID, "bad smoother");
+    const Level &L = g->lev[level];
+    sweep(g->prec, smoother, HMG_ORDER_LEX, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, sweeps,
+          zero_guess != 0, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }

@@ -1,0 +1,189 @@
+// hmg_lex.hip -- lexicographic Gauss-Seidel and Kaczmarz sweeps (Section 4:
+// the smoothers are analysed, and run by the paper, in lexicographic order,
+// x fastest).  These give the results of the sequential sweeps, computed as
+// a wavefront; the default schedule's coloured sweeps are the parallel
+// alternative.
+//
+// Order.  A sweep visits the rows (i, j) with j outer and i inner.  In the
+// skewed coordinate c = i + j the 5-point neighbours of (c, j) are (c -+ 1, j)
+// (left, right), (c - 1, j - 1) (down) and (c + 1, j + 1) (up).
+//   Gauss-Seidel reads the new values of left and down and the old values of
+//   right and up: all rows with the same c are independent, and processing
+//   c = 0, 1, 2, ... reproduces the sequential sweep.
+//   Kaczmarz row p changes u on the whole stencil of p, so two rows interact
+//   whenever their stencils meet (Manhattan distance <= 2).  The earlier row
+//   of such a pair always has the smaller t = c + j = i + 2j, and rows with
+//   equal t are at distance >= 3: processing t = 0, 1, 2, ... reproduces the
+//   sequential sweep.
+// Every dependency of row (c, j) points to a row with c' <= c and j' <= j, so
+// rectangular tiles of the skewed plane (TC columns of c by TR rows of j) are
+// processed in diagonal order a + b = 0, 1, 2, ... (tile (a, b)): one launch
+// per diagonal; tiles of one diagonal touch disjoint node sets (their rows
+// are pairwise at distance >= 3) except for two corner halo cells, which the
+// kernel reads but neither uses nor writes back.
+//
+// Kernel.  One 64-lane wave per tile, lane = tile row.  The tile's nodes, f
+// and k plus a one-cell halo ring of u are staged in LDS (rows of the skewed
+// tile are contiguous runs of a grid row in HBM, so the staging loads are
+// coalesced); the wave then steps through the tile's columns (Gauss-Seidel:
+// TC steps, all lanes on column c; Kaczmarz: TC + TR - 1 steps, lane l on
+// column t - l), with a barrier between steps, and writes back what it
+// changed.  Arithmetic is FP64 as in the other kernels; u is rounded to the
+// level precision at every store, as the coloured kernels do.
+
+#include "hmg_device.h"
+
+namespace hmgk {
+
+constexpr int LX_TR = 64;            // rows per tile = lanes
+constexpr int LX_TC = 32;            // skewed columns per tile
+constexpr int LX_UH = LX_TR + 2;     // staged rows of u (halo ring)
+constexpr int LX_UW = LX_TC + 3;     // staged columns of u: TC + 2, padded to an odd 16-byte stride
+constexpr int LX_FW = LX_TC + 1;     // row stride of the staged f and k (odd)
+
+template <typename T>
+__device__ __forceinline__ C<double> lds_c(const C<T> &v) {
+    return cmk((double)v.x, (double)v.y);
+}
+
+template <typename T, bool KACZ>
+__global__ __launch_bounds__(LX_TR) void k_lex(GeoT g, double H, double ih2, const T *__restrict__ k, double sigma,
+                                               const C<T> *__restrict__ f, C<T> *u, int diag, int b_lo,
+                                               const int *skip) {
+    if (skip && *skip) return;
+    __shared__ C<T> U[LX_UH][LX_UW];
+    __shared__ C<T> F[LX_TR][LX_FW];
+    __shared__ T K[LX_TR][LX_FW];
+    const int b = b_lo + (int)blockIdx.x, a = diag - b;
+    const int c0 = a * LX_TC, j0 = b * LX_TR, lane = threadIdx.x;
+
+    // u with the halo ring: cell (jj, cc) holds node (i, j) = (c0 - 1 + cc - j, j0 - 1 + jj),
+    // zero outside the grid (the matching weights of row_at are zero there)
+    for (int q = lane; q < LX_UH * (LX_TC + 2); q += LX_TR) {
+        const int jj = q / (LX_TC + 2), cc = q - jj * (LX_TC + 2);
+        const int j = j0 - 1 + jj, i = c0 - 1 + cc - j;
+        C<T> v = cmk(T(0), T(0));
+        if (j >= 0 && j <= g.N && i >= 0 && i <= g.N) v = u[(size_t)j * g.M + i];
+        U[jj][cc] = v;
+    }
+    for (int q = lane; q < LX_TR * LX_TC; q += LX_TR) {
+        const int jl = q / LX_TC, cl = q - jl * LX_TC;
+        const int j = j0 + jl, i = c0 + cl - j;
+        const bool in = j <= g.N && i >= 0 && i <= g.N;
+        const size_t p = in ? (size_t)j * g.M + i : 0;
+        F[jl][cl] = in ? f[p] : cmk(T(0), T(0));
+        K[jl][cl] = in ? k[p] : T(1);
+    }
+    __syncthreads();
+
+    const int j = j0 + lane, jj = lane + 1;
+    if (!KACZ) {
+        for (int s = 0; s < LX_TC; ++s) {
+            const int i = c0 + s - j, cc = s + 1;
+            if (j <= g.N && i >= 0 && i <= g.N) {
+                Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][s], sigma);
+                // neighbours in the order left, right, down, up
+                C<double> o = cscale(r.wl, lds_c(U[jj][cc - 1]));
+                o = cadd(o, cscale(r.wr, lds_c(U[jj][cc + 1])));
+                o = cadd(o, cscale(r.wd, lds_c(U[jj - 1][cc - 1])));
+                o = cadd(o, cscale(r.wu, lds_c(U[jj + 1][cc + 1])));
+                U[jj][cc] = st_as<T>(cdiv(csub(lds_c(F[lane][s]), o), r.dre, r.dim));
+            }
+            __syncthreads();
+        }
+        for (int q = lane; q < LX_TR * LX_TC; q += LX_TR) {
+            const int jl = q / LX_TC, cl = q - jl * LX_TC;
+            const int jg = j0 + jl, i = c0 + cl - jg;
+            if (jg <= g.N && i >= 0 && i <= g.N) u[(size_t)jg * g.M + i] = U[jl + 1][cl + 1];
+        }
+        return;
+    }
+
+    // Kaczmarz: delta = (f_p - (A u)_p) / ||a_p||^2, u_q += conj(a_pq) delta on the stencil of p
+    for (int s = 0; s < LX_TC + LX_TR - 1; ++s) {
+        const int cl = s - lane, i = c0 + cl - j, cc = cl + 1;
+        if (cl >= 0 && cl < LX_TC && j <= g.N && i >= 0 && i <= g.N) {
+            Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][cl], sigma);
+            const C<double> up = lds_c(U[jj][cc]), ul = lds_c(U[jj][cc - 1]), ur = lds_c(U[jj][cc + 1]);
+            const C<double> ud = lds_c(U[jj - 1][cc - 1]), uu = lds_c(U[jj + 1][cc + 1]);
+            C<double> o = cscale(r.wl, ul);
+            o = cadd(o, cscale(r.wr, ur));
+            o = cadd(o, cscale(r.wd, ud));
+            o = cadd(o, cscale(r.wu, uu));
+            const C<double> res = csub(lds_c(F[lane][cl]), cadd(cmul(cmk(r.dre, r.dim), up), o));
+            const double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+            const C<double> d = cmk(res.x / nrm, res.y / nrm);
+            U[jj][cc] = st_as<T>(cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x)));
+            if (i > 0) U[jj][cc - 1] = st_as<T>(cadd(ul, cscale(r.wl, d)));
+            if (i < g.N) U[jj][cc + 1] = st_as<T>(cadd(ur, cscale(r.wr, d)));
+            if (j > 0) U[jj - 1][cc - 1] = st_as<T>(cadd(ud, cscale(r.wd, d)));
+            if (j < g.N) U[jj + 1][cc + 1] = st_as<T>(cadd(uu, cscale(r.wu, d)));
+        }
+        __syncthreads();
+    }
+    // write back the union of the rows' stencils: the staged rectangle less
+    // the corners (0, TC), (0, TC+1), (TR+1, 0), (TR+1, 1); two of those
+    // belong to the tiles that run concurrently
+    for (int q = lane; q < LX_UH * (LX_TC + 2); q += LX_TR) {
+        const int rj = q / (LX_TC + 2), cc = q - rj * (LX_TC + 2);
+        if ((rj == 0 && cc >= LX_TC) || (rj == LX_UH - 1 && cc <= 1)) continue;
+        const int jg = j0 - 1 + rj, i = c0 - 1 + cc - jg;
+        if (jg >= 0 && jg <= g.N && i >= 0 && i <= g.N) u[(size_t)jg * g.M + i] = U[rj][cc];
+    }
+}
+
+// Tiles of diagonal d that hold at least one node: b in [lo, hi] (lo > hi
+// when none).  Tile (a, b) covers c in [a TC, a TC + TC), j in [b TR, b TR + TR);
+// it holds a node iff its largest i = c - j is >= 0 and its smallest is <= N.
+static void lex_tiles(int N, int d, int NA, int NB, int &lo, int &hi) {
+    lo = 0;
+    hi = -1;
+    bool seen = false;
+    for (int b = (d - NA + 1 > 0 ? d - NA + 1 : 0); b <= (d < NB - 1 ? d : NB - 1); ++b) {
+        const int c0 = (d - b) * LX_TC, j0 = b * LX_TR, j1 = (j0 + LX_TR - 1 < N) ? j0 + LX_TR - 1 : N;
+        if (c0 + LX_TC - 1 - j0 >= 0 && c0 - j1 <= N) {
+            if (!seen) lo = b;
+            seen = true;
+            hi = b;
+        }
+    }
+}
+
+int lex_launches(const Geo &g) {
+    const int NA = (2 * g.N + LX_TC) / LX_TC, NB = (g.N + LX_TR) / LX_TR;
+    int count = 0;
+    for (int d = 0; d < NA + NB - 1; ++d) {
+        int lo, hi;
+        lex_tiles(g.N, d, NA, NB, lo, hi);
+        count += (hi >= lo);
+    }
+    return count;
+}
+
+template <typename T, bool KACZ>
+static void lex_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u,
+                  const int *skip) {
+    const double H = g.H, ih2 = 1.0 / (g.H * g.H);
+    const int NA = (2 * g.N + LX_TC) / LX_TC, NB = (g.N + LX_TR) / LX_TR;
+    const GeoT gt{g.n, g.M, g.N};
+    for (int d = 0; d < NA + NB - 1; ++d) {
+        int lo, hi;
+        lex_tiles(g.N, d, NA, NB, lo, hi);
+        if (hi < lo) continue;
+        k_lex<T, KACZ><<<hi - lo + 1, LX_TR, 0, s>>>(gt, H, ih2, (const T *)k, sigma, (const C<T> *)f, (C<T> *)u,
+                                                     d, lo, skip);
+    }
+}
+
+void launch_lex_sweep(Prec p, int kacz, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f,
+                      void *u, const int *skip) {
+    if (p == P64) {
+        if (kacz) lex_t<double, true>(s, g, k, sigma, f, u, skip);
+        else lex_t<double, false>(s, g, k, sigma, f, u, skip);
+    } else {
+        if (kacz) lex_t<float, true>(s, g, k, sigma, f, u, skip);
+        else lex_t<float, false>(s, g, k, sigma, f, u, skip);
+    }
+}
+
+}  // namespace hmgk

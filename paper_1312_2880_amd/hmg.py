@@ -28,6 +28,7 @@ ERR_BREAKDOWN, PENDING, ERR_TOO_LARGE, ERR_UNKNOWN_TICKET, ERR_CANCELLED = 5, 6,
 SL, HLM, HYB = 0, 1, 2
 FP64, MIXED = 0, 1
 SM_GS, SM_KACZ, SM_LU = 0, 1, 2
+ORDER_COLOUR, ORDER_LEX = 0, 1
 MAX_LEVELS = 24
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED",
                 5: "BREAKDOWN", 6: "PENDING", 7: "TOO_LARGE", 8: "UNKNOWN_TICKET",
@@ -47,7 +48,8 @@ class Opts(ctypes.Structure):
                 ("kacz_post", ctypes.c_int), ("kacz_band", ctypes.c_int),
                 ("coarsest_n", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("one_pass_kernels", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("bottom_dense", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("bottom_dense", ctypes.c_int), ("relax_order", ctypes.c_int),
+                ("reserved", ctypes.c_int * 3)]
 
 
 class Plan(ctypes.Structure):
@@ -104,6 +106,7 @@ _SIGS = {
     "hmg_ctx_clock": (_d, [P]),
     "hmg_op_apply_dev": (_i, [P, _i, _d, P, P, P]),
     "hmg_op_smooth_dev": (_i, [P, _i, _i, _d, _i, _i, P, P, P]),
+    "hmg_op_smooth_lex_dev": (_i, [P, _i, _i, _d, _i, _i, P, P, P]),
     "hmg_op_restrict_dev": (_i, [P, _i, _d, P, P, P, P]),
     "hmg_op_prolong_dev": (_i, [P, _i, P, P, P]),
     "hmg_op_coarsest_dev": (_i, [P, P, P, P]),
@@ -329,6 +332,10 @@ class Grid:
     def op_smooth(self, level, smoother, sigma, sweeps, zero_guess, d_f, d_u, stream=None):
         _check(_lib.hmg_op_smooth_dev(self._h, level, smoother, sigma, sweeps, zero_guess,
                                       _dptr(d_f), _dptr(d_u), _stream(stream)))
+
+    def op_smooth_lex(self, level, smoother, sigma, sweeps, zero_guess, d_f, d_u, stream=None):
+        _check(_lib.hmg_op_smooth_lex_dev(self._h, level, smoother, sigma, sweeps, zero_guess,
+                                          _dptr(d_f), _dptr(d_u), _stream(stream)))
 
     def op_restrict(self, level, sigma, d_f, d_u, d_fc, stream=None):
         _check(_lib.hmg_op_restrict_dev(self._h, level, sigma, _dptr(d_f), _dptr(d_u),

@@ -140,6 +140,53 @@ def test_kaczmarz_5c_matches_oracle(ctx, hmg, n, klo, khi, sigma, zero_guess):
     assert rel(got, want) <= 1e-12, rel(got, want)
 
 
+# Lexicographic sweeps (Section 4 order) run as wavefronts over tiles of 64
+# rows by 32 skewed columns: n = 1 and 7 fit one tile, 127 and 255 span
+# several tiles both ways with ragged last tiles (129 and 257 rows).
+LEX_CASES = [(1, 3.0, 9.0), (7, 3.0, 9.0), (63, 20.0, 60.0), (127, 40.0, 120.0), (255, 60.0, 200.0)]
+
+
+@pytest.mark.parametrize("n,klo,khi", LEX_CASES)
+@pytest.mark.parametrize("smoother", ["GS", "KACZ"])
+@pytest.mark.parametrize("sigma", [0.0, 0.5])
+@pytest.mark.parametrize("zero_guess", [0, 1])
+def test_lexicographic_sweeps_match_oracle(ctx, hmg, n, klo, khi, smoother, sigma, zero_guess):
+    say(f"case lex {smoother} n={n} sigma={sigma} zero_guess={zero_guess}")
+    h = 1.0 / (n + 1)
+    k = rand_k(n, 5 * n + 1, klo, khi)
+    g = hmg.Grid(ctx, h, k, coarsest_n=1 if n < 15 else 7)
+    f = inputs.random_field(n, 27)
+    u0 = np.zeros_like(f) if zero_guess else inputs.random_field(n, 28)
+    d_f, d_u = dev(f), dev(u0 if not zero_guess else inputs.random_field(n, 29))
+    sm = hmg.SM_GS if smoother == "GS" else hmg.SM_KACZ
+    g.op_smooth_lex(0, sm, sigma, 2, zero_guess, d_f, d_u)
+    got = host(d_u)
+    step = oracle.gs_lex if smoother == "GS" else oracle.kacz_lex
+    want = step(h, k, sigma, f, step(h, k, sigma, f, u0))
+    assert rel(got, want) <= 1e-12, rel(got, want)
+
+
+@pytest.mark.parametrize("smoother", ["GS", "KACZ"])
+def test_lexicographic_sweeps_mixed_precision(ctx, hmg, smoother):
+    """Complex-float fields (u rounded at every store, arithmetic in FP64)."""
+    n = 127
+    say(f"case lex mixed {smoother} n={n}")
+    h = 1.0 / (n + 1)
+    k = rand_k(n, 11, 40.0, 120.0)
+    g = hmg.Grid(ctx, h, k, precision=hmg.MIXED)
+    f = inputs.random_field(n, 31)
+    u0 = inputs.random_field(n, 32)
+    d_f = torch.from_numpy(f.astype(np.complex64)).to("cuda")
+    d_u = torch.from_numpy(u0.astype(np.complex64)).to("cuda")
+    sm = hmg.SM_GS if smoother == "GS" else hmg.SM_KACZ
+    g.op_smooth_lex(0, sm, 0.5, 2, 0, d_f, d_u)
+    got = host(d_u).astype(np.complex128)
+    step = oracle.gs_lex if smoother == "GS" else oracle.kacz_lex
+    want = step(h, k, 0.5, f.astype(np.complex64), step(h, k, 0.5, f.astype(np.complex64),
+                                                           u0.astype(np.complex64)))
+    assert rel(got, want) <= 1e-5, rel(got, want)
+
+
 @pytest.mark.parametrize("n,klo,khi", OP_CASES)
 @pytest.mark.parametrize("sigma", [0.0, 0.5])
 def test_residual_full_weighting_matches_oracle(ctx, hmg, n, klo, khi, sigma):
@@ -429,6 +476,51 @@ def test_vcycle_matches_oracle(ctx, hmg, case, schedule):
         got = g.vcycle(r)
         want = og.vcycle(r)
         assert rel(got, want) <= 1e-12, (seed, rel(got, want))
+
+
+@pytest.mark.parametrize("case", vcycle_cases(), ids=lambda c: c[0])
+def test_lexicographic_vcycle_matches_oracle(ctx, hmg, case):
+    """relax_order = LEX: every Gauss-Seidel and Kaczmarz sweep of the cycle in
+    lexicographic order, against the oracle cycle with lexicographic sweeps."""
+    name, h, k, kw = case
+    say(f"case lex vcycle {name}")
+    g = hmg.Grid(ctx, h, k, relax_order=hmg.ORDER_LEX, **kw)
+    og = oracle.Grid(h, k, gs_order=1, kacz_order=1, **kw)
+    n = k.shape[0] - 2
+    r = inputs.random_field(n, 3)
+    got = g.vcycle(r)
+    want = og.vcycle(r)
+    assert rel(got, want) <= 1e-12, rel(got, want)
+    # the colour-ordered cycle is a different (valid) preconditioner
+    assert rel(og.vcycle(r), oracle.Grid(h, k, **kw).vcycle(r)) > 1e-6
+
+
+def test_lexicographic_vcycle_full_size_layered_1023(ctx, hmg):
+    say("case lex vcycle layered1023")
+    h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=2, relax_order=hmg.ORDER_LEX)
+    og = oracle.Grid(h, k, variant=2, gs_order=1, kacz_order=1)
+    r = inputs.random_field(1023, 6)
+    got = g.vcycle(r)
+    want = og.vcycle(r)
+    assert rel(got, want) <= 1e-12, rel(got, want)
+
+
+def test_lexicographic_solve_matches_oracle(ctx, hmg):
+    """SL-V and HYB-V with lexicographic smoothers on the 63^2 point source of
+    Table 1 (k = 40, h = 1/64): counts against the oracle's."""
+    h, k, f = inputs.workload_const_point(63, 40.0)
+    for variant in (0, 2):
+        say(f"case lex solve point63 variant={variant}")
+        g = hmg.Grid(ctx, h, k, f, variant=variant, relax_order=hmg.ORDER_LEX)
+        x, info = g.solve(rtol=1e-7, maxit=300)
+        og = oracle.Grid(h, k, variant=variant, gs_order=1, kacz_order=1)
+        _, ref = og.bicgstab(f, rtol=1e-7, maxit=300, history=True)
+        i0 = info[0]
+        say(f"gpu {i0['iters']} oracle {ref['iters']}")
+        assert i0["status"] == hmg.OK and i0["rel_res_true"] <= 1e-7
+        assert abs(i0["iters"] - ref["iters"]) <= count_margin(ref["iters"]), (i0, ref)
+        np.testing.assert_allclose(g.history(0)[:8], ref["history"][:8], rtol=1e-7)
 
 
 def test_vcycle_full_size_layered_1023(ctx, hmg):
