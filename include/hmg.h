@@ -10,8 +10,11 @@
  * boundary condition closed by central-difference ghost points.
  *
  * Grid and array conventions used by every call:
- *   - n interior nodes per side, n = 2^m - 1; h = 1/(n+1) on the unit square
- *     (any h > 0 is accepted: the domain is then [0, (n+1) h]^2);
+ *   - n interior nodes per side; h = 1/(n+1) on the unit square (any h > 0 is
+ *     accepted: the domain is then [0, (n+1) h]^2).  Coarse levels halve the
+ *     interval count n + 1 until n <= coarsest_n, so n + 1 must stay even
+ *     down to there: n = 2^m - 1 (down to 7 by default), or e.g. n = 79
+ *     (h = 1/80: levels 79, 39, 19, 9, 4);
  *   - every node (i,j), 0 <= i,j <= n+1, is an unknown, node (i,j) sits at
  *     (i h, j h);
  *   - arrays are row-major with x fastest: element (i,j) at j*(n+2) + i,
@@ -84,7 +87,8 @@ typedef struct {
     int    nu_pre, nu_post;  /* Gauss-Seidel sweeps, default 1 + 1               */
     int    kacz_pre, kacz_post; /* Kaczmarz sweeps, default 4 + 4                 */
     int    kacz_band;        /* 1: Kaczmarz on the kH ~ 1.25 levels (default)     */
-    int    coarsest_n;       /* interior size of the dense-LU level, default 7    */
+    int    coarsest_n;       /* in [1, 31]: coarsening stops at the first level
+                                with n <= coarsest_n (dense LU), default 7    */
     int    use_graph;        /* 1: replay each Bi-CGSTAB iteration as a hipGraph  */
     int    one_pass_kernels; /* 1: one kernel launch per colour pass / transfer
                                 (reference schedule); 0: fused LDS-tiled kernels
@@ -143,9 +147,10 @@ const char *hmg_last_error(void);
 /* ---- grid ----------------------------------------------------------------- */
 
 /* Build the hierarchy for one problem (Section 1 problem statement; Section 5
- * V-cycle components): n = 2^m - 1 >= opts->coarsest_n, h > 0, k per node
+ * V-cycle components): n >= opts->coarsest_n with n + 1 even on every level
+ * above the coarsest (see the grid conventions), h > 0, k per node
  * ((n+2)^2 doubles), f: nrhs right-hand sides of (n+2)^2 complex each (NULL:
- * all zero), nrhs >= 1.  Coarse grids halve the interval count down to
+ * all zero), nrhs >= 1.  Coarse grids halve the interval count until n <=
  * coarsest_n, take k by injection and rediscretise the 5-point operator; the
  * coarsest operator is factored by dense LU in FP64 on the host.  opts NULL
  * means the defaults.  All inputs are copied. */

@@ -205,12 +205,6 @@ struct Carver {
     }
 };
 
-static bool valid_n(int n, int nc) {
-    if (n < 1 || n < nc) return false;
-    unsigned v = (unsigned)n + 1;
-    return (v & (v - 1)) == 0;
-}
-
 // Lay out (or size, when c.base is null) every device buffer of the grid.
 static void layout(hmg_grid *g, Carver &c) {
     size_t csz = (g->prec == P64) ? 16 : 8, rsz = (g->prec == P64) ? 8 : 4;
@@ -529,10 +523,12 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     hmg_opts o;
     if (opts) o = *opts;
     else hmg_opts_default(&o);
-    if (o.coarsest_n < 1 || o.coarsest_n > 31 || !valid_n(o.coarsest_n, 1))
-        return hmg_fail(HMG_ERR_INVALID, "coarsest_n must be 2^m - 1 in [1, 31], got %d", o.coarsest_n);
-    if (!valid_n(n, o.coarsest_n))
-        return hmg_fail(HMG_ERR_INVALID, "n must be 2^m - 1 >= coarsest_n (%d), got %d", o.coarsest_n, n);
+    if (o.coarsest_n < 1 || o.coarsest_n > 31)
+        return hmg_fail(HMG_ERR_INVALID, "coarsest_n must be in [1, 31], got %d", o.coarsest_n);
+    if (!valid_hierarchy(n, o.coarsest_n))
+        return hmg_fail(HMG_ERR_INVALID,
+                        "n must be >= coarsest_n (%d) and halve exactly (n + 1 even) down to it, got %d",
+                        o.coarsest_n, n);
     if (!(h > 0.0) || !std::isfinite(h)) return hmg_fail(HMG_ERR_INVALID, "h must be finite and > 0");
     if (!k) return hmg_fail(HMG_ERR_INVALID, "k is required");
     if (nrhs < 1 || nrhs > 4096) return hmg_fail(HMG_ERR_INVALID, "nrhs must be in [1, 4096]");
@@ -559,7 +555,7 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     g->nrhs = nrhs;
     g->prec = (o.precision == HMG_MIXED) ? P32 : P64;
 
-    // hierarchy: halve the interval count down to coarsest_n, k by injection
+    // hierarchy: halve the interval count until n <= coarsest_n, k by injection
     std::vector<std::vector<double>> kl;
     kl.emplace_back(k, k + m0);
     int nl = n;

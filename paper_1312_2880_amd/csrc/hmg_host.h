@@ -16,6 +16,20 @@
 
 struct ServerState;
 
+// Grid sizes the hierarchy accepts.  Each coarser level halves the interval
+// count of the one above (vertex-centred nesting), so every level with
+// n > nc must have an even interval count n + 1; the walk stops at the first
+// level with n <= nc, the coarsest.  n = 2^m - 1 halves down to nc exactly;
+// h = 1/80 (n = 79) gives the levels 79, 39, 19, 9, 4.
+inline bool valid_hierarchy(int n, int nc) {
+    if (n < 1 || nc < 1 || n < nc) return false;
+    for (int l = 0; n > nc; ++l) {
+        if (n % 2 == 0 || l >= HMG_MAX_LEVELS - 1) return false;
+        n = (n - 1) / 2;
+    }
+    return true;
+}
+
 struct hmg_ctx {
     int    device = 0;
     size_t budget = 0;      // bytes of device memory the server may admit

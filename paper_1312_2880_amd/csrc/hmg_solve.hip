@@ -517,9 +517,7 @@ extern "C" hmg_status hmg_submit(hmg_ctx *ctx, const hmg_request *req, uint64_t 
     if (!ctx || !req || !ticket || !req->k) return hmg_fail(HMG_ERR_INVALID, "null argument");
     hmg_status st = check_solve_args(req->rtol, req->maxit);
     if (st) return st;
-    int nc = req->opts.coarsest_n;
-    unsigned v = (unsigned)req->n + 1;
-    if (req->n < 1 || (v & (v - 1)) != 0 || req->n < nc || !(req->h > 0.0))
+    if (!valid_hierarchy(req->n, req->opts.coarsest_n) || !(req->h > 0.0))
         return hmg_fail(HMG_ERR_INVALID, "bad grid size or spacing");
     size_t m0 = (size_t)(req->n + 2) * (req->n + 2);
     Request *q = new Request();

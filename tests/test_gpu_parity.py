@@ -523,6 +523,58 @@ def test_lexicographic_solve_matches_oracle(ctx, hmg):
         np.testing.assert_allclose(g.history(0)[:8], ref["history"][:8], rtol=1e-7)
 
 
+# Grids whose interval count is not a power of two (Table 1: h = 1/80, 1/160,
+# 1/240); the coarsest level is where the halving stops.
+NPOW2_CASES = [(79, 50.0, 9), (79, 50.0, 7), (159, 100.0, 19), (239, 150.0, 29)]
+
+
+@pytest.mark.parametrize("schedule", ["fused", "one_pass"])
+@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("n,kk,nc", NPOW2_CASES)
+def test_vcycle_non_power_of_two_grids(ctx, hmg, n, kk, nc, variant, schedule):
+    say(f"case vcycle n={n} k={kk} coarsest_n={nc} variant={variant} {schedule}")
+    h, k = inputs.grid_h(n), inputs.random_k(n, n, 0.8 * kk, kk)
+    g = hmg.Grid(ctx, h, k, variant=variant, coarsest_n=nc, **SCHEDULES[schedule])
+    og = oracle.Grid(h, k, variant=variant, coarsest_n=nc)
+    assert [p["n"] for p in g.plan()] == [p["n"] for p in og.plan()]
+    assert [p["smoother"] for p in g.plan()] == [p["smoother"] for p in og.plan()]
+    r = inputs.random_field(n, 4)
+    got = g.vcycle(r)
+    want = og.vcycle(r)
+    assert rel(got, want) <= 1e-12, rel(got, want)
+
+
+def _table_cases():
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_table_counts.json")))
+    out = []
+    for row in ref["rows"]:
+        for key, val in row["counts"].items():
+            if key.startswith("HLM") or val["status"] != 0:
+                continue
+            out.append(pytest.param(row, key, val["iters"], ref["rtol"],
+                                    id=f"{row['table']}-k{row['k']}-N{row['N']}-{key}"))
+    return out
+
+
+@pytest.mark.parametrize("row,key,ref_iters,rtol", _table_cases())
+def test_table_counts_match_oracle(ctx, hmg, row, key, ref_iters, rtol):
+    """Section 6.1 model problem (Tables 1 and 2 configurations): the GPU's
+    Bi-CGSTAB count against the oracle's stored count (written by
+    tests/golden/make_table_counts.py), coloured and lexicographic sweeps."""
+    n = row["n"]
+    say(f"case table {row['table']} k={row['k']} N={row['N']} {key}")
+    h, k, f = inputs.grid_h(n), inputs.constant_k(n, float(row["k"])), inputs.centre_source(n)
+    variant = {"SL": hmg.SL, "HY": hmg.HYB}[key[:2]]
+    order = hmg.ORDER_LEX if key.endswith("-lex") else hmg.ORDER_COLOUR
+    g = hmg.Grid(ctx, h, k, f, variant=variant, coarsest_n=row["coarsest_n"], relax_order=order)
+    assert [p["n"] for p in g.plan()] == row["levels"]
+    x, info = g.solve(rtol=rtol, maxit=400)
+    i0 = info[0]
+    say(f"gpu {i0['iters']} oracle {ref_iters}")
+    assert i0["status"] == hmg.OK and i0["rel_res_true"] <= rtol
+    assert abs(i0["iters"] - ref_iters) <= count_margin(ref_iters), (i0["iters"], ref_iters)
+
+
 def test_vcycle_full_size_layered_1023(ctx, hmg):
     """The 1023^2 layered-medium hierarchy (8 levels, Kaczmarz levels
     included), as the benchmark runs it."""
@@ -735,7 +787,13 @@ def test_vcycle_full_size_layered_2047(ctx, hmg):
 def test_invalid_arguments(ctx, hmg):
     k = np.full((64, 64), 5.0)
     with pytest.raises(hmg.HmgError):
-        hmg.Grid(ctx, 1 / 63, k)                       # n = 62 is not 2^m - 1
+        hmg.Grid(ctx, 1 / 63, k)                       # n = 62: 63 intervals do not halve
+    k = np.full((81, 81), 5.0)
+    with pytest.raises(hmg.HmgError):
+        hmg.Grid(ctx, 1 / 80, k, coarsest_n=3)         # 79 -> 39 -> 19 -> 9 -> 4: 5 intervals
+    assert [p["n"] for p in hmg.Grid(ctx, 1 / 80, k).plan()] == [79, 39, 19, 9, 4]
+    with pytest.raises(hmg.HmgError):
+        hmg.Grid(ctx, 1 / 80, k, coarsest_n=32)        # coarsest_n above 31
     k = np.full((65, 65), 5.0)
     k[3, 3] = 0.0
     with pytest.raises(hmg.HmgError):
