@@ -2,6 +2,10 @@
 Helmholtz problem (HYB-V preconditioner, FP64) on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+                    [--variant hyb|sl] [--order colour|lex]
+
+(--order lex runs every relaxation in lexicographic order, the sweeps as
+wavefronts; the timed kernels are then one sweep per level.)
 
 One step is one full solve to relative residual 1e-6 from x0 = 0, with k, f
 and the hierarchy already resident in device memory.  Prints one JSON line
@@ -32,7 +36,8 @@ def kernel_source_hash() -> str:
 
 
 FP64_PEAK_TFLOPS = 78.6       # MI355X FP64 vector, vendor figure
-KACZ_ROW_FLOPS = 50           # one Kaczmarz row update, real flops (DESIGN.md section 6)
+KACZ_ROW_FLOPS = 50           # one Kaczmarz row update, real flops
+GS_NODE_FLOPS = 28            # one Gauss-Seidel node update, real flops
 
 
 def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rbytes: int,
@@ -86,7 +91,28 @@ def graph_time(torch, stream, fn, count, reps=3):
     return best
 
 
-def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
+def lex_cases(g, plan, field, cb, rb):
+    """Lexicographic sweeps (one call = one sweep = one launch per tile
+    diagonal) on every relaxation level: (name, level, sweep(q), sweeps per
+    V-cycle, roofline model, None)."""
+    from paper_1312_2880_amd import hmg
+    out = []
+    for l, p in enumerate(plan):
+        if p["smoother"] == "LU":
+            continue
+        n, kacz = p["n"], p["smoother"] == "KACZ"
+        kb = [dict(f=field(n), u=field(n)) for _ in range(2)]
+        sm, sig = (hmg.SM_KACZ if kacz else hmg.SM_GS), p["sigma_relax"]
+        flops = (KACZ_ROW_FLOPS if kacz else GS_NODE_FLOPS) * (n + 2) ** 2
+        out.append(("lex_kacz" if kacz else "lex_gs", l,
+                    lambda q, st, l=l, sm=sm, sig=sig, kb=kb: g.op_smooth_lex(
+                        l, sm, sig, 1, 0, kb[q % 2]["f"], kb[q % 2]["u"], st),
+                    p["pre"] + p["post"],
+                    ("alu", flops, algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb)), None))
+    return out
+
+
+def kernel_cases(torch, g, plan, precision, sets=24, fixed=None, lex=False):
     """The V-cycle kernels timed by the benchmark, as closures over device
     buffers shaped like the solve's: (name, level, launch(q), launches per
     V-cycle, roofline model).  The finest-level Gauss-Seidel kernels cycle
@@ -98,6 +124,8 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None):
     def field(n):
         return torch.randn((n + 2, n + 2), dtype=cdt, device="cuda", generator=gen)
 
+    if lex:
+        return lex_cases(g, plan, field, cb, rb)
     out = []
     n0, nc = plan[0]["n"], plan[1]["n"]
     nodes, cnodes = (n0 + 2) ** 2, (nc + 2) ** 2
@@ -159,14 +187,14 @@ def roofline_of(model, ms):
             "hbm_equiv_gbs": round(model[2] / (ms * 1e-3) / 1e9, 1)}
 
 
-def time_kernels(torch, g, plan, precision, only=None, fixed=None):
+def time_kernels(torch, g, plan, precision, only=None, fixed=None, lex=False):
     stream = torch.cuda.Stream()
     res = []
-    for name, level, fn, per_vc, model, cfg in kernel_cases(torch, g, plan, precision, fixed=fixed):
+    for name, level, fn, per_vc, model, cfg in kernel_cases(torch, g, plan, precision, fixed=fixed, lex=lex):
         key = f"{name}@{plan[level]['n']}"
         if only and key != only:
             continue
-        ms = graph_time(torch, stream, lambda q: fn(q, stream), 48)
+        ms = graph_time(torch, stream, lambda q: fn(q, stream), 8 if lex else 48)
         res.append(dict(key=key, name=name, level=level, ms=ms, per_vcycle=per_vc, model=model, cfg=cfg))
     torch.cuda.synchronize()
     return res
@@ -175,11 +203,10 @@ def time_kernels(torch, g, plan, precision, only=None, fixed=None):
 COPY_BYTES = 512 << 20
 
 
-def traffic_probe(torch, g, plan, precision, which, fixed):
-    """Launches kernel `which` (e.g. "kacz_tb@127") 48 times as the timing
-    does, then copies COPY_BYTES device to device three times (the counter
-    reference)."""
-    kt = time_kernels(torch, g, plan, precision, only=which, fixed=fixed)
+def traffic_probe(torch, g, plan, precision, which, fixed, lex=False):
+    """Launches kernel `which` (e.g. "kacz_tb@127") as the timing does, then
+    copies COPY_BYTES device to device three times (the counter reference)."""
+    kt = time_kernels(torch, g, plan, precision, only=which, fixed=fixed, lex=lex)
     if not kt:
         raise SystemExit(f"no kernel {which}")
     src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -191,13 +218,14 @@ def traffic_probe(torch, g, plan, precision, which, fixed):
                       "kernel_ms": round(kt[0]["ms"], 5)}), flush=True)
 
 
-def cpu_baseline(h, k, f, variant, budget_s=10.0, max_solves=3):
+def cpu_baseline(h, k, f, variant, budget_s=10.0, max_solves=3, lex=False):
     """The FP64 oracle on the host cores, on the same problem: full solves
     until about `budget_s` seconds have passed (at most `max_solves`); the
     rate is solves per second of wall time."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    og = oracle.Grid(h, k, variant=variant)
+    order = 1 if lex else 0
+    og = oracle.Grid(h, k, variant=variant, gs_order=order, kacz_order=order)
     t0 = time.perf_counter()
     done, iters = 0, []
     while done < max_solves and (done == 0 or time.perf_counter() - t0 < budget_s):
@@ -225,6 +253,11 @@ def main():
     ap.add_argument("--traffic-probe", default=None, metavar="KERNEL@N",
                     help="only launch this kernel (e.g. kacz_tb@127) as the timing does, then "
                          "a plain copy of known size, for the FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--variant", choices=["hyb", "sl"], default="hyb",
+                    help="preconditioner (HYB-V: the benchmark; SL-V)")
+    ap.add_argument("--order", choices=["colour", "lex"], default="colour",
+                    help="relaxation order: coloured sweeps (the benchmark) or the lexicographic "
+                         "sweeps of Section 4 (wavefronts, one-pass schedule)")
     ap.add_argument("--kacz-configs", default=None, metavar="C,C,...",
                     help="tile configuration per level for the tiled Kaczmarz levels (-1 elsewhere) "
                          "instead of tuning; counter runs pass the configurations the timed run "
@@ -248,10 +281,13 @@ def main():
     fixed = None
     if args.kacz_configs:
         fixed = [int(c) for c in args.kacz_configs.split(",")]
-    g = hmg.Grid(ctx, h, k, f, variant=hmg.HYB, precision=prec, autotune=0 if fixed else 1)
+    lex = args.order == "lex"
+    variant = hmg.HYB if args.variant == "hyb" else hmg.SL
+    g = hmg.Grid(ctx, h, k, f, variant=variant, precision=prec, autotune=0 if fixed else 1,
+                 relax_order=hmg.ORDER_LEX if lex else hmg.ORDER_COLOUR)
     plan = g.plan()
     if args.traffic_probe:
-        traffic_probe(torch, g, plan, args.precision, args.traffic_probe, fixed)
+        traffic_probe(torch, g, plan, args.precision, args.traffic_probe, fixed, lex)
         g.close()
         ctx.close()
         return
@@ -274,7 +310,7 @@ def main():
 
     # the V-cycle kernels: per-launch time from graph replays, share of the
     # solve from launches per iteration (two V-cycles per Bi-CGSTAB iteration)
-    kt = time_kernels(torch, g, plan, args.precision)
+    kt = time_kernels(torch, g, plan, args.precision, lex=lex)
     mean_iters = sum(i["iters"] for i in infos[args.warmup:]) / args.steps
     it_ms = 1e3 * dt / args.steps / max(mean_iters, 0.5)
     for k_ in kt:
@@ -299,7 +335,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(h, k, f, 2)
+        cpu = cpu_baseline(h, k, f, variant, lex=lex)
         cpu = {k_: (round(v, 5) if isinstance(v, float) else v) for k_, v in cpu.items()}
 
     line = {
@@ -316,7 +352,8 @@ def main():
         "dtype": "c128" if args.precision == "fp64" else "c64/c128",
         "data": "synthetic",
         "config": {"workload": (f"layered-medium Helmholtz {n}x{n}, omega = 2 pi {40 * (n + 1) // 1024}, "
-                                "HYB-V preconditioned Bi-CGSTAB to 1e-6, seed 2"),
+                                f"{args.variant.upper()}-V preconditioned Bi-CGSTAB to 1e-6, seed 2"
+                                + (", lexicographic sweeps" if lex else "")),
                    "n": n, "precision": args.precision,
                    "iters": last["iters"], "mean_iters": mean_iters, "rel_res_true": last["rel_res_true"],
                    "all_converged": ok,

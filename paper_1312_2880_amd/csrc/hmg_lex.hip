@@ -22,24 +22,38 @@
 // are pairwise at distance >= 3) except for two corner halo cells, which the
 // kernel reads but neither uses nor writes back.
 //
-// Kernel.  One 64-lane wave per tile, lane = tile row.  The tile's nodes, f
-// and k plus a one-cell halo ring of u are staged in LDS (rows of the skewed
-// tile are contiguous runs of a grid row in HBM, so the staging loads are
-// coalesced); the wave then steps through the tile's columns (Gauss-Seidel:
-// TC steps, all lanes on column c; Kaczmarz: TC + TR - 1 steps, lane l on
-// column t - l), with a barrier between steps, and writes back what it
-// changed.  Arithmetic is FP64 as in the other kernels; u is rounded to the
-// level precision at every store, as the coloured kernels do.
+// Kernel.  One tile per workgroup of four waves.  The tile's nodes, f and k
+// plus a one-cell halo ring of u are staged in LDS by all four waves, every
+// thread issuing all of its loads before its first LDS store (rows of the
+// skewed tile are contiguous runs of a grid row in HBM, so the loads are
+// coalesced).  The first wave then steps through the tile, lane = tile row
+// (Gauss-Seidel: TC steps, all lanes on column c; Kaczmarz: TC + TR - 1
+// steps, lane l on column t - l), and all four waves write back what changed.  Arithmetic is FP64 as in the other kernels;
+// u is rounded to the level precision at every store, as the coloured
+// kernels do.
 
 #include "hmg_device.h"
 
 namespace hmgk {
 
-constexpr int LX_TR = 64;            // rows per tile = lanes
+constexpr int LX_TR = 64;            // rows per tile = lanes of the computing wave
 constexpr int LX_TC = 32;            // skewed columns per tile
+constexpr int LX_NT = 256;           // threads per workgroup (staging and write-back)
 constexpr int LX_UH = LX_TR + 2;     // staged rows of u (halo ring)
 constexpr int LX_UW = LX_TC + 3;     // staged columns of u: TC + 2, padded to an odd 16-byte stride
 constexpr int LX_FW = LX_TC + 1;     // row stride of the staged f and k (odd)
+constexpr int LX_UCELLS = LX_UH * (LX_TC + 2);
+constexpr int LX_UPER = (LX_UCELLS + LX_NT - 1) / LX_NT;   // u cells per thread
+constexpr int LX_FPER = LX_TR * LX_TC / LX_NT;             // f and k cells per thread
+static_assert(LX_TR * LX_TC % LX_NT == 0, "f and k cells divide over the threads");
+
+// End of one wavefront step: order this step's LDS stores before the next
+// step's LDS loads of other lanes of the same wave.
+__device__ __forceinline__ void wave_step() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T>
 __device__ __forceinline__ C<double> lds_c(const C<T> &v) {
@@ -47,7 +61,7 @@ __device__ __forceinline__ C<double> lds_c(const C<T> &v) {
 }
 
 template <typename T, bool KACZ>
-__global__ __launch_bounds__(LX_TR) void k_lex(GeoT g, double H, double ih2, const T *__restrict__ k, double sigma,
+__global__ __launch_bounds__(LX_NT) void k_lex(GeoT g, double H, double ih2, const T *__restrict__ k, double sigma,
                                                const C<T> *__restrict__ f, C<T> *u, int diag, int b_lo,
                                                const int *skip) {
     if (skip && *skip) return;
@@ -55,76 +69,103 @@ __global__ __launch_bounds__(LX_TR) void k_lex(GeoT g, double H, double ih2, con
     __shared__ C<T> F[LX_TR][LX_FW];
     __shared__ T K[LX_TR][LX_FW];
     const int b = b_lo + (int)blockIdx.x, a = diag - b;
-    const int c0 = a * LX_TC, j0 = b * LX_TR, lane = threadIdx.x;
+    const int c0 = a * LX_TC, j0 = b * LX_TR, tid = threadIdx.x;
 
     // u with the halo ring: cell (jj, cc) holds node (i, j) = (c0 - 1 + cc - j, j0 - 1 + jj),
-    // zero outside the grid (the matching weights of row_at are zero there)
-    for (int q = lane; q < LX_UH * (LX_TC + 2); q += LX_TR) {
-        const int jj = q / (LX_TC + 2), cc = q - jj * (LX_TC + 2);
+    // zero outside the grid (the matching weights of row_at are zero there).
+    // All loads first, then the LDS stores.
+    C<T> uv[LX_UPER], fv[LX_FPER];
+    T kv[LX_FPER];
+#pragma unroll
+    for (int t = 0; t < LX_UPER; ++t) {
+        const int q = t * LX_NT + tid, jj = q / (LX_TC + 2), cc = q - jj * (LX_TC + 2);
         const int j = j0 - 1 + jj, i = c0 - 1 + cc - j;
-        C<T> v = cmk(T(0), T(0));
-        if (j >= 0 && j <= g.N && i >= 0 && i <= g.N) v = u[(size_t)j * g.M + i];
-        U[jj][cc] = v;
+        uv[t] = (q < LX_UCELLS && j >= 0 && j <= g.N && i >= 0 && i <= g.N) ? u[(size_t)j * g.M + i]
+                                                                          : cmk(T(0), T(0));
     }
-    for (int q = lane; q < LX_TR * LX_TC; q += LX_TR) {
-        const int jl = q / LX_TC, cl = q - jl * LX_TC;
+#pragma unroll
+    for (int t = 0; t < LX_FPER; ++t) {
+        const int q = t * LX_NT + tid, jl = q / LX_TC, cl = q - jl * LX_TC;
         const int j = j0 + jl, i = c0 + cl - j;
         const bool in = j <= g.N && i >= 0 && i <= g.N;
         const size_t p = in ? (size_t)j * g.M + i : 0;
-        F[jl][cl] = in ? f[p] : cmk(T(0), T(0));
-        K[jl][cl] = in ? k[p] : T(1);
+        fv[t] = in ? f[p] : cmk(T(0), T(0));
+        kv[t] = in ? k[p] : T(1);
+    }
+#pragma unroll
+    for (int t = 0; t < LX_UPER; ++t) {
+        const int q = t * LX_NT + tid, jj = q / (LX_TC + 2), cc = q - jj * (LX_TC + 2);
+        if (q < LX_UCELLS) U[jj][cc] = uv[t];
+    }
+#pragma unroll
+    for (int t = 0; t < LX_FPER; ++t) {
+        const int q = t * LX_NT + tid, jl = q / LX_TC, cl = q - jl * LX_TC;
+        F[jl][cl] = fv[t];
+        K[jl][cl] = kv[t];
     }
     __syncthreads();
 
-    const int j = j0 + lane, jj = lane + 1;
-    if (!KACZ) {
-        for (int s = 0; s < LX_TC; ++s) {
-            const int i = c0 + s - j, cc = s + 1;
-            if (j <= g.N && i >= 0 && i <= g.N) {
-                Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][s], sigma);
-                // neighbours in the order left, right, down, up
-                C<double> o = cscale(r.wl, lds_c(U[jj][cc - 1]));
-                o = cadd(o, cscale(r.wr, lds_c(U[jj][cc + 1])));
-                o = cadd(o, cscale(r.wd, lds_c(U[jj - 1][cc - 1])));
-                o = cadd(o, cscale(r.wu, lds_c(U[jj + 1][cc + 1])));
-                U[jj][cc] = st_as<T>(cdiv(csub(lds_c(F[lane][s]), o), r.dre, r.dim));
+    // Only the first wave computes.  Between steps its lanes exchange values
+    // through LDS; a wave's LDS operations complete in issue order, so
+    // wavefront-scope fences (which keep the compiler from moving LDS accesses
+    // across them) order each step's stores before the next step's loads.
+    // The other waves wait at the barrier that follows.
+    if (tid < LX_TR) {
+        const int lane = tid, j = j0 + lane, jj = lane + 1;
+        if (!KACZ) {
+            for (int s = 0; s < LX_TC; ++s) {
+                const int i = c0 + s - j, cc = s + 1;
+                if (j <= g.N && i >= 0 && i <= g.N) {
+                    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][s], sigma);
+                    // neighbours in the order left, right, down, up
+                    C<double> o = cscale(r.wl, lds_c(U[jj][cc - 1]));
+                    o = cadd(o, cscale(r.wr, lds_c(U[jj][cc + 1])));
+                    o = cadd(o, cscale(r.wd, lds_c(U[jj - 1][cc - 1])));
+                    o = cadd(o, cscale(r.wu, lds_c(U[jj + 1][cc + 1])));
+                    U[jj][cc] = st_as<T>(cdiv(csub(lds_c(F[lane][s]), o), r.dre, r.dim));
+                }
+                wave_step();
             }
-            __syncthreads();
+        } else {
+            // delta = (f_p - (A u)_p) / ||a_p||^2, u_q += conj(a_pq) delta on the stencil of p
+            for (int s = 0; s < LX_TC + LX_TR - 1; ++s) {
+                const int cl = s - lane, i = c0 + cl - j, cc = cl + 1;
+                if (cl >= 0 && cl < LX_TC && j <= g.N && i >= 0 && i <= g.N) {
+                    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][cl], sigma);
+                    const C<double> up = lds_c(U[jj][cc]), ul = lds_c(U[jj][cc - 1]), ur = lds_c(U[jj][cc + 1]);
+                    const C<double> ud = lds_c(U[jj - 1][cc - 1]), uu = lds_c(U[jj + 1][cc + 1]);
+                    C<double> o = cscale(r.wl, ul);
+                    o = cadd(o, cscale(r.wr, ur));
+                    o = cadd(o, cscale(r.wd, ud));
+                    o = cadd(o, cscale(r.wu, uu));
+                    const C<double> res = csub(lds_c(F[lane][cl]), cadd(cmul(cmk(r.dre, r.dim), up), o));
+                    const double nrm =
+                        r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
+                    const C<double> d = cmk(res.x / nrm, res.y / nrm);
+                    U[jj][cc] = st_as<T>(cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x)));
+                    if (i > 0) U[jj][cc - 1] = st_as<T>(cadd(ul, cscale(r.wl, d)));
+                    if (i < g.N) U[jj][cc + 1] = st_as<T>(cadd(ur, cscale(r.wr, d)));
+                    if (j > 0) U[jj - 1][cc - 1] = st_as<T>(cadd(ud, cscale(r.wd, d)));
+                    if (j < g.N) U[jj + 1][cc + 1] = st_as<T>(cadd(uu, cscale(r.wu, d)));
+                }
+                wave_step();
+            }
         }
-        for (int q = lane; q < LX_TR * LX_TC; q += LX_TR) {
+    }
+    __syncthreads();
+
+    if (!KACZ) {
+        for (int q = tid; q < LX_TR * LX_TC; q += LX_NT) {
             const int jl = q / LX_TC, cl = q - jl * LX_TC;
             const int jg = j0 + jl, i = c0 + cl - jg;
             if (jg <= g.N && i >= 0 && i <= g.N) u[(size_t)jg * g.M + i] = U[jl + 1][cl + 1];
         }
         return;
     }
-
-    // Kaczmarz: delta = (f_p - (A u)_p) / ||a_p||^2, u_q += conj(a_pq) delta on the stencil of p
-    for (int s = 0; s < LX_TC + LX_TR - 1; ++s) {
-        const int cl = s - lane, i = c0 + cl - j, cc = cl + 1;
-        if (cl >= 0 && cl < LX_TC && j <= g.N && i >= 0 && i <= g.N) {
-            Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][cl], sigma);
-            const C<double> up = lds_c(U[jj][cc]), ul = lds_c(U[jj][cc - 1]), ur = lds_c(U[jj][cc + 1]);
-            const C<double> ud = lds_c(U[jj - 1][cc - 1]), uu = lds_c(U[jj + 1][cc + 1]);
-            C<double> o = cscale(r.wl, ul);
-            o = cadd(o, cscale(r.wr, ur));
-            o = cadd(o, cscale(r.wd, ud));
-            o = cadd(o, cscale(r.wu, uu));
-            const C<double> res = csub(lds_c(F[lane][cl]), cadd(cmul(cmk(r.dre, r.dim), up), o));
-            const double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
-            const C<double> d = cmk(res.x / nrm, res.y / nrm);
-            U[jj][cc] = st_as<T>(cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x)));
-            if (i > 0) U[jj][cc - 1] = st_as<T>(cadd(ul, cscale(r.wl, d)));
-            if (i < g.N) U[jj][cc + 1] = st_as<T>(cadd(ur, cscale(r.wr, d)));
-            if (j > 0) U[jj - 1][cc - 1] = st_as<T>(cadd(ud, cscale(r.wd, d)));
-            if (j < g.N) U[jj + 1][cc + 1] = st_as<T>(cadd(uu, cscale(r.wu, d)));
-        }
-        __syncthreads();
-    }
-    // write back the union of the rows' stencils: the staged rectangle less
-    // the corners (0, TC), (0, TC+1), (TR+1, 0), (TR+1, 1); two of those
-    // belong to the tiles that run concurrently
-    for (int q = lane; q < LX_UH * (LX_TC + 2); q += LX_TR) {
+    // Kaczmarz: write back the union of the rows' stencils: the staged
+    // rectangle less the corners (0, TC), (0, TC+1), (TR+1, 0), (TR+1, 1); two
+    // of those belong to the tiles that run concurrently
+    for (int q = tid; q < LX_UCELLS; q += LX_NT) {
         const int rj = q / (LX_TC + 2), cc = q - rj * (LX_TC + 2);
         if ((rj == 0 && cc >= LX_TC) || (rj == LX_UH - 1 && cc <= 1)) continue;
         const int jg = j0 - 1 + rj, i = c0 - 1 + cc - jg;
@@ -170,7 +211,7 @@ static void lex_t(hipStream_t s, const Geo &g, const void *k, double sigma, cons
         int lo, hi;
         lex_tiles(g.N, d, NA, NB, lo, hi);
         if (hi < lo) continue;
-        k_lex<T, KACZ><<<hi - lo + 1, LX_TR, 0, s>>>(gt, H, ih2, (const T *)k, sigma, (const C<T> *)f, (C<T> *)u,
+        k_lex<T, KACZ><<<hi - lo + 1, LX_NT, 0, s>>>(gt, H, ih2, (const T *)k, sigma, (const C<T> *)f, (C<T> *)u,
                                                      d, lo, skip);
     }
 }
