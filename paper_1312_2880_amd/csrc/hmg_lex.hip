@@ -67,7 +67,10 @@ __global__ __launch_bounds__(LX_NT) void k_lex(GeoT g, double H, double ih2, con
     if (skip && *skip) return;
     __shared__ C<T> U[LX_UH][LX_UW];
     __shared__ C<T> F[LX_TR][LX_FW];
-    __shared__ T K[LX_TR][LX_FW];
+    // per-node constants of the row, formed while staging (off the steps'
+    // dependency chain): Gauss-Seidel conj(a_pp) / |a_pp|^2; Kaczmarz a_pp
+    // and 1 / ||a_p||^2
+    __shared__ double RW[LX_TR][LX_FW][3];
     const int b = b_lo + (int)blockIdx.x, a = diag - b;
     const int c0 = a * LX_TC, j0 = b * LX_TR, tid = threadIdx.x;
 
@@ -100,8 +103,19 @@ __global__ __launch_bounds__(LX_NT) void k_lex(GeoT g, double H, double ih2, con
 #pragma unroll
     for (int t = 0; t < LX_FPER; ++t) {
         const int q = t * LX_NT + tid, jl = q / LX_TC, cl = q - jl * LX_TC;
+        const int j = j0 + jl, i = c0 + cl - j;
         F[jl][cl] = fv[t];
-        K[jl][cl] = kv[t];
+        const Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)kv[t], sigma);
+        if (KACZ) {
+            RW[jl][cl][0] = r.dre;
+            RW[jl][cl][1] = r.dim;
+            RW[jl][cl][2] = 1.0 / (r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd +
+                                   r.wu * r.wu);
+        } else {
+            const double inv = 1.0 / (r.dre * r.dre + r.dim * r.dim);
+            RW[jl][cl][0] = r.dre * inv;
+            RW[jl][cl][1] = -r.dim * inv;
+        }
     }
     __syncthreads();
 
@@ -116,13 +130,13 @@ __global__ __launch_bounds__(LX_NT) void k_lex(GeoT g, double H, double ih2, con
             for (int s = 0; s < LX_TC; ++s) {
                 const int i = c0 + s - j, cc = s + 1;
                 if (j <= g.N && i >= 0 && i <= g.N) {
-                    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][s], sigma);
+                    const Row<double> r = row_at<double>(i, j, g.N, H, ih2, 0.0, 0.0);   // weights only
                     // neighbours in the order left, right, down, up
                     C<double> o = cscale(r.wl, lds_c(U[jj][cc - 1]));
                     o = cadd(o, cscale(r.wr, lds_c(U[jj][cc + 1])));
                     o = cadd(o, cscale(r.wd, lds_c(U[jj - 1][cc - 1])));
                     o = cadd(o, cscale(r.wu, lds_c(U[jj + 1][cc + 1])));
-                    U[jj][cc] = st_as<T>(cdiv(csub(lds_c(F[lane][s]), o), r.dre, r.dim));
+                    U[jj][cc] = st_as<T>(cmul(csub(lds_c(F[lane][s]), o), cmk(RW[lane][s][0], RW[lane][s][1])));
                 }
                 wave_step();
             }
@@ -131,7 +145,9 @@ __global__ __launch_bounds__(LX_NT) void k_lex(GeoT g, double H, double ih2, con
             for (int s = 0; s < LX_TC + LX_TR - 1; ++s) {
                 const int cl = s - lane, i = c0 + cl - j, cc = cl + 1;
                 if (cl >= 0 && cl < LX_TC && j <= g.N && i >= 0 && i <= g.N) {
-                    Row<double> r = row_at<double>(i, j, g.N, H, ih2, (double)K[lane][cl], sigma);
+                    Row<double> r = row_at<double>(i, j, g.N, H, ih2, 0.0, 0.0);   // weights only
+                    r.dre = RW[lane][cl][0];
+                    r.dim = RW[lane][cl][1];
                     const C<double> up = lds_c(U[jj][cc]), ul = lds_c(U[jj][cc - 1]), ur = lds_c(U[jj][cc + 1]);
                     const C<double> ud = lds_c(U[jj - 1][cc - 1]), uu = lds_c(U[jj + 1][cc + 1]);
                     C<double> o = cscale(r.wl, ul);
@@ -139,9 +155,8 @@ __global__ __launch_bounds__(LX_NT) void k_lex(GeoT g, double H, double ih2, con
                     o = cadd(o, cscale(r.wd, ud));
                     o = cadd(o, cscale(r.wu, uu));
                     const C<double> res = csub(lds_c(F[lane][cl]), cadd(cmul(cmk(r.dre, r.dim), up), o));
-                    const double nrm =
-                        r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
-                    const C<double> d = cmk(res.x / nrm, res.y / nrm);
+                    const double rn = RW[lane][cl][2];
+                    const C<double> d = cmk(res.x * rn, res.y * rn);
                     U[jj][cc] = st_as<T>(cmk(up.x + (r.dre * d.x + r.dim * d.y), up.y + (r.dre * d.y - r.dim * d.x)));
                     if (i > 0) U[jj][cc - 1] = st_as<T>(cadd(ul, cscale(r.wl, d)));
                     if (i < g.N) U[jj][cc + 1] = st_as<T>(cadd(ur, cscale(r.wr, d)));
