@@ -13,6 +13,10 @@ Workloads (the paper's own media are not available, so these stand in):
     c in [1.5, 4.5], times (1 + 0.05 g / max|g|) for a sum g of 64 seeded
     Gaussian bumps of width 0.05; k = omega / c.  It stands in for the
     heterogeneous (wedge) medium of Table 3;
+  * a wedge-type medium (Table 3 analogue, own geometry: the paper's picture
+    of its medium is missing): three regions of constant k = k_ref,
+    1.5 k_ref and 2 k_ref separated by two slanted interfaces that meet
+    inside the domain, unit source at the middle of the upper edge;
   * batches of constant-k instances of mixed sizes with several point sources;
   * Poisson request streams of layered-medium solves of mixed sizes.
 """
@@ -99,6 +103,34 @@ class LayeredMedium:
 def layered_problem(n: int, seed: int, omega: float):
     med = LayeredMedium(seed)
     return grid_h(n), med.k(n, omega), med.source(n)
+
+
+# ---- wedge-type medium ----------------------------------------------------
+
+WEDGE_UPPER = (0.75, -0.25)   # interface y = a + b x between the upper and the middle region
+WEDGE_LOWER = (0.20, 0.35)    # interface between the middle (wedge) and the lower region
+WEDGE_K = (1.0, 1.5, 2.0)     # k / k_ref in the upper, middle and lower region
+
+
+def wedge_k(n: int, k_ref: float) -> np.ndarray:
+    """k on the (n+2)^2 nodes: lower region y <= 0.20 + 0.35 x (2 k_ref),
+    middle region up to y = 0.75 - 0.25 x (1.5 k_ref; it narrows to nothing
+    at x = 11/12), upper region above both (k_ref)."""
+    xs = node_coords(n)
+    x, y = xs[None, :], xs[:, None]
+    lower = y <= WEDGE_LOWER[0] + WEDGE_LOWER[1] * x
+    middle = ~lower & (y <= WEDGE_UPPER[0] + WEDGE_UPPER[1] * x)
+    k = np.full((n + 2, n + 2), WEDGE_K[0] * k_ref)
+    k[middle] = WEDGE_K[1] * k_ref
+    k[lower] = WEDGE_K[2] * k_ref
+    return k
+
+
+def wedge_problem(n: int):
+    """Table 3 setting: k_ref h = 15/64 (k_ref = 15 on h = 1/64 up to 240 on
+    h = 1/1024), unit source at the node nearest (0.5, 1)."""
+    k_ref = 15.0 * (n + 1) / 64.0
+    return grid_h(n), wedge_k(n, k_ref), point_source(n, (n + 1) // 2, n + 1)
 
 
 # ---- named workloads ------------------------------------------------------
