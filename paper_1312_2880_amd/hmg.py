@@ -187,7 +187,9 @@ class Context:
         return self._h
 
     def close(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone; the
+        # process end releases the device memory then
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.hmg_ctx_destroy(self._h)
             self._h = None
 
@@ -264,7 +266,7 @@ class Grid:
         self._h = hdl
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.hmg_grid_destroy(self._h)
             self._h = None
 
