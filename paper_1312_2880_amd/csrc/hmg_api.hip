@@ -12,6 +12,7 @@
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -422,6 +423,9 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
             (void)hipGraphExecDestroy(ge);
             (void)hipGraphDestroy(gr);
             if (le != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "tuner: %s", hipGetErrorString(le));
+            if (std::getenv("HMG_TUNE_LOG"))
+                std::fprintf(stderr, "hmg tune: n=%d config %d (tile %d, %d sweeps, %d threads): %.4f ms\n",
+                             L.geo.n, cfg, kKaczCfgs[cfg].ts, sw, kKaczCfgs[cfg].threads, ms);
             // the default keeps its place unless another configuration is
             // clearly faster (runs then agree on the choice)
             if (cfg == g->lev[l].kacz_cfg) ms *= 0.95f;
@@ -460,6 +464,8 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
             if (ge) (void)hipGraphExecDestroy(ge);
             (void)hipGraphDestroy(gr);
             if (le != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "tuner: %s", hipGetErrorString(le));
+            if (std::getenv("HMG_TUNE_LOG"))
+                std::fprintf(stderr, "hmg tune: n=%d whole level in one workgroup: %.4f ms\n", L.geo.n, ms);
             whole = ms < 0.95f * best_ms;
         }
         (void)hipEventDestroy(e0);
