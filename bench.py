@@ -46,17 +46,18 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
     (c = complex size, r = real size of the level precision; per fine node,
     plus c per coarse node where a coarse field is read or written):
       gs_down     read f, k; write coarse f (+ write u0)     N (c + r) + Nc c   (+ N c)
-      gs_up       read f, k, coarse e (+ read u0); write u   N (2c + r) + Nc c  (+ N c)
+      gs_up       read f, k, coarse e (+ read u0 on the      N (2c + r) + Nc c  (+ N c / 2)
+                  black nodes); write u
       kacz_tb     read f, k, u; write u                      N (3c + r)
-    (FP64 levels store the pre-smoothed iterate u0 for the up kernel;
-    complex-float levels recompute it on chip)
+    (FP64 levels store the pre-smoothed iterate u0 for the up kernel, which
+    needs it on the black nodes only: the red half-sweep overwrites red
+    values unread; complex-float levels recompute it on chip)
     """
     c, r = cbytes, rbytes
-    extra = nodes * c if stored_u0 else 0
     if kind == "gs_down":
-        return nodes * (c + r) + coarse_nodes * c + extra
+        return nodes * (c + r) + coarse_nodes * c + (nodes * c if stored_u0 else 0)
     if kind == "gs_up":
-        return nodes * (2 * c + r) + coarse_nodes * c + extra
+        return nodes * (2 * c + r) + coarse_nodes * c + (nodes * c // 2 if stored_u0 else 0)
     if kind == "kacz_tb":
         return nodes * (3 * c + r)
     raise KeyError(kind)

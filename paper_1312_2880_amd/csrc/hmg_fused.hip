@@ -111,6 +111,21 @@ __device__ __forceinline__ void xcd_tile(int &tx, int &ty) {
     ty = t / gridDim.x;
 }
 
+// Row of node (i, j) for a region that may (IN = false) or may not (IN =
+// true, every node of the region at least one node inside the boundary)
+// touch the domain boundary.  The interior form gives the same values as
+// row_at (weights 1/H^2, no boundary term) without its per-node tests.
+template <bool IN>
+__device__ __forceinline__ Row<double> row_in(int i, int j, int N, double H, double ih2, double kp, double sigma) {
+    if (!IN) return row_at<double>(i, j, N, H, ih2, kp, sigma);
+    Row<double> r;
+    const double k2 = kp * kp;
+    r.dre = -4.0 * ih2 + k2;
+    r.dim = k2 * sigma;
+    r.wl = r.wr = r.wd = r.wu = ih2;
+    return r;
+}
+
 // ===========================================================================
 // Fused Gauss-Seidel kernels.  A tile of X x Y fine nodes (x0, y0 even) is
 // processed with a halo of RH = 3 held in LDS.  Each thread owns fixed
@@ -159,17 +174,14 @@ using GsSmall2 = GsTile<32, 12, 2>;
 // tile + 1, full weighting to the coarse nodes of the tile.  The smoothed
 // iterate stays on chip (written only when uo != null).
 // ===========================================================================
-template <class TL, typename T, typename TF>
-__global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
-                                                 double sb, const C<TF> *__restrict__ f, C<T> *uo,
-                                                 C<T> *__restrict__ fc, const int *skip) {
-    if (skip && *skip) return;
-    __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
-    const int tid = threadIdx.x;
-    int tx, ty;
-    xcd_tile(tx, ty);
-    const int x0 = tx * TL::X, y0 = ty * TL::Y;
+template <class TL, bool IN, typename T, typename TF>
+__device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, const T *__restrict__ k, double sa, double sb,
+                                                const C<TF> *__restrict__ f, C<T> *uo, C<T> *__restrict__ fc,
+                                                C<double> *U, int tid, int x0, int y0) {
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
+    auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > g.N || j > g.N); };
+    auto mir = [&](int x, int n) { return IN ? x : mirror(x, n); };
+    (void)mir;
     const int N = g.N, M = g.M;
     C<double> fr[2][TL::NS];
     double kr[2][TL::NS];
@@ -194,11 +206,11 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
         bool own = TL::owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
         if (!own) continue;
-        if (i < 0 || j < 0 || i > N || j > N) {
+        if (outside(i, j)) {
             U[ly * TL::LW + lx] = cmk(0.0, 0.0);
             continue;
         }
-        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[0][m], sa);
         U[ly * TL::LW + lx] = cdiv(fr[0][m], r.dre, r.dim);
     }
     __syncthreads();
@@ -210,11 +222,11 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
         int i = ox + lx, j = oy + ly;
         if (!own || !TL::ring(lx, ly, 2)) continue;
         int l = ly * TL::LW + lx;
-        if (i < 0 || j < 0 || i > N || j > N) {
+        if (outside(i, j)) {
             U[l] = cmk(0.0, 0.0);
             continue;
         }
-        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
         U[l] = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
     }
     __syncthreads();
@@ -226,7 +238,7 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
             const int q = tid + GNT * m;
             int tx = q % TL::X, ty = q / TL::X;
             int i = x0 + tx, j = y0 + ty;
-            if (q >= TL::X * TL::Y || i > N || j > N) continue;
+            if (q >= TL::X * TL::Y || (!IN && (i > N || j > N))) continue;
             uo[(size_t)j * M + i] = st_as<T>(U[(ty + TL::RH) * TL::LW + tx + TL::RH]);
         }
     }
@@ -240,9 +252,9 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
             int lx, ly;
             bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+            if (!own || !TL::ring(lx, ly, 1) || outside(i, j)) continue;
             int l = ly * TL::LW + lx;
-            Row<double> r = row_at<double>(i, j, N, H, ih2, kr[c][m], sb);
+            Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[c][m], sb);
             C<double> au = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, TL::LW));
             res[c][m] = csub(fr[c][m], au);
         }
@@ -254,7 +266,7 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
             int lx, ly;
             bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+            if (!own || !TL::ring(lx, ly, 1) || outside(i, j)) continue;
             U[ly * TL::LW + lx] = res[c][m];
         }
     __syncthreads();
@@ -270,9 +282,9 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
             if (I > Nc || J > Nc) continue;
             C<double> s = cmk(0.0, 0.0);
             for (int e = -1; e <= 1; ++e) {
-                int j = mirror(2 * J + e, N);
+                int j = mir(2 * J + e, N);
                 for (int d = -1; d <= 1; ++d) {
-                    int i = mirror(2 * I + d, N);
+                    int i = mir(2 * I + d, N);
                     double w = (double)((2 - (d < 0 ? -d : d)) * (2 - (e < 0 ? -e : e)));
                     s = cadd(s, cscale(w, U[(j - oy) * TL::LW + (i - ox)]));
                 }
@@ -282,12 +294,125 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
     }
 }
 
+template <class TL, typename T, typename TF>
+__global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
+                                                 double sb, const C<TF> *__restrict__ f, C<T> *uo,
+                                                 C<T> *__restrict__ fc, const int *skip) {
+    if (skip && *skip) return;
+    __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
+    const int tid = threadIdx.x;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * TL::X, y0 = ty * TL::Y;
+    const int N = g.N;
+    // tiles whose region lies inside the domain skip the boundary tests
+    if (x0 - TL::RH >= 1 && y0 - TL::RH >= 1 && x0 - TL::RH + TL::LW <= N && y0 - TL::RH + TL::LH <= N)
+        k_gs_down_body<TL, true>(g, H, ih2, k, sa, sb, f, uo, fc, U, tid, x0, y0);
+    else
+        k_gs_down_body<TL, false>(g, H, ih2, k, sa, sb, f, uo, fc, U, tid, x0, y0);
+}
+
 // ===========================================================================
 // k_gs_up: u0 = the zero-guess red-black sweep of k_gs_down (recomputed from
 // f), u = u0 + P ec, then one red-black sweep; result to uo.  Regions shrink
-// by one per dependent step: red u0 on tile + 3, black u0 on tile + 2,
-// correction on tile + 2, red on tile + 1, black on the tile.
+// by one per dependent step: red u0 on tile + 3, black u0 plus correction on
+// tile + 2, red on tile + 1, black on the tile.  The red half-sweep reads
+// only black values, so red nodes never get the correction: their values
+// before the sweep are overwritten unread (the result is that of u0 + P ec
+// on every node).  Tiles whose
+// region lies inside the domain run the phases without boundary tests (a
+// branch per workgroup; the same values either way).
 // ===========================================================================
+template <class TL, bool IN, typename T, typename TU>
+__device__ __forceinline__ void gs_up_phases(C<double> *U, int tid, int ox, int oy, int N, int M, int Mc, double H,
+                                             double ih2, double sa, const C<double> (&fr)[2][TL::NS],
+                                             const double (&kr)[2][TL::NS], const C<T> *__restrict__ ec,
+                                             C<TU> *__restrict__ uo) {
+    auto prolong = [&](int i, int j) { return prolong_at(ec, i, j, Mc); };
+    auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > N || j > N); };
+    // red u0 on tile + 3 (zero outside the domain)
+#pragma unroll
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 0, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own) continue;
+        if (outside(i, j)) {
+            U[ly * TL::LW + lx] = cmk(0.0, 0.0);
+            continue;
+        }
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[0][m], sa);
+        U[ly * TL::LW + lx] = cdiv(fr[0][m], r.dre, r.dim);
+    }
+    __syncthreads();
+    // black u0 on tile + 2, plus the correction on the black nodes
+#pragma unroll
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 1, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own || !TL::ring(lx, ly, 2)) continue;
+        int l = ly * TL::LW + lx;
+        if (outside(i, j)) {
+            U[l] = cmk(0.0, 0.0);
+            continue;
+        }
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
+        U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim), prolong(i, j));
+    }
+    __syncthreads();
+    // red on tile + 1 (the red half-sweep reads only black values, so the
+    // correction is needed on the black nodes alone)
+#pragma unroll
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 0, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own || !TL::ring(lx, ly, 1) || outside(i, j)) continue;
+        int l = ly * TL::LW + lx;
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[0][m], sa);
+        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+    }
+    __syncthreads();
+    // black on the tile -> output; red tile nodes -> output
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < TL::NS; ++m) {
+            int lx, ly;
+            bool own = TL::owned(tid, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (!own || !TL::ring(lx, ly, 0) || (!IN && (i > N || j > N))) continue;
+            int l = ly * TL::LW + lx;
+            C<double> v = U[l];
+            if (c == 1) {
+                Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
+                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+            }
+            uo[(size_t)j * M + i] = st_as<TU>(v);
+        }
+}
+
+// f and k of the nodes of tile (ox + RH, oy + RH) owned by thread tid
+template <class TL, typename T, typename TF>
+__device__ __forceinline__ void gs_load(int tid, int ox, int oy, int N, int M, const C<TF> *__restrict__ f,
+                                        const T *__restrict__ k, C<double> (&fr)[2][TL::NS],
+                                        double (&kr)[2][TL::NS]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < TL::NS; ++m) {
+            int lx, ly;
+            bool own = TL::owned(tid, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (own && i >= 0 && j >= 0 && i <= N && j <= N) {
+                size_t p = (size_t)j * M + i;
+                fr[c][m] = ldr<double>(f, p);
+                kr[c][m] = (double)k[p];
+            }
+        }
+}
+
 template <class TL, typename T, typename TF, typename TU>
 __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                const C<TF> *__restrict__ f, const C<T> *__restrict__ ec,
@@ -302,112 +427,29 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     C<double> fr[2][TL::NS];
     double kr[2][TL::NS];
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int m = 0; m < TL::NS; ++m) {
-            int lx, ly;
-            bool own = TL::owned(tid, c, m, lx, ly);
-            int i = ox + lx, j = oy + ly;
-            if (own && i >= 0 && j >= 0 && i <= N && j <= N) {
-                size_t p = (size_t)j * M + i;
-                fr[c][m] = ldr<double>(f, p);
-                kr[c][m] = (double)k[p];
-            }
-        }
-    // red u0 on tile + 3 (zero outside the domain)
-#pragma unroll
-    for (int m = 0; m < TL::NS; ++m) {
-        int lx, ly;
-        bool own = TL::owned(tid, 0, m, lx, ly);
-        int i = ox + lx, j = oy + ly;
-        if (!own) continue;
-        if (i < 0 || j < 0 || i > N || j > N) {
-            U[ly * TL::LW + lx] = cmk(0.0, 0.0);
-            continue;
-        }
-        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[ly * TL::LW + lx] = cdiv(fr[0][m], r.dre, r.dim);
-    }
-    __syncthreads();
-    // black u0 on tile + 2, plus the correction on the black nodes
-#pragma unroll
-    for (int m = 0; m < TL::NS; ++m) {
-        int lx, ly;
-        bool own = TL::owned(tid, 1, m, lx, ly);
-        int i = ox + lx, j = oy + ly;
-        if (!own || !TL::ring(lx, ly, 2)) continue;
-        int l = ly * TL::LW + lx;
-        if (i < 0 || j < 0 || i > N || j > N) {
-            U[l] = cmk(0.0, 0.0);
-            continue;
-        }
-        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-        U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim), prolong_at(ec, i, j, Mc));
-    }
-    __syncthreads();
-    // the correction on the red nodes of tile + 2 (after every black u0 has
-    // read the uncorrected red values)
-#pragma unroll
-    for (int m = 0; m < TL::NS; ++m) {
-        int lx, ly;
-        bool own = TL::owned(tid, 0, m, lx, ly);
-        int i = ox + lx, j = oy + ly;
-        if (!own || !TL::ring(lx, ly, 2) || i < 0 || j < 0 || i > N || j > N) continue;
-        int l = ly * TL::LW + lx;
-        U[l] = cadd(U[l], prolong_at(ec, i, j, Mc));
-    }
-    __syncthreads();
-    // red on tile + 1
-#pragma unroll
-    for (int m = 0; m < TL::NS; ++m) {
-        int lx, ly;
-        bool own = TL::owned(tid, 0, m, lx, ly);
-        int i = ox + lx, j = oy + ly;
-        if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
-        int l = ly * TL::LW + lx;
-        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
-        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
-    }
-    __syncthreads();
-    // black on the tile -> output; red tile nodes -> output
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int m = 0; m < TL::NS; ++m) {
-            int lx, ly;
-            bool own = TL::owned(tid, c, m, lx, ly);
-            int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, 0) || i > N || j > N) continue;
-            int l = ly * TL::LW + lx;
-            C<double> v = U[l];
-            if (c == 1) {
-                Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
-                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
-            }
-            uo[(size_t)j * M + i] = st_as<TU>(v);
-        }
+    gs_load<TL>(tid, ox, oy, N, M, f, k, fr, kr);
+    if (ox >= 1 && oy >= 1 && ox + TL::LW <= N && oy + TL::LH <= N)
+        gs_up_phases<TL, true>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo);
+    else
+        gs_up_phases<TL, false>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo);
 }
 
 // ===========================================================================
 // k_gs_up_u0: as k_gs_up, but the pre-smoothed iterate u0 is read from
-// memory (written by k_gs_down) instead of recomputed: u = u0 + P ec on
-// tile + 2, red on tile + 1, black on the tile -> uo.  Used where u0 is
-// stored without rounding (FP64 levels); three phases instead of five.
+// memory (written by k_gs_down) instead of recomputed: u = u0 + P ec on the
+// black nodes of tile + 2 (red values are overwritten unread), red on tile
+// + 1, black on the tile -> uo.  Used where u0 is stored without rounding
+// (FP64 levels); three phases instead of four.
 // ===========================================================================
-template <class TL, typename T, typename TF, typename TU>
-__global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
-                                                  const C<TF> *__restrict__ f, const C<T> *__restrict__ u0,
-                                                  const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
-                                                  const int *skip) {
-    static_assert(TL::RH == 2, "halo of two");
-    if (skip && *skip) return;
-    __shared__ C<double> U[TL::LW * TL::LH];
-    const int tid = threadIdx.x;
-    int tx, ty;
-    xcd_tile(tx, ty);
-    const int x0 = tx * TL::X, y0 = ty * TL::Y;
+template <class TL, bool IN, typename T, typename TF, typename TU>
+__device__ __forceinline__ void k_gs_up_u0_body(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
+                                                 const C<TF> *__restrict__ f, const C<T> *__restrict__ u0,
+                                                 const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
+                                                 C<double> *U, int tid, int x0, int y0) {
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
+    auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > g.N || j > g.N); };
+    auto mir = [&](int x, int n) { return IN ? x : mirror(x, n); };
+    (void)mir;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     // f and k of the nodes relaxed here (tile + 1), and u0 + P ec on tile + 2
     C<double> fr[2][TL::NS];
@@ -421,7 +463,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
             int i = ox + lx, j = oy + ly;
             if (!own) continue;
             const int l = ly * TL::LW + lx;
-            if (i < 0 || j < 0 || i > N || j > N) {
+            if (outside(i, j)) {
                 U[l] = cmk(0.0, 0.0);
                 continue;
             }
@@ -430,7 +472,10 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
                 fr[c][m] = ldr<double>(f, p);
                 kr[c][m] = (double)k[p];
             }
-            U[l] = cadd(ldr<double>(u0, p), prolong_at(ec, i, j, Mc));
+            // the red half-sweep reads only black values: red nodes need
+            // neither u0 nor the correction (their cells are overwritten
+            // on tile + 1 and never read elsewhere)
+            U[l] = (c == 1) ? cadd(ldr<double>(u0, p), prolong_at(ec, i, j, Mc)) : cmk(0.0, 0.0);
         }
     __syncthreads();
     // red on tile + 1
@@ -439,9 +484,9 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
         int lx, ly;
         bool own = TL::owned(tid, 0, m, lx, ly);
         int i = ox + lx, j = oy + ly;
-        if (!own || !TL::ring(lx, ly, 1) || i < 0 || j < 0 || i > N || j > N) continue;
+        if (!own || !TL::ring(lx, ly, 1) || outside(i, j)) continue;
         int l = ly * TL::LW + lx;
-        Row<double> r = row_at<double>(i, j, N, H, ih2, kr[0][m], sa);
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[0][m], sa);
         U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
     }
     __syncthreads();
@@ -453,15 +498,35 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
             int lx, ly;
             bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, 0) || i > N || j > N) continue;
+            if (!own || !TL::ring(lx, ly, 0) || (!IN && (i > N || j > N))) continue;
             int l = ly * TL::LW + lx;
             C<double> v = U[l];
             if (c == 1) {
-                Row<double> r = row_at<double>(i, j, N, H, ih2, kr[1][m], sa);
+                Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
                 v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
             }
             uo[(size_t)j * M + i] = st_as<TU>(v);
         }
+}
+
+template <class TL, typename T, typename TF, typename TU>
+__global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
+                                                  const C<TF> *__restrict__ f, const C<T> *__restrict__ u0,
+                                                  const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
+                                                  const int *skip) {
+    static_assert(TL::RH == 2, "halo of two");
+    if (skip && *skip) return;
+    __shared__ C<double> U[TL::LW * TL::LH];
+    const int tid = threadIdx.x;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int x0 = tx * TL::X, y0 = ty * TL::Y;
+    const int N = g.N;
+    // tiles whose region lies inside the domain skip the boundary tests
+    if (x0 - TL::RH >= 1 && y0 - TL::RH >= 1 && x0 - TL::RH + TL::LW <= N && y0 - TL::RH + TL::LH <= N)
+        k_gs_up_u0_body<TL, true>(g, H, ih2, k, sa, f, u0, ec, uo, U, tid, x0, y0);
+    else
+        k_gs_up_u0_body<TL, false>(g, H, ih2, k, sa, f, u0, ec, uo, U, tid, x0, y0);
 }
 
 // ===========================================================================
