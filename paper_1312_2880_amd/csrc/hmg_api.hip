@@ -755,15 +755,16 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         return dst;
     }
     if (L.mode == LM_GS_FUSED) {
-        // The up kernel needs the pre-smoothed iterate u0.  On FP64 levels
-        // small enough for their fields to stay in cache (n <= 511) the down
-        // kernel stores it and the up kernel reads it (two dependent phases
-        // fewer); on larger levels the extra HBM traffic costs more than the
-        // phases, and complex-float levels must not round it: both recompute
-        // it from f.
+        // The up kernel needs the pre-smoothed iterate u0 (on the black
+        // nodes: red values are overwritten unread).  On FP64 levels small
+        // enough for their fields to stay in cache (n <= 511) the down kernel
+        // stores it there and the up kernel reads it (one dependent phase
+        // fewer); on larger levels the extra HBM traffic costs as much as the
+        // phase saves, and complex-float levels must not round it: both
+        // recompute it from f.
         void *u0 = (g->prec == P64 && L.geo.n <= 511) ? S.u[l] : nullptr;
         launch_gs_down(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, u0, S.f[l + 1],
-                       skip);
+                       skip, true);
         const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
         void *dst = out ? out : S.u2[l];
         launch_gs_up(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip);

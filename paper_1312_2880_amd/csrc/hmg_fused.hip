@@ -177,7 +177,7 @@ using GsSmall2 = GsTile<32, 12, 2>;
 template <class TL, bool IN, typename T, typename TF>
 __device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, const T *__restrict__ k, double sa, double sb,
                                                 const C<TF> *__restrict__ f, C<T> *uo, C<T> *__restrict__ fc,
-                                                C<double> *U, int tid, int x0, int y0) {
+                                                int uo_black, C<double> *U, int tid, int x0, int y0) {
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > g.N || j > g.N); };
     auto mir = [&](int x, int n) { return IN ? x : mirror(x, n); };
@@ -231,14 +231,15 @@ __device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, con
     }
     __syncthreads();
     // the smoothed iterate on the tile (only when asked for: the up kernel
-    // recomputes it)
+    // recomputes it), on the black nodes alone when uo_black (all the up
+    // kernel reads)
     if (uo) {
 #pragma unroll
         for (int m = 0; m < (TL::X * TL::Y + GNT - 1) / GNT; ++m) {
             const int q = tid + GNT * m;
             int tx = q % TL::X, ty = q / TL::X;
             int i = x0 + tx, j = y0 + ty;
-            if (q >= TL::X * TL::Y || (!IN && (i > N || j > N))) continue;
+            if (q >= TL::X * TL::Y || (!IN && (i > N || j > N)) || (uo_black && !((i + j) & 1))) continue;
             uo[(size_t)j * M + i] = st_as<T>(U[(ty + TL::RH) * TL::LW + tx + TL::RH]);
         }
     }
@@ -297,7 +298,7 @@ __device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, con
 template <class TL, typename T, typename TF>
 __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                  double sb, const C<TF> *__restrict__ f, C<T> *uo,
-                                                 C<T> *__restrict__ fc, const int *skip) {
+                                                 C<T> *__restrict__ fc, int uo_black, const int *skip) {
     if (skip && *skip) return;
     __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
     const int tid = threadIdx.x;
@@ -307,9 +308,9 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
     const int N = g.N;
     // tiles whose region lies inside the domain skip the boundary tests
     if (x0 - TL::RH >= 1 && y0 - TL::RH >= 1 && x0 - TL::RH + TL::LW <= N && y0 - TL::RH + TL::LH <= N)
-        k_gs_down_body<TL, true>(g, H, ih2, k, sa, sb, f, uo, fc, U, tid, x0, y0);
+        k_gs_down_body<TL, true>(g, H, ih2, k, sa, sb, f, uo, fc, uo_black, U, tid, x0, y0);
     else
-        k_gs_down_body<TL, false>(g, H, ih2, k, sa, sb, f, uo, fc, U, tid, x0, y0);
+        k_gs_down_body<TL, false>(g, H, ih2, k, sa, sb, f, uo, fc, uo_black, U, tid, x0, y0);
 }
 
 // ===========================================================================
@@ -1156,20 +1157,22 @@ static dim3 gs_grid(const Geo &g) { return dim3((g.M + TL::X - 1) / TL::X, (g.M 
 
 template <typename T, typename TF>
 static void gs_down_t(hipStream_t s, const Geo &g, const void *k, double sa, double sb, const void *f, void *uo,
-                      void *fc, const int *skip) {
+                      void *fc, bool uo_black, const int *skip) {
     if (gs_small(g))
         k_gs_down<GsSmall, T, TF><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
-            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
+            uo_black ? 1 : 0, skip);
     else
         k_gs_down<GsDownBig, T, TF><<<gs_grid<GsDownBig>(g), GNT, 0, s>>>(
-            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc, skip);
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
+            uo_black ? 1 : 0, skip);
 }
 
 void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void *k, double sa, double sb,
-                    const void *f, void *uo, void *fc, const int *skip) {
-    if (p == P64) gs_down_t<double, double>(s, g, k, sa, sb, f, uo, fc, skip);
-    else if (f64in) gs_down_t<float, double>(s, g, k, sa, sb, f, uo, fc, skip);
-    else gs_down_t<float, float>(s, g, k, sa, sb, f, uo, fc, skip);
+                    const void *f, void *uo, void *fc, const int *skip, bool uo_black) {
+    if (p == P64) gs_down_t<double, double>(s, g, k, sa, sb, f, uo, fc, uo_black, skip);
+    else if (f64in) gs_down_t<float, double>(s, g, k, sa, sb, f, uo, fc, uo_black, skip);
+    else gs_down_t<float, float>(s, g, k, sa, sb, f, uo, fc, uo_black, skip);
 }
 
 template <typename T, typename TF, typename TU>

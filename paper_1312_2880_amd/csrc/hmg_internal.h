@@ -104,8 +104,9 @@ int    bottom_real_slots();
 // f64in / io64: the level-0 input (and output) are FP64 while the level
 // computes in float (mixed precision).
 void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void *k, double sa, double sb,
-                    const void *f, void *uo, void *fc, const int *skip);
+                    const void *f, void *uo, void *fc, const int *skip, bool uo_black = false);
 // uo may be null in launch_gs_down (the smoothed iterate is not stored);
+// uo_black: store it on the black nodes only (all that launch_gs_up reads);
 // launch_gs_up recomputes it from f.
 // u0: the pre-smoothed iterate stored by launch_gs_down, or null (recomputed
 // from f)
