@@ -2,7 +2,7 @@
 sizes through the request server (continuous batching, admission by device
 footprint), against the same stream served one request at a time in FP64.
 
-    python bench_serve.py [--rates 5,50] [--count 30] [--warmup 4]
+    python bench_serve.py [--rates 5,50,200] [--count 30] [--warmup 4]
 
 Each request: n ~ U{255, 511, 1023, 2047}, a seeded layered medium with
 omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, SL-V
@@ -92,7 +92,7 @@ def serve(hmg, reqs, precision, max_active, warmup, maxit):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rates", default="5,50")
+    ap.add_argument("--rates", default="5,50,200")
     ap.add_argument("--count", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--seed", type=int, default=5)
