@@ -129,7 +129,13 @@ typedef struct {
     int    levels;
     int    restarts;         /* breakdown / true-residual restarts             */
     double seconds;          /* wall time of the solve                         */
+    int    flags;            /* HMG_INFO_* bits                                */
 } hmg_solve_info;
+
+/* hmg_solve_info.flags: the largest k h of the finest grid exceeds 2 pi / 10,
+ * i.e. fewer than ten nodes per wavelength somewhere (the resolution the
+ * problem statement of Section 1 asks for); the solve is run regardless. */
+#define HMG_INFO_KH_ABOVE_GUIDE 1
 
 typedef struct hmg_ctx  hmg_ctx;
 typedef struct hmg_grid hmg_grid;

@@ -197,6 +197,7 @@ static hmg_status run_finish(SolveRun &R, hmg_solve_info *info) {
         info->levels = R.g->nlev;
         info->restarts = k.restarts;
         info->seconds = hmg_now() - R.t_start;
+        info->flags = (R.g->plan.kHmax[0] > 0.2 * M_PI) ? HMG_INFO_KH_ABOVE_GUIDE : 0;
     }
     return res;
 }

@@ -28,6 +28,7 @@ ERR_BREAKDOWN, PENDING, ERR_TOO_LARGE, ERR_UNKNOWN_TICKET, ERR_CANCELLED = 5, 6,
 SL, HLM, HYB = 0, 1, 2
 FP64, MIXED = 0, 1
 SM_GS, SM_KACZ, SM_LU = 0, 1, 2
+INFO_KH_ABOVE_GUIDE = 1
 ORDER_COLOUR, ORDER_LEX = 0, 1
 MAX_LEVELS = 24
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED",
@@ -66,7 +67,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_double), ("halfsteps", ctypes.c_int),
                 ("rel_res_true", ctypes.c_double), ("status", ctypes.c_int),
                 ("levels", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("flags", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):

@@ -817,6 +817,19 @@ def test_invalid_arguments(ctx, hmg):
         hmg.Grid(ctx, 1 / 64, k)                       # k must be > 0
 
 
+def test_info_flags_under_resolved_grid(ctx, hmg):
+    """max k h above 2 pi / 10 (fewer than ten nodes per wavelength) is
+    reported in the solve info; the solve still runs."""
+    say("case info flags")
+    n = 63
+    for kh, flagged in ((0.5, False), (0.7, True)):
+        h, k, f = inputs.grid_h(n), inputs.constant_k(n, kh * (n + 1)), inputs.centre_source(n)
+        g = hmg.Grid(ctx, h, k, f, variant=hmg.SL)
+        _, info = g.solve(rtol=1e-6, maxit=300)
+        assert bool(info[0]["flags"] & hmg.INFO_KH_ABOVE_GUIDE) == flagged, (kh, info[0])
+        assert info[0]["status"] == hmg.OK
+
+
 def test_solve_dev_with_torch_buffers(ctx, hmg):
     say("case solve_dev")
     h, k, f = inputs.workload_const_point(63)

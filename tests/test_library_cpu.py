@@ -57,12 +57,11 @@ def test_defaults_are_the_papers_constants():
     assert (o.one_pass_kernels, o.autotune, o.bottom_dense, o.use_graph) == (0, 1, 1, 1)
 
 
-def test_opts_struct_matches_the_header():
-    """The ctypes mirror of hmg_opts has the header's size and field order."""
+def _header_fields(typedef_name):
+    """Field names of a `typedef struct { ... } name;` of the public header."""
     import re
-    from paper_1312_2880_amd import hmg
     hdr = open(os.path.join(ROOT, "include", "hmg.h")).read()
-    end = hdr.index("} hmg_opts;")
+    end = hdr.index("} %s;" % typedef_name)
     body = hdr[hdr.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = []
@@ -72,7 +71,20 @@ def test_opts_struct_matches_the_header():
             continue
         for part in decl.split(None, 1)[1].split(","):
             names.append(part.strip().split("[")[0])
-    assert [f for f, _ in hmg.Opts._fields_] == names
+    return names
+
+
+def test_opts_struct_matches_the_header():
+    """The ctypes mirror of hmg_opts has the header's field order."""
+    from paper_1312_2880_amd import hmg
+    assert [f for f, _ in hmg.Opts._fields_] == _header_fields("hmg_opts")
+
+
+def test_info_and_result_structs_match_the_header():
+    from paper_1312_2880_amd import hmg
+    assert [f for f, _ in hmg.SolveInfo._fields_] == _header_fields("hmg_solve_info")
+    assert [f for f, _ in hmg.Result._fields_] == _header_fields("hmg_result")
+    assert [f for f, _ in hmg.Plan._fields_] == _header_fields("hmg_plan")
 
 
 def test_null_arguments_are_rejected():
