@@ -55,7 +55,10 @@ typedef enum {
     HMG_ERR_NOMEM = 2,          /* device or host allocation failed             */
     HMG_ERR_DEVICE = 3,         /* a HIP call failed                            */
     HMG_ERR_NOT_CONVERGED = 4,  /* maxit reached; x holds the last iterate      */
-    HMG_ERR_BREAKDOWN = 5,      /* repeated Bi-CGSTAB breakdown                 */
+    HMG_ERR_BREAKDOWN = 5,      /* reserved: a Bi-CGSTAB breakdown (rho ~ 0)
+                                   restarts the iteration from the current
+                                   residual instead (counted in
+                                   hmg_solve_info.restarts)                     */
     HMG_PENDING = 6,            /* request not finished yet                     */
     HMG_ERR_TOO_LARGE = 7,      /* request footprint above the context budget   */
     HMG_ERR_UNKNOWN_TICKET = 8,
