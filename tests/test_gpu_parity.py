@@ -950,6 +950,29 @@ def test_serving_results_same_alone_and_in_mix(hmg):
         assert np.array_equal(xs, x) and rs["iters"] == res["iters"]
 
 
+def test_serving_and_batch_with_lexicographic_order(hmg):
+    """Requests and batched grids carry their options: a lexicographic-order
+    request served next to a coloured one, and both in one batch, give the
+    bits of the same problems solved alone."""
+    say("case serving/batch lexicographic")
+    n = 63
+    h, k, f = inputs.workload_const_point(n, 40.0)
+    reqs = [dict(n=n, h=h, k=k, f=f, rtol=1e-6, maxit=300, variant=0, relax_order=hmg.ORDER_LEX),
+            dict(n=n, h=h, k=k, f=f, rtol=1e-6, maxit=300, variant=0, relax_order=hmg.ORDER_COLOUR)]
+    c = hmg.Context(0)
+    served = _serve_all(c, reqs)
+    grids = [hmg.Grid(c, h, k, f, variant=0, relax_order=r["relax_order"]) for r in reqs]
+    xb, infob = c.solve_batch(grids, rtol=1e-6, maxit=300)
+    for q, g in enumerate(grids):
+        xs, infos = g.solve(rtol=1e-6, maxit=300)
+        assert infos[0]["status"] == hmg.OK
+        assert np.array_equal(served[q][0], xs[0]) and served[q][1]["iters"] == infos[0]["iters"]
+        assert np.array_equal(xb[q][0], xs[0]) and infob[q][0]["iters"] == infos[0]["iters"]
+        g.close()
+    assert served[0][1]["iters"] != served[1][1]["iters"] or not np.array_equal(served[0][0], served[1][0])
+    c.close()
+
+
 def test_serving_admission_budget_and_cancel(hmg):
     say("case serving budget")
     reqs = _requests()
