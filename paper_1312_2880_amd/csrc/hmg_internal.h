@@ -70,10 +70,9 @@ void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, siz
 // ---- lexicographic sweeps (hmg_lex.hip) -------------------------------------
 // One sweep in lexicographic order (x fastest) of Gauss-Seidel (kacz = 0) or
 // Kaczmarz (kacz = 1) on A_sigma u = f, in place on u; launches one kernel
-// per tile diagonal of the wavefront (lex_launches of them).
+// per tile diagonal of the wavefront.
 void launch_lex_sweep(Prec p, int kacz, hipStream_t s, const Geo &g, const void *k, double sigma,
                       const void *f, void *u, const int *skip);
-int  lex_launches(const Geo &g);
 
 // ---- fused LDS-tiled kernels (hmg_fused.hip) --------------------------------
 constexpr int HMG_SM_GS_DEV = 0, HMG_SM_KACZ_DEV = 1;

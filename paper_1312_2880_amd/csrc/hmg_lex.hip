@@ -205,17 +205,6 @@ static void lex_tiles(int N, int d, int NA, int NB, int &lo, int &hi) {
     }
 }
 
-int lex_launches(const Geo &g) {
-    const int NA = (2 * g.N + LX_TC) / LX_TC, NB = (g.N + LX_TR) / LX_TR;
-    int count = 0;
-    for (int d = 0; d < NA + NB - 1; ++d) {
-        int lo, hi;
-        lex_tiles(g.N, d, NA, NB, lo, hi);
-        count += (hi >= lo);
-    }
-    return count;
-}
-
 template <typename T, bool KACZ>
 static void lex_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, void *u,
                   const int *skip) {
