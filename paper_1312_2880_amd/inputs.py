@@ -9,10 +9,9 @@ arrays of shape ``(n+2, n+2)`` indexed ``[j, i]`` with node (i, j) at
 Workloads (the paper's own media are not available, so these stand in):
   * constant k with a unit point source at the centre (the setting of the
     paper's Tables 1 and 2);
-  * a layered medium: 8 horizontal layers with seeded interfaces and speeds
-    c in [1.5, 4.5], times (1 + 0.05 g / max|g|) for a sum g of 64 seeded
-    Gaussian bumps of width 0.05; k = omega / c.  It stands in for the
-    heterogeneous (wedge) medium of Table 3;
+  * a layered medium (the benchmark medium): 8 horizontal layers with seeded
+    interfaces and speeds c in [1.5, 4.5], times (1 + 0.05 g / max|g|) for a
+    sum g of 64 seeded Gaussian bumps of width 0.05; k = omega / c;
   * a wedge-type medium (Table 3 analogue, own geometry: the paper's picture
     of its medium is missing): three regions of constant k = k_ref,
     1.5 k_ref and 2 k_ref separated by two slanted interfaces that meet
