@@ -801,6 +801,25 @@ def test_vcycle_full_size_layered_2047(ctx, hmg):
     assert rel(gm.vcycle(r), want) <= 1e-4
 
 
+def test_vcycle_and_solve_layered_4095(ctx, hmg):
+    """The largest grid tested: 4095^2 (16.8 M nodes, 10 levels) of the same
+    medium at omega = 2 pi 160 (same max kh).  One V-cycle against the
+    oracle, and a short SL-V solve whose first half steps follow the
+    oracle's residual history."""
+    n = 4095
+    say(f"case vcycle layered{n}")
+    h, k, f = inputs.layered_problem(n, 2, 2 * math.pi * 160)
+    og = oracle.Grid(h, k, variant=0)
+    g = hmg.Grid(ctx, h, k, f, variant=0)
+    assert [p["n"] for p in g.plan()] == [p["n"] for p in og.plan()]
+    r = inputs.random_field(n, 9)
+    assert rel(g.vcycle(r), og.vcycle(r)) <= 1e-11
+    _, info = g.solve(rtol=1e-6, maxit=4)
+    _, ref = og.bicgstab(f, rtol=1e-6, maxit=4, history=True)
+    np.testing.assert_allclose(g.history(0)[:8], ref["history"][:8], rtol=1e-7)
+    g.close()
+
+
 def test_invalid_arguments(ctx, hmg):
     k = np.full((64, 64), 5.0)
     with pytest.raises(hmg.HmgError):
