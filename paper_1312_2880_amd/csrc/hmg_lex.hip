@@ -22,15 +22,16 @@
 // are pairwise at distance >= 3) except for two corner halo cells, which the
 // kernel reads but neither uses nor writes back.
 //
-// Kernel.  One tile per workgroup of four waves.  The tile's nodes, f and k
-// plus a one-cell halo ring of u are staged in LDS by all four waves, every
-// thread issuing all of its loads before its first LDS store (rows of the
-// skewed tile are contiguous runs of a grid row in HBM, so the loads are
-// coalesced).  The first wave then steps through the tile, lane = tile row
-// (Gauss-Seidel: TC steps, all lanes on column c; Kaczmarz: TC + TR - 1
-// steps, lane l on column t - l), and all four waves write back what changed.  Arithmetic is FP64 as in the other kernels;
-// u is rounded to the level precision at every store, as the coloured
-// kernels do.
+// Kernel.  One tile per workgroup of four waves.  The tile's u with a
+// one-cell halo ring, its f and the constants of its rows (Gauss-Seidel:
+// conj(a_pp) / |a_pp|^2; Kaczmarz: a_pp and 1 / ||a_p||^2) are staged in LDS
+// by all four waves, every thread issuing all of its loads before its first
+// LDS store (rows of the skewed tile are contiguous runs of a grid row in
+// HBM, so the loads are coalesced).  The first wave then steps through the
+// tile, lane = tile row (Gauss-Seidel: TC steps, all lanes on column c;
+// Kaczmarz: TC + TR - 1 steps, lane l on column t - l), and all four waves
+// write back what changed.  Arithmetic is FP64 as in the other kernels; u is
+// rounded to the level precision at every store, as the coloured kernels do.
 
 #include "hmg_device.h"
 
@@ -41,10 +42,10 @@ constexpr int LX_TC = 32;            // skewed columns per tile
 constexpr int LX_NT = 256;           // threads per workgroup (staging and write-back)
 constexpr int LX_UH = LX_TR + 2;     // staged rows of u (halo ring)
 constexpr int LX_UW = LX_TC + 3;     // staged columns of u: TC + 2, padded to an odd 16-byte stride
-constexpr int LX_FW = LX_TC + 1;     // row stride of the staged f and k (odd)
+constexpr int LX_FW = LX_TC + 1;     // row stride of the staged f and row constants (odd)
 constexpr int LX_UCELLS = LX_UH * (LX_TC + 2);
 constexpr int LX_UPER = (LX_UCELLS + LX_NT - 1) / LX_NT;   // u cells per thread
-constexpr int LX_FPER = LX_TR * LX_TC / LX_NT;             // f and k cells per thread
+constexpr int LX_FPER = LX_TR * LX_TC / LX_NT;             // f and k values per thread
 static_assert(LX_TR * LX_TC % LX_NT == 0, "f and k cells divide over the threads");
 
 // End of one wavefront step: order this step's LDS stores before the next
