@@ -404,6 +404,27 @@ def test_vcycle_equals_dense_matrix_vcycle(case):
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
 
 
+@pytest.mark.parametrize("variant", [oracle.SL, oracle.HYB])
+def test_vcycle_on_a_hierarchy_that_is_not_a_power_of_two(variant):
+    """h = 1/20 (Table 1's grids halve 80 -> 40 -> 20 -> 10 -> 5): interval
+    counts 20 -> 10 -> 5 with the coarsest level at n = 4; the V-cycle equals
+    the dense-matrix composition, restriction and prolongation included."""
+    n, h = 19, 1 / 20
+    k = rng_k(n, 33, 8.0, 14.0)
+    g = oracle.Grid(h, k, variant=variant, coarsest_n=4)
+    plan = g.plan()
+    assert [p["n"] for p in plan] == [19, 9, 4]
+    ref = D.DenseVCycle(h, k, plan)
+    m = (n + 2) ** 2
+    for col in range(0, m, 11):
+        f = np.zeros(m, complex)
+        f[col] = 1.0
+        f[(col * 7 + 5) % m] = -0.25j
+        want = ref.apply(f)
+        got = g.vcycle(f.reshape(n + 2, n + 2)).reshape(-1)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
 def test_vcycle_plans_cover_both_smoothers():
     kinds = set()
     mixed_roles = False
