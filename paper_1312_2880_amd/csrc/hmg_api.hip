@@ -745,7 +745,7 @@ static void vcycle_level(hmg_grid *g, Slot &S, int l, const void *f, void *u, hi
 // `out` when given (else to a level buffer, whose pointer is returned).  f64
 // marks the FP64 level-0 input / output of the mixed precision.
 static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64, void *out, hipStream_t s,
-                           const int *skip) {
+                           const int *skip, MvFuse *mv = nullptr) {
     const Level &L = g->lev[l];
     const hmg_plan &pl = g->plan;
     if (l == g->lb) {
@@ -767,6 +767,16 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
                        skip, true);
         const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
         void *dst = out ? out : S.u2[l];
+        // the finest up kernel of an FP64 solve also forms the Krylov product
+        // of its result when the caller asks for it
+        if (mv && l == 0 && !u0 && !f64 && gs_up_mv_ok(g->prec, L.geo) &&
+            gs_up_mv_blocks(L.geo) <= S.K.nblocks) {
+            launch_gs_up_mv(s, mv->kind, L.geo, L.k, pl.sigma_relax[l], f, e, dst, mv->out, mv->dot, mv->partials,
+                            skip);
+            mv->blocks = gs_up_mv_blocks(L.geo);
+            mv->fused = true;
+            return dst;
+        }
         launch_gs_up(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip);
         return dst;
     }
@@ -830,11 +840,12 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
 }
 
 // z = B_V r on FP64 device fields r, z (finest level).
-void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip) {
+void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip,
+                    MvFuse *mv) {
     if (!one_pass(g)) {
         bool mixed = g->prec == P32;
         if (!mixed || g->lb == 0 || g->lev[0].mode == LM_GS_FUSED) {
-            vc_fast(g, S, 0, r, mixed, z, s, skip);
+            vc_fast(g, S, 0, r, mixed, z, s, skip, mv);
         } else {
             size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
             launch_convert(s, 1, r, S.f[0], m0, skip);

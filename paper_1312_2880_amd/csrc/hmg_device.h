@@ -110,4 +110,41 @@ struct GeoT {
     int n, M, N;
 };
 
+// Sum NV values over a 256-thread block; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
+    __shared__ double red[NV][NT / 64];
+    int tid = threadIdx.y * BX + threadIdx.x;
+    int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) red[q][wave] = x;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double x = red[q][0];
+            for (int w = 1; w < NT / 64; ++w) x += red[q][w];
+            out[q] = x;
+        }
+    }
+}
+
+// Writes the block's NV sums to partials[q * nblocks + block].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials) {
+    double tot[NV];
+    block_sum<NV>(v, tot);
+    int nb = gridDim.x * gridDim.y;
+    int b = blockIdx.y * gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) partials[(size_t)q * nb + b] = tot[q];
+    }
+}
+
+
 }  // namespace hmgk

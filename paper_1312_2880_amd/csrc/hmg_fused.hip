@@ -167,6 +167,9 @@ using GsSmall = GsTile<32, 12>;
 using GsDownBig = GsTile<64, 12>;
 // the up kernel that reads the stored pre-smoothed iterate needs a halo of 2
 using GsBig2 = GsTile<64, 20, 2>;
+// the up kernel with the Bi-CGSTAB matrix-vector product needs its result on
+// tile + 1: a halo of 4
+using GsBigMV = GsTile<64, 20, 4>;
 using GsSmall2 = GsTile<32, 12, 2>;
 
 // ===========================================================================
@@ -412,6 +415,137 @@ __device__ __forceinline__ void gs_load(int tid, int ox, int oy, int N, int M, c
                 kr[c][m] = (double)k[p];
             }
         }
+}
+
+// ===========================================================================
+// k_gs_up_mv: k_gs_up on the finest level of an FP64 solve, followed by the
+// Bi-CGSTAB product with L of the result it writes (Section 6): the phases
+// run one ring further out (red u0 on tile + 4, black u0 + correction on
+// tile + 3, red on tile + 2, black on tile + 1), so that uo is known on tile
+// + 1 in LDS; then mvo = L uo on the tile and the block's partial sums
+//   KIND 1: (dot, mvo)                 (v = L p^ and (rh, v), for alpha)
+//   KIND 2: (mvo, dot), (mvo, mvo)     (t = L s^, (t, s) and (t, t), for omega)
+// with (a, b) = sum conj(a) b, written to partials[q * blocks + block] as the
+// separate product kernels do.  The product kernel and its launch go away.
+// ===========================================================================
+template <bool IN, int KIND>
+__device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, int oy, int N, int M, int Mc,
+                                                double H, double ih2, double sa,
+                                                const C<double> (&fr)[2][GsBigMV::NS],
+                                                const double (&kr)[2][GsBigMV::NS],
+                                                const C<double> *__restrict__ ec, C<double> *__restrict__ uo,
+                                                C<double> *__restrict__ mvo, const C<double> *__restrict__ dot,
+                                                const double *__restrict__ kf, double *partials) {
+    using TL = GsBigMV;
+    auto prolong = [&](int i, int j) { return prolong_at(ec, i, j, Mc); };
+    auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > N || j > N); };
+    // red u0 on tile + 4 (zero outside the domain)
+#pragma unroll
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 0, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own) continue;
+        if (outside(i, j)) {
+            U[ly * TL::LW + lx] = cmk(0.0, 0.0);
+            continue;
+        }
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[0][m], sa);
+        U[ly * TL::LW + lx] = cdiv(fr[0][m], r.dre, r.dim);
+    }
+    __syncthreads();
+    // black u0 plus the correction on tile + 3
+#pragma unroll
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 1, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own || !TL::ring(lx, ly, 3)) continue;
+        int l = ly * TL::LW + lx;
+        if (outside(i, j)) {
+            U[l] = cmk(0.0, 0.0);
+            continue;
+        }
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
+        U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim), prolong(i, j));
+    }
+    __syncthreads();
+    // red on tile + 2, black on tile + 1 (black reads red only, so it may
+    // write its own cells in place); tile nodes -> uo
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int m = 0; m < TL::NS; ++m) {
+            int lx, ly;
+            bool own = TL::owned(tid, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (!own || !TL::ring(lx, ly, 2 - c) || outside(i, j)) continue;
+            int l = ly * TL::LW + lx;
+            Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[c][m], sa);
+            C<double> v = cdiv(csub(fr[c][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+            U[l] = v;
+            if (TL::ring(lx, ly, 0)) uo[(size_t)j * M + i] = v;
+        }
+        __syncthreads();
+    }
+    // the product with L (sigma = 0) on the tile and the partial sums
+    constexpr int NV = KIND == 1 ? 2 : 3;
+    // the slot positions are recomputed from an opaque copy of tid: reusing
+    // the ones of the sweeps would keep them live across every phase and
+    // push the kernel past 128 VGPRs (three waves per SIMD instead of four);
+    // k is reloaded (a cache hit) for the same reason
+    int tid2 = tid;
+    asm volatile("" : "+v"(tid2));
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < TL::NS; ++m) {
+            int lx, ly;
+            bool own = TL::owned(tid2, c, m, lx, ly);
+            int i = ox + lx, j = oy + ly;
+            if (!own || !TL::ring(lx, ly, 0) || outside(i, j)) continue;
+            const int l = ly * TL::LW + lx;
+            const size_t p = (size_t)j * M + i;
+            const Row<double> r = row_in<IN>(i, j, N, H, ih2, kf[p], 0.0);
+            const C<double> w = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, TL::LW));
+            mvo[p] = w;
+            const C<double> a = dot[p];
+            if (KIND == 1) {
+                acc[0] += a.x * w.x + a.y * w.y;      // conj(rh) v
+                acc[NV - 1] += a.x * w.y - a.y * w.x;
+            } else {
+                acc[0] += w.x * a.x + w.y * a.y;      // conj(t) s
+                acc[1] += w.x * a.y - w.y * a.x;
+                acc[NV - 1] += w.x * w.x + w.y * w.y;
+            }
+        }
+    block_partials<NV>(acc, partials);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, const double *__restrict__ k,
+                                                  double sa, const C<double> *__restrict__ f,
+                                                  const C<double> *__restrict__ ec, C<double> *__restrict__ uo,
+                                                  C<double> *__restrict__ mvo, const C<double> *__restrict__ dot,
+                                                  double *partials, const int *skip) {
+    using TL = GsBigMV;
+    if (skip && *skip) return;
+    __shared__ C<double> U[TL::LW * TL::LH];
+    const int tid = threadIdx.x;
+    int tx, ty;
+    xcd_tile(tx, ty);
+    const int ox = tx * TL::X - TL::RH, oy = ty * TL::Y - TL::RH;
+    const int N = g.N, M = g.M, Mc = N / 2 + 1;
+    C<double> fr[2][TL::NS];
+    double kr[2][TL::NS];
+    gs_load<TL>(tid, ox, oy, N, M, f, k, fr, kr);
+    if (ox >= 1 && oy >= 1 && ox + TL::LW <= N && oy + TL::LH <= N)
+        gs_up_mv_phases<true, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, k, partials);
+    else
+        gs_up_mv_phases<false, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, k, partials);
 }
 
 template <class TL, typename T, typename TF, typename TU>
@@ -1196,6 +1330,24 @@ static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const
     else
         k_gs_up<GsBig, T, TF, TU><<<gs_grid<GsBig>(g), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
+}
+
+bool gs_up_mv_ok(Prec p, const Geo &g) { return p == P64 && !gs_small(g) && g.n > 511; }
+int gs_up_mv_blocks(const Geo &g) {
+    const dim3 tg = gs_grid<GsBigMV>(g);
+    return (int)(tg.x * tg.y);
+}
+void launch_gs_up_mv(hipStream_t s, int kind, const Geo &g, const void *k, double sa, const void *f,
+                     const void *ec, void *uo, void *mvo, const void *dot, double *partials, const int *skip) {
+    const double ih2 = 1.0 / (g.H * g.H);
+    if (kind == 1)
+        k_gs_up_mv<1><<<gs_grid<GsBigMV>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, ih2, (const double *)k, sa, (const C<double> *)f, (const C<double> *)ec,
+            (C<double> *)uo, (C<double> *)mvo, (const C<double> *)dot, partials, skip);
+    else
+        k_gs_up_mv<2><<<gs_grid<GsBigMV>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, ih2, (const double *)k, sa, (const C<double> *)f, (const C<double> *)ec,
+            (C<double> *)uo, (C<double> *)mvo, (const C<double> *)dot, partials, skip);
 }
 
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,

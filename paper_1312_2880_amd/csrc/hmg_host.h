@@ -87,5 +87,16 @@ double     hmg_now();
 hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> &kl,
                             const std::vector<std::complex<double>> &inv, const hmg_c64 *f);
 size_t     estimate_footprint(int n, const hmg_opts &o);
+// A Bi-CGSTAB product the finest up kernel may take over: out = L z with the
+// partial sums of kind 1 ((dot, out)) or kind 2 ((out, dot), (out, out)) in
+// partials, laid out for `blocks` blocks.  fused reports whether it did.
+struct MvFuse {
+    int         kind = 0;
+    void       *out = nullptr;
+    const void *dot = nullptr;
+    double     *partials = nullptr;
+    int         blocks = 0;
+    bool        fused = false;
+};
 void       enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s,
-                          const int *skip);
+                          const int *skip, MvFuse *mv = nullptr);

@@ -111,6 +111,15 @@ void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void 
 // from f)
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
                   const void *u0, const void *ec, void *uo, const int *skip);
+// The finest up kernel of an FP64 solve fused with the Bi-CGSTAB product
+// (kind 1: v = L uo with the partials of (dot, v); kind 2: t = L uo with the
+// partials of (t, dot) and (t, t)); partials laid out for gs_up_mv_blocks(g)
+// blocks.  Only where gs_up_mv_ok (FP64 level without a stored iterate, big
+// tiles).
+bool gs_up_mv_ok(Prec p, const Geo &g);
+int  gs_up_mv_blocks(const Geo &g);
+void launch_gs_up_mv(hipStream_t s, int kind, const Geo &g, const void *k, double sa, const void *f,
+                     const void *ec, void *uo, void *mvo, const void *dot, double *partials, const int *skip);
 // tab: (k_p, 1 / ||a_p||^2) for sigma from launch_kacz_table, or null (the
 // kernel forms them)
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
@@ -140,6 +149,9 @@ void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int
               double rtol, int maxhalf);
 void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
+// the single-block finalisations after a fused product (nb partial blocks)
+void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb);
+void kry_omega_fin(hipStream_t s, const Krylov &K, int nb);
 void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K);

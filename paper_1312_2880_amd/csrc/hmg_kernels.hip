@@ -278,42 +278,6 @@ void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, siz
 // in a fixed order, so results do not depend on scheduling.
 // ===========================================================================
 
-// Sum NV values over a 256-thread block; result valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {
-    __shared__ double red[NV][NT / 64];
-    int tid = threadIdx.y * BX + threadIdx.x;
-    int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double x = v[q];
-        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-        if (lane == 0) red[q][wave] = x;
-    }
-    __syncthreads();
-    if (tid == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double x = red[q][0];
-            for (int w = 1; w < NT / 64; ++w) x += red[q][w];
-            out[q] = x;
-        }
-    }
-}
-
-// Writes the block's NV sums to partials[q * nblocks + block].
-template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials) {
-    double tot[NV];
-    block_sum<NV>(v, tot);
-    int nb = gridDim.x * gridDim.y;
-    int b = blockIdx.y * gridDim.x + blockIdx.x;
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q) partials[(size_t)q * nb + b] = tot[q];
-    }
-}
-
 // Single 256-thread block: total of each of NV partial rows.  Thread t sums
 // entries t, t + 256, ... in eight interleaved accumulators (independent
 // loads in flight instead of one dependent chain), combined in a fixed
@@ -676,6 +640,12 @@ void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov
     KDev d = kdev(K);
     k_kry_matvec_alpha<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
     k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb) {
+    k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(kdev(K), nb);
+}
+void kry_omega_fin(hipStream_t s, const Krylov &K, int nb) {
+    k_kry_omega_fin<<<1, dim3(BX, BY), 0, s>>>(kdev(K), nb);
 }
 void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K) {
     KDev d = kdev(K);

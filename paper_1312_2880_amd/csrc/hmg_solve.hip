@@ -78,11 +78,25 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     const Geo &g0 = g->lev[0].geo;
     const int *stop = &S.K.st->stop;
     kry_update_p(s, g0, S.K);
-    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop);
-    kry_matvec_alpha(s, g0, g->k0, S.K);
+    // v = L p^ and t = L s^ come from the V-cycle's last kernel where it can
+    // form them, else from kernels of their own
+    MvFuse mv;
+    mv.kind = 1;
+    mv.out = S.K.v;
+    mv.dot = S.K.rh;
+    mv.partials = S.K.partials;
+    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop, &mv);
+    if (mv.fused) kry_alpha_fin(s, S.K, mv.blocks);
+    else kry_matvec_alpha(s, g0, g->k0, S.K);
     kry_update_s(s, g0, S.K);
-    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop);
-    kry_matvec_omega(s, g0, g->k0, S.K);
+    mv = MvFuse();
+    mv.kind = 2;
+    mv.out = S.K.t;
+    mv.dot = S.K.s;
+    mv.partials = S.K.partials;
+    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop, &mv);
+    if (mv.fused) kry_omega_fin(s, S.K, mv.blocks);
+    else kry_matvec_omega(s, g0, g->k0, S.K);
     kry_update_xr(s, g0, S.K);
 }
 
