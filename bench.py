@@ -48,6 +48,8 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
       gs_down     read f, k; write coarse f (+ write u0)     N (c + r) + Nc c   (+ N c)
       gs_up       read f, k, coarse e (+ read u0 on the      N (2c + r) + Nc c  (+ N c / 2)
                   black nodes); write u
+      gs_up_mv    gs_up without u0, then read the inner      N (4c + r) + Nc c
+                  product's other vector, write L u
       kacz_tb     read f, k, u; write u                      N (3c + r)
     (FP64 levels store the pre-smoothed iterate u0 for the up kernel, which
     needs it on the black nodes only: the red half-sweep overwrites red
@@ -58,6 +60,8 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
         return nodes * (c + r) + coarse_nodes * c + (nodes * c if stored_u0 else 0)
     if kind == "gs_up":
         return nodes * (2 * c + r) + coarse_nodes * c + (nodes * c // 2 if stored_u0 else 0)
+    if kind == "gs_up_mv":
+        return nodes * (4 * c + r) + coarse_nodes * c
     if kind == "kacz_tb":
         return nodes * (3 * c + r)
     raise KeyError(kind)
@@ -134,16 +138,28 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None, lex=False):
         # the kernels as the solve runs them: FP64 levels with n <= 511 store
         # u0 in the down kernel and read it in the up kernel
         st_u0 = precision == "fp64" and n0 <= 511
+        # larger FP64 levels: the up kernel also forms the Bi-CGSTAB product
+        # (alternately the alpha and the omega form, as a solve does)
+        mv = precision == "fp64" and n0 > 511
         bufs = [dict(f=field(n0), u0=field(n0), uo=field(n0), ec=field(nc), fc=field(nc)) for _ in range(sets)]
+        if mv:
+            for b in bufs:
+                b.update(mv=field(n0), dot=field(n0))
         sa, sb = plan[0]["sigma_relax"], plan[0]["sigma_resid"]
         out.append(("gs_down", 0, lambda q, st: g.op_gs_down(0, sa, sb, bufs[q % sets]["f"],
                                                              bufs[q % sets]["u0"] if st_u0 else None,
                                                              bufs[q % sets]["fc"], st), 1,
                     ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb, st_u0)), None))
-        out.append(("gs_up", 0, lambda q, st: g.op_gs_up(0, sa, bufs[q % sets]["f"], bufs[q % sets]["ec"],
-                                                         bufs[q % sets]["uo"], st,
-                                                         d_u0=bufs[q % sets]["u0"] if st_u0 else None), 1,
-                    ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb, st_u0)), None))
+        if mv:
+            out.append(("gs_up_mv", 0, lambda q, st: g.op_gs_up_product(
+                0, sa, 1 + q % 2, bufs[q % sets]["f"], bufs[q % sets]["ec"], bufs[q % sets]["uo"],
+                bufs[q % sets]["mv"], bufs[q % sets]["dot"], None, st), 1,
+                ("hbm", algorithmic_bytes("gs_up_mv", nodes, cnodes, cb, rb)), None))
+        else:
+            out.append(("gs_up", 0, lambda q, st: g.op_gs_up(0, sa, bufs[q % sets]["f"], bufs[q % sets]["ec"],
+                                                             bufs[q % sets]["uo"], st,
+                                                             d_u0=bufs[q % sets]["u0"] if st_u0 else None), 1,
+                        ("hbm", algorithmic_bytes("gs_up", nodes, cnodes, cb, rb, st_u0)), None))
     for l, p in enumerate(plan):
         cfg = g.kacz_config(l)
         if cfg < 0:

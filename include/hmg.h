@@ -296,6 +296,20 @@ hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_relax, const vo
                             const void *d_u0, const void *d_ec, void *d_uo, void *stream);
 hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int config, const void *d_f,
                                  const void *d_ui, const void *d_ec, void *d_uo, void *stream);
+/* The up kernel that ends each V-cycle of an FP64 solve on the finest level,
+ * with the Bi-CGSTAB product that follows the preconditioner (Section 6:
+ * v = A p^ and t = A s^ with A the operator L, sigma = 0): uo as
+ * hmg_op_gs_up_dev with d_u0 = NULL, then d_mv = L uo and, in d_sums
+ * (device, 3 doubles),
+ *   kind 1: Re, Im of sum_p conj(dot_p) mv_p, then 0
+ *   kind 2: Re, Im of sum_p conj(mv_p) dot_p, then sum_p |mv_p|^2.
+ * d_sums may be NULL: the sums are then left unformed (the kernel alone).
+ * FP64 grids only (HMG_ERR_INVALID otherwise).  Uses the grid's reduction
+ * scratch, so it must not overlap a solve on the same grid.  Outputs must
+ * not alias inputs or each other. */
+hmg_status hmg_op_gs_up_product_dev(hmg_grid *g, int level, double sigma_relax, int kind, const void *d_f,
+                                    const void *d_ec, void *d_uo, void *d_mv, const void *d_dot,
+                                    void *d_sums, void *stream);
 /* Kaczmarz pre-smoothing with the restriction (Section 5): uo = S 5-colour
  * Kaczmarz sweeps on A_{sigma_relax} from ui (NULL: zero), then
  * fc = R (f - A_{sigma_resid} uo) on level + 1.  The configuration must be

@@ -990,6 +990,31 @@ extern "C" hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_rela
     return HMG_OK;
 }
 
+extern "C" hmg_status hmg_op_gs_up_product_dev(hmg_grid *g, int level, double sigma_relax, int kind,
+                                               const void *d_f, const void *d_ec, void *d_uo, void *d_mv,
+                                               const void *d_dot, void *d_sums, void *stream) {
+    hmg_status st = check_level(g, level, true);
+    if (st) return st;
+    if (g->prec != P64) return hmg_fail(HMG_ERR_INVALID, "the fused product runs on FP64 grids only");
+    if (kind != 1 && kind != 2) return hmg_fail(HMG_ERR_INVALID, "kind must be 1 or 2");
+    if (!d_f || !d_ec || !d_uo || !d_mv || !d_dot) return hmg_fail(HMG_ERR_INVALID, "null field");
+    const void *ins[] = {d_f, d_ec, d_dot};
+    for (const void *in : ins)
+        if (in == d_uo || in == d_mv || (d_sums && in == d_sums))
+            return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs)");
+    if (d_uo == d_mv || (d_sums && (d_uo == d_sums || d_mv == d_sums)))
+        return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias each other)");
+    const Level &L = g->lev[level];
+    Krylov &K = g->slot[0].K;
+    const int nb = gs_up_mv_blocks(L.geo);
+    if (nb > K.nblocks) return hmg_fail(HMG_ERR_INVALID, "level %d too large for the reduction scratch", level);
+    hipStream_t s = pick_stream(g, stream);
+    launch_gs_up_mv(s, kind, L.geo, L.k, sigma_relax, d_f, d_ec, d_uo, d_mv, d_dot, K.partials, nullptr);
+    if (d_sums) launch_sum_partials(s, K.partials, nb, kind == 1 ? 2 : 3, (double *)d_sums);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
+}
+
 extern "C" hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int config, const void *d_f,
                                             const void *d_ui, const void *d_ec, void *d_uo, void *stream) {
     hmg_status st = check_level(g, level, false);

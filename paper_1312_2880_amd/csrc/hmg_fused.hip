@@ -435,7 +435,7 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
                                                 const double (&kr)[2][GsBigMV::NS],
                                                 const C<double> *__restrict__ ec, C<double> *__restrict__ uo,
                                                 C<double> *__restrict__ mvo, const C<double> *__restrict__ dot,
-                                                const double *__restrict__ kf, double *partials) {
+                                                double *partials) {
     using TL = GsBigMV;
     auto prolong = [&](int i, int j) { return prolong_at(ec, i, j, Mc); };
     auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > N || j > N); };
@@ -470,30 +470,45 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
         U[l] = cadd(cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim), prolong(i, j));
     }
     __syncthreads();
-    // red on tile + 2, black on tile + 1 (black reads red only, so it may
-    // write its own cells in place); tile nodes -> uo
+    // red on tile + 2; then black on tile + 1 (black reads red only, so it
+    // writes its own cells in place) with the tile nodes of both colours ->
+    // uo in the same phase (whole cache lines leave together)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 0, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own || !TL::ring(lx, ly, 2) || outside(i, j)) continue;
+        int l = ly * TL::LW + lx;
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[0][m], sa);
+        U[l] = cdiv(csub(fr[0][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int m = 0; m < TL::NS; ++m) {
             int lx, ly;
             bool own = TL::owned(tid, c, m, lx, ly);
             int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, 2 - c) || outside(i, j)) continue;
+            if (!own || !TL::ring(lx, ly, c) || outside(i, j)) continue;
             int l = ly * TL::LW + lx;
-            Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[c][m], sa);
-            C<double> v = cdiv(csub(fr[c][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
-            U[l] = v;
+            C<double> v;
+            if (c == 1) {
+                Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
+                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+                U[l] = v;
+            } else {
+                v = U[l];
+            }
             if (TL::ring(lx, ly, 0)) uo[(size_t)j * M + i] = v;
         }
-        __syncthreads();
-    }
+    __syncthreads();
     // the product with L (sigma = 0) on the tile and the partial sums
     constexpr int NV = KIND == 1 ? 2 : 3;
     // the slot positions are recomputed from an opaque copy of tid: reusing
     // the ones of the sweeps would keep them live across every phase and
-    // push the kernel past 128 VGPRs (three waves per SIMD instead of four);
-    // k is reloaded (a cache hit) for the same reason
+    // push the kernel past 128 VGPRs (three waves per SIMD instead of four)
     int tid2 = tid;
     asm volatile("" : "+v"(tid2));
     double acc[NV];
@@ -509,7 +524,7 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
             if (!own || !TL::ring(lx, ly, 0) || outside(i, j)) continue;
             const int l = ly * TL::LW + lx;
             const size_t p = (size_t)j * M + i;
-            const Row<double> r = row_in<IN>(i, j, N, H, ih2, kf[p], 0.0);
+            const Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[c][m], 0.0);
             const C<double> w = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, TL::LW));
             mvo[p] = w;
             const C<double> a = dot[p];
@@ -543,9 +558,9 @@ __global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, 
     double kr[2][TL::NS];
     gs_load<TL>(tid, ox, oy, N, M, f, k, fr, kr);
     if (ox >= 1 && oy >= 1 && ox + TL::LW <= N && oy + TL::LH <= N)
-        gs_up_mv_phases<true, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, k, partials);
+        gs_up_mv_phases<true, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials);
     else
-        gs_up_mv_phases<false, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, k, partials);
+        gs_up_mv_phases<false, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials);
 }
 
 template <class TL, typename T, typename TF, typename TU>

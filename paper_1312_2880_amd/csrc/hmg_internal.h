@@ -151,6 +151,8 @@ void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 // the single-block finalisations after a fused product (nb partial blocks)
 void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb);
+// out[0..2] = the totals of nv (2 or 3) block partials, zero-padded
+void launch_sum_partials(hipStream_t s, const double *partials, int nb, int nv, double *out);
 void kry_omega_fin(hipStream_t s, const Krylov &K, int nb);
 void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K);

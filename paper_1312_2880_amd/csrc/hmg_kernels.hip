@@ -641,6 +641,17 @@ void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov
     k_kry_matvec_alpha<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
     k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
+// partial sums of nv quantities over nb blocks -> out[0..2] (zero-padded)
+__global__ __launch_bounds__(NT) void k_sum_partials(const double *partials, int nb, int nv, double *out) {
+    double tot[3];
+    if (nv == 2) finalize_sums<2>(partials, nb, tot);
+    else finalize_sums<3>(partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    for (int q = 0; q < 3; ++q) out[q] = q < nv ? tot[q] : 0.0;
+}
+void launch_sum_partials(hipStream_t s, const double *partials, int nb, int nv, double *out) {
+    k_sum_partials<<<1, dim3(BX, BY), 0, s>>>(partials, nb, nv, out);
+}
 void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb) {
     k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(kdev(K), nb);
 }

@@ -114,6 +114,7 @@ _SIGS = {
     "hmg_op_gs_down_dev": (_i, [P, _i, _d, _d, P, P, P, P]),
     "hmg_op_gs_up_dev": (_i, [P, _i, _d, P, P, P, P, P]),
     "hmg_op_kacz_tiled_dev": (_i, [P, _i, _d, _i, P, P, P, P, P]),
+    "hmg_op_gs_up_product_dev": (_i, [P, _i, _d, _i, P, P, P, P, P, P, P]),
     "hmg_kacz_tile_config": (_i, [_i, P, P, P]),
     "hmg_op_kacz_down_dev": (_i, [P, _i, _d, _d, _i, P, P, P, P, P]),
     "hmg_op_kacz_level_dev": (_i, [P, _i, _d, _d, _i, P, P, P, P, P, P]),
@@ -355,6 +356,11 @@ class Grid:
     def op_gs_up(self, level, sigma_relax, d_f, d_ec, d_uo, stream=None, d_u0=None):
         _check(_lib.hmg_op_gs_up_dev(self._h, level, sigma_relax, _dptr(d_f), _dptr(d_u0),
                                      _dptr(d_ec), _dptr(d_uo), _stream(stream)))
+
+    def op_gs_up_product(self, level, sigma_relax, kind, d_f, d_ec, d_uo, d_mv, d_dot, d_sums, stream=None):
+        _check(_lib.hmg_op_gs_up_product_dev(self._h, level, sigma_relax, kind, _dptr(d_f), _dptr(d_ec),
+                                             _dptr(d_uo), _dptr(d_mv), _dptr(d_dot), _dptr(d_sums),
+                                             _stream(stream)))
 
     def op_kacz_tiled(self, level, sigma, config, d_f, d_ui, d_ec, d_uo, stream=None):
         _check(_lib.hmg_op_kacz_tiled_dev(self._h, level, sigma, config, _dptr(d_f), _dptr(d_ui),

@@ -304,6 +304,50 @@ def test_fused_gs_up_from_stored_iterate(ctx, hmg, n):
     assert rel(host(d_uo), host(d_uo2)) <= 1e-14
 
 
+@pytest.mark.parametrize("n,klo,khi", [(63, 20.0, 60.0), (95, 30.0, 90.0), (255, 60.0, 200.0),
+                                       (1023, 70.0, 160.0)])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_fused_gs_up_with_product_matches_oracle(ctx, hmg, n, klo, khi, kind):
+    """The up kernel of FP64 solves with the Bi-CGSTAB product after the
+    preconditioner (Section 6): uo as the plain up kernel, mv = L uo
+    (sigma = 0) and the inner products of the alpha (kind 1) or omega
+    (kind 2) step.  mv differences nodes of size ~ ||L|| |uo|, so its
+    tolerance is that of uo times the operator's norm over |mv|."""
+    say(f"case gs_up_product n={n} kind={kind}")
+    h = 1.0 / (n + 1)
+    k = rand_k(n, 8 * n + kind, klo, khi)
+    g = hmg.Grid(ctx, h, k)
+    f = inputs.random_field(n, 81)
+    nc = (n - 1) // 2
+    ec = inputs.random_field(nc, 82)
+    dot = inputs.random_field(n, 83)
+    d_uo, d_mv = dev(np.zeros_like(f)), dev(np.zeros_like(f))
+    d_sums = torch.full((3,), 7.0, dtype=torch.float64, device="cuda")
+    g.op_gs_up_product(0, 0.5, kind, dev(f), dev(ec), d_uo, d_mv, dev(dot), d_sums)
+    u0 = oracle.gs_rb(h, k, 0.5, f, np.zeros_like(f))
+    want_u = oracle.gs_rb(h, k, 0.5, f, oracle.prolong_add(ec, u0))
+    want_mv = oracle.apply(h, k, 0.0, want_u)
+    assert rel(host(d_uo), want_u) <= 1e-13
+    amp = 8.0 / h ** 2 * np.linalg.norm(want_u) / np.linalg.norm(want_mv)
+    assert rel(host(d_mv), want_mv) <= 1e-13 * max(1.0, amp)
+    got = d_sums.cpu().numpy()
+    scale = np.linalg.norm(dot) * np.linalg.norm(want_mv) * 1e-13 * max(1.0, amp)
+    if kind == 1:
+        want = np.vdot(dot, want_mv)
+        assert abs(complex(got[0], got[1]) - want) <= scale
+        assert got[2] == 0.0
+    else:
+        want = np.vdot(want_mv, dot)
+        assert abs(complex(got[0], got[1]) - want) <= scale
+        want2 = np.vdot(want_mv, want_mv).real
+        assert abs(got[2] - want2) <= 2e-13 * max(1.0, amp) * want2
+    # without d_sums the fields are the same and the sums are left alone
+    d_uo2, d_mv2 = dev(np.zeros_like(f)), dev(np.zeros_like(f))
+    g.op_gs_up_product(0, 0.5, kind, dev(f), dev(ec), d_uo2, d_mv2, dev(dot), None)
+    assert np.array_equal(host(d_uo2), host(d_uo)) and np.array_equal(host(d_mv2), host(d_mv))
+    assert np.array_equal(d_sums.cpu().numpy(), got)
+
+
 def test_fused_gs_down_without_iterate_output(ctx, hmg):
     n = 255
     h = 1 / 256
@@ -432,6 +476,18 @@ def test_fused_ops_reject_aliasing(ctx, hmg):
         g.op_gs_up(0, 0.5, a, ec, a)
     with pytest.raises(hmg.HmgError):
         g.vcycle_dev(a, a)
+    b, c = dev(np.zeros((65, 65), np.complex128)), dev(np.zeros((65, 65), np.complex128))
+    sums = dev(np.zeros(3, np.float64))
+    with pytest.raises(hmg.HmgError):
+        g.op_gs_up_product(0, 0.5, 1, a, ec, b, b, c, sums)      # uo aliases mv
+    with pytest.raises(hmg.HmgError):
+        g.op_gs_up_product(0, 0.5, 2, a, ec, b, c, b, sums)      # dot aliases uo
+    with pytest.raises(hmg.HmgError):
+        g.op_gs_up_product(0, 0.5, 3, a, ec, b, c, a, sums)      # no such kind
+    gm = hmg.Grid(ctx, 1 / 64, np.full((65, 65), 30.0), precision=hmg.MIXED)
+    with pytest.raises(hmg.HmgError):
+        gm.op_gs_up_product(0, 0.5, 1, a, ec, b, c, a, sums)     # FP64 grids only
+    gm.close()
 
 
 # ---------------------------------------------------------------------------
