@@ -110,6 +110,22 @@ struct GeoT {
     int n, M, N;
 };
 
+// Launches queued past convergence see a device flag and return.  The flag
+// is read together with a kernel's first loads instead of before them (one
+// memory latency less on the path of every launch): flag_read issues the
+// load, flag_set tests it once the kernel's loads are in flight, and a
+// launch that returns waits for its loads before it ends.  No launch stores
+// anything before the test.
+static __device__ int kNoFlag = 0;   // read (never written) where a launch has no flag
+__device__ __forceinline__ int flag_read(const int *flag) { return *(flag ? flag : &kNoFlag); }
+__device__ __forceinline__ bool flag_set(int v) {
+    if (v) {
+        __builtin_amdgcn_s_waitcnt(0);
+        return true;
+    }
+    return false;
+}
+
 // Sum NV values over a 256-thread block; result valid in thread 0.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double *out) {

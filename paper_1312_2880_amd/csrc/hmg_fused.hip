@@ -180,7 +180,7 @@ using GsSmall2 = GsTile<32, 12, 2>;
 template <class TL, bool IN, typename T, typename TF>
 __device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, const T *__restrict__ k, double sa, double sb,
                                                 const C<TF> *__restrict__ f, C<T> *uo, C<T> *__restrict__ fc,
-                                                int uo_black, C<double> *U, int tid, int x0, int y0) {
+                                                int uo_black, C<double> *U, int tid, int x0, int y0, int sk) {
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > g.N || j > g.N); };
     auto mir = [&](int x, int n) { return IN ? x : mirror(x, n); };
@@ -201,6 +201,7 @@ __device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, con
                 kr[c][m] = (double)k[p];
             }
         }
+    if (flag_set(sk)) return;
     // red on tile + 3 (zero guess: u = f / a_pp); cells outside the domain
     // are set to zero (missing neighbours of the rows below)
 #pragma unroll
@@ -302,7 +303,7 @@ template <class TL, typename T, typename TF>
 __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                  double sb, const C<TF> *__restrict__ f, C<T> *uo,
                                                  C<T> *__restrict__ fc, int uo_black, const int *skip) {
-    if (skip && *skip) return;
+    const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
     const int tid = threadIdx.x;
     int tx, ty;
@@ -311,9 +312,9 @@ __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, c
     const int N = g.N;
     // tiles whose region lies inside the domain skip the boundary tests
     if (x0 - TL::RH >= 1 && y0 - TL::RH >= 1 && x0 - TL::RH + TL::LW <= N && y0 - TL::RH + TL::LH <= N)
-        k_gs_down_body<TL, true>(g, H, ih2, k, sa, sb, f, uo, fc, uo_black, U, tid, x0, y0);
+        k_gs_down_body<TL, true>(g, H, ih2, k, sa, sb, f, uo, fc, uo_black, U, tid, x0, y0, sk);
     else
-        k_gs_down_body<TL, false>(g, H, ih2, k, sa, sb, f, uo, fc, uo_black, U, tid, x0, y0);
+        k_gs_down_body<TL, false>(g, H, ih2, k, sa, sb, f, uo, fc, uo_black, U, tid, x0, y0, sk);
 }
 
 // ===========================================================================
@@ -547,7 +548,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, 
                                                   C<double> *__restrict__ mvo, const C<double> *__restrict__ dot,
                                                   double *partials, const int *skip) {
     using TL = GsBigMV;
-    if (skip && *skip) return;
+    const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
     int tx, ty;
@@ -557,6 +558,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, 
     C<double> fr[2][TL::NS];
     double kr[2][TL::NS];
     gs_load<TL>(tid, ox, oy, N, M, f, k, fr, kr);
+    if (flag_set(sk)) return;
     if (ox >= 1 && oy >= 1 && ox + TL::LW <= N && oy + TL::LH <= N)
         gs_up_mv_phases<true, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials);
     else
@@ -567,7 +569,7 @@ template <class TL, typename T, typename TF, typename TU>
 __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                const C<TF> *__restrict__ f, const C<T> *__restrict__ ec,
                                                C<TU> *__restrict__ uo, const int *skip) {
-    if (skip && *skip) return;
+    const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
     int tx, ty;
@@ -578,6 +580,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, con
     C<double> fr[2][TL::NS];
     double kr[2][TL::NS];
     gs_load<TL>(tid, ox, oy, N, M, f, k, fr, kr);
+    if (flag_set(sk)) return;
     if (ox >= 1 && oy >= 1 && ox + TL::LW <= N && oy + TL::LH <= N)
         gs_up_phases<TL, true>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo);
     else
@@ -595,7 +598,7 @@ template <class TL, bool IN, typename T, typename TF, typename TU>
 __device__ __forceinline__ void k_gs_up_u0_body(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                  const C<TF> *__restrict__ f, const C<T> *__restrict__ u0,
                                                  const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
-                                                 C<double> *U, int tid, int x0, int y0) {
+                                                 C<double> *U, int tid, int x0, int y0, int sk) {
     const int ox = x0 - TL::RH, oy = y0 - TL::RH;
     auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > g.N || j > g.N); };
     auto mir = [&](int x, int n) { return IN ? x : mirror(x, n); };
@@ -627,6 +630,7 @@ __device__ __forceinline__ void k_gs_up_u0_body(GeoT g, double H, double ih2, co
             // on tile + 1 and never read elsewhere)
             U[l] = (c == 1) ? cadd(ldr<double>(u0, p), prolong_at(ec, i, j, Mc)) : cmk(0.0, 0.0);
         }
+    if (flag_set(sk)) return;
     __syncthreads();
     // red on tile + 1
 #pragma unroll
@@ -665,7 +669,7 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
                                                   const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
                                                   const int *skip) {
     static_assert(TL::RH == 2, "halo of two");
-    if (skip && *skip) return;
+    const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
     int tx, ty;
@@ -674,9 +678,9 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
     const int N = g.N;
     // tiles whose region lies inside the domain skip the boundary tests
     if (x0 - TL::RH >= 1 && y0 - TL::RH >= 1 && x0 - TL::RH + TL::LW <= N && y0 - TL::RH + TL::LH <= N)
-        k_gs_up_u0_body<TL, true>(g, H, ih2, k, sa, f, u0, ec, uo, U, tid, x0, y0);
+        k_gs_up_u0_body<TL, true>(g, H, ih2, k, sa, f, u0, ec, uo, U, tid, x0, y0, sk);
     else
-        k_gs_up_u0_body<TL, false>(g, H, ih2, k, sa, f, u0, ec, uo, U, tid, x0, y0);
+        k_gs_up_u0_body<TL, false>(g, H, ih2, k, sa, f, u0, ec, uo, U, tid, x0, y0, sk);
 }
 
 // ===========================================================================
@@ -707,7 +711,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
                                                 double sigb, const C<T> *__restrict__ f,
                                                 const C<T> *__restrict__ ui, const C<T> *__restrict__ ec,
                                                 C<T> *__restrict__ uo, C<T> *__restrict__ fc, const int *skip) {
-    if (skip && *skip) return;
+    const int sk = flag_read(skip);
     constexpr int TS = RESID ? TS0 - 4 : TS0;
     constexpr int RH = 10 * S + (RESID ? 2 : 0), LW = TS + 2 * RH;
     // f and (k, 1/||a_p||^2) of the region are staged in LDS when they fit
@@ -808,6 +812,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         sa[m] = (((-(ox + 1) - 2 * j) % 5) + 5) % 5;
     }
     if (dma) __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed in LDS
+    if (flag_set(sk)) return;
     __syncthreads();
 #pragma unroll
     for (int pass = 0; pass < 5 * S; ++pass) {
@@ -1253,7 +1258,7 @@ template <typename TF, typename TU>
 __global__ __launch_bounds__(DNT) void k_dense_apply(const C<double> *__restrict__ B, int m,
                                                      const C<TF> *__restrict__ f, C<TU> *__restrict__ u,
                                                      const int *skip) {
-    if (skip && *skip) return;
+    const int sk = flag_read(skip);
     __shared__ double part[2][DNT / 64];
     const int tid = threadIdx.x, r = blockIdx.x;
     const C<double> *row = B + (size_t)r * m;
@@ -1264,6 +1269,7 @@ __global__ __launch_bounds__(DNT) void k_dense_apply(const C<double> *__restrict
         b[q] = row[c];
         x[q] = ldr<double>(f, c);
     }
+    if (flag_set(sk)) return;
     double ax = 0.0, ay = 0.0;
 #pragma unroll
     for (int q = 0; q < DPT; ++q) {

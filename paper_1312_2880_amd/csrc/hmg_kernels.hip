@@ -386,20 +386,31 @@ __global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol
 // ---- p = r + beta (p - omega v); on restart rh = r and p = r ----------------
 __global__ __launch_bounds__(NT) void k_kry_update_p(GeoT g, KDev K) {
     const KState *s = K.st;
-    if (s->done) return;
+    const int done = flag_read(&s->done);
     int i = blockIdx.x * BX + threadIdx.x;
     const int restart = s->restart;
     C<double> beta = ld2(s->beta), omega = ld2(s->omega);
+    C<double> r[KRY], pv[KRY], vv[KRY];
+#pragma unroll
     for (int rr = 0; rr < KRY; ++rr) {
         int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
         if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
-        C<double> r = K.r[p];
+        r[rr] = K.r[p];
+        pv[rr] = K.p[p];
+        vv[rr] = K.v[p];
+    }
+    if (flag_set(done)) return;
+#pragma unroll
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
+        size_t p = (size_t)j * g.M + i;
         if (restart) {
-            K.rh[p] = r;
-            K.p[p] = r;
+            K.rh[p] = r[rr];
+            K.p[p] = r[rr];
         } else {
-            K.p[p] = cadd(r, cmul(beta, csub(K.p[p], cmul(omega, K.v[p]))));
+            K.p[p] = cadd(r[rr], cmul(beta, csub(pv[rr], cmul(omega, vv[rr]))));
         }
     }
 }
@@ -425,10 +436,10 @@ __global__ __launch_bounds__(NT) void k_kry_matvec_alpha(GeoT g, double H, doubl
 }
 
 __global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K, int nb) {
-    if (K.st->done) return;
+    const int done = flag_read(&K.st->done);
     double tot[2];
     finalize_sums<2>(K.partials, nb, tot);
-    if (threadIdx.x || threadIdx.y) return;
+    if (flag_set(done) || threadIdx.x || threadIdx.y) return;
     KState *s = K.st;
     s->restart = 0;
     st2(s->alpha, cdivc(ld2(s->rho), cmk(tot[0], tot[1])));
@@ -436,15 +447,26 @@ __global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K, int nb) {
 
 // ---- s = r - alpha v, partial ||s||^2 ----------------------------------------
 __global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K) {
-    if (K.st->done) return;
+    const int done = flag_read(&K.st->done);
     int i = blockIdx.x * BX + threadIdx.x;
-    double v[1] = {0.0};
+    const C<double> alpha = ld2(K.st->alpha);
+    C<double> r[KRY], vv[KRY];
+#pragma unroll
     for (int rr = 0; rr < KRY; ++rr) {
         int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
         if (i > g.N || j > g.N) continue;
         size_t p = (size_t)j * g.M + i;
-        C<double> alpha = ld2(K.st->alpha);
-        C<double> sp = csub(K.r[p], cmul(alpha, K.v[p]));
+        r[rr] = K.r[p];
+        vv[rr] = K.v[p];
+    }
+    if (flag_set(done)) return;
+    double v[1] = {0.0};
+#pragma unroll
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
+        size_t p = (size_t)j * g.M + i;
+        C<double> sp = csub(r[rr], cmul(alpha, vv[rr]));
         K.s[p] = sp;
         v[0] += sp.x * sp.x + sp.y * sp.y;
     }
@@ -452,10 +474,10 @@ __global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K) {
 }
 
 __global__ __launch_bounds__(NT) void k_kry_s_fin(KDev K, int nb) {
-    if (K.st->done) return;
+    const int done = flag_read(&K.st->done);
     double tot[1];
     finalize_sums<1>(K.partials, nb, tot);
-    if (threadIdx.x || threadIdx.y) return;
+    if (flag_set(done) || threadIdx.x || threadIdx.y) return;
     KState *s = K.st;
     s->halfsteps += 1;
     s->snorm2 = tot[0];
@@ -489,30 +511,34 @@ __global__ __launch_bounds__(NT) void k_kry_matvec_omega(GeoT g, double H, doubl
 }
 
 __global__ __launch_bounds__(NT) void k_kry_omega_fin(KDev K, int nb) {
-    if (K.st->stop) return;
+    const int stop = flag_read(&K.st->stop);
     double tot[3];
     finalize_sums<3>(K.partials, nb, tot);
-    if (threadIdx.x || threadIdx.y) return;
+    if (flag_set(stop) || threadIdx.x || threadIdx.y) return;
     st2(K.st->omega, cdivc(cmk(tot[0], tot[1]), cmk(tot[2], 0.0)));
 }
 
 // ---- x += alpha ph + omega sh; r = s - omega t; partials ||r||^2, (rh, r) -----
 __global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
     const KState *s = K.st;
-    if (s->done) return;
-    int half = s->half_exit;
+    const int done = flag_read(&s->done);
+    const int half = s->half_exit;
+    const C<double> alpha = ld2(s->alpha), omega = ld2(s->omega);
     int i = blockIdx.x * BX + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
     for (int rr = 0; rr < KRY; ++rr) {
         int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
-        if (i > g.N || j > g.N) continue;
-        size_t p = (size_t)j * g.M + i;
-        C<double> alpha = ld2(s->alpha);
+        const bool in = i <= g.N && j <= g.N;
+        size_t p = in ? (size_t)j * g.M + i : 0;
+        // the first row's fields are requested before the flag is tested
+        const C<double> xp = K.x[p], php = K.ph[p];
+        if (rr == 0 && flag_set(done)) return;
+        if (!in) continue;
         if (half) {
-            K.x[p] = cadd(K.x[p], cmul(alpha, K.ph[p]));
+            K.x[p] = cadd(xp, cmul(alpha, php));
         } else {
-            C<double> omega = ld2(s->omega);
-            K.x[p] = cadd(K.x[p], cadd(cmul(alpha, K.ph[p]), cmul(omega, K.sh[p])));
+            K.x[p] = cadd(xp, cadd(cmul(alpha, php), cmul(omega, K.sh[p])));
             C<double> rp = csub(K.s[p], cmul(omega, K.t[p]));
             K.r[p] = rp;
             C<double> a = K.rh[p];
@@ -526,16 +552,18 @@ __global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
 
 __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
     KState *s = K.st;
-    if (s->done) return;
-    if (s->half_exit) {
+    const int done = flag_read(&s->done);
+    const int half = s->half_exit;
+    double tot[3];
+    finalize_sums<3>(K.partials, nb, tot);     // unused after a half step
+    if (flag_set(done)) return;
+    if (half) {
         if (threadIdx.x == 0 && threadIdx.y == 0) {
             s->done = 1;
             s->stop = 1;
         }
         return;
     }
-    double tot[3];
-    finalize_sums<3>(K.partials, nb, tot);
     if (threadIdx.x || threadIdx.y) return;
     s->halfsteps += 1;
     s->rnorm2 = tot[0];
