@@ -95,6 +95,7 @@ def lib():
             "orc_grid_plan": [P, P],
             "orc_vcycle": [P, P, P],
             "orc_bicgstab": [P, P, P, d, i, i, P, P, i],
+            "orc_bicgstab_ex": [P, P, P, d, i, i, P, P, i, i],
             "orc_grid_override_level": [P, i, i, d, d, i, i],
         }
         for name, args in sig.items():
@@ -104,6 +105,7 @@ def lib():
         _lib.orc_grid_create.restype = P
         _lib.orc_lu_factor.restype = i
         _lib.orc_bicgstab.restype = i
+        _lib.orc_bicgstab_ex.restype = i
         _lib.orc_grid_override_level.restype = i
     return _lib
 
@@ -283,15 +285,17 @@ class Grid:
         return u
 
     def bicgstab(self, b, rtol=1e-6, maxit=500, precond=PREC_VCYCLE, x0=None,
-                 history=False):
+                 history=False, force_breakdown_at=0):
+        # force_breakdown_at = K > 0: the breakdown restart (rhat = r) is taken
+        # at the start of iteration K + 1 whatever rho is (restart-path tests)
         b, bp = _c(b, np.complex128)
         x = np.zeros_like(b) if x0 is None else np.array(x0, np.complex128, order="C")
         info = _Info()
         cap = 4 * maxit + 8
         hist = np.zeros(cap, np.float64)
-        lib().orc_bicgstab(self._ptr, bp, x.ctypes.data_as(ctypes.c_void_p), rtol,
-                           maxit, precond, ctypes.byref(info),
-                           hist.ctypes.data_as(ctypes.c_void_p), cap)
+        lib().orc_bicgstab_ex(self._ptr, bp, x.ctypes.data_as(ctypes.c_void_p), rtol,
+                              maxit, precond, ctypes.byref(info),
+                              hist.ctypes.data_as(ctypes.c_void_p), cap, int(force_breakdown_at))
         out = dict(iters=info.halfsteps / 2.0, halfsteps=info.halfsteps,
                    rel_res=info.rel_res, restarts=info.restarts,
                    status=info.status, vcycles=info.vcycles)

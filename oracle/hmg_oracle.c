@@ -559,6 +559,13 @@ int orc_bicgstab(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
                  int maxit, int precond, orc_info *info,
                  double *res_hist, int hist_cap)
 {
+    return orc_bicgstab_ex(g, b, x, rtol, maxit, precond, info, res_hist, hist_cap, 0);
+}
+
+int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
+                    int maxit, int precond, orc_info *info,
+                    double *res_hist, int hist_cap, int force_breakdown_at)
+{
     int    n = g->n;
     double h = g->h;
     size_t m = (size_t)(n + 2) * (n + 2);
@@ -594,7 +601,8 @@ int orc_bicgstab(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
         }
         if (half >= 2 * maxit) break;
         orc_cplx rho = dotc(m, rh, r);
-        if (cabs(rho) <= 1e-14 * nrm2(m, rh) * rn) {
+        int forced = force_breakdown_at > 0 && half == 2 * force_breakdown_at;
+        if (cabs(rho) <= 1e-14 * nrm2(m, rh) * rn || forced) {
             memcpy(rh, r, m * sizeof(orc_cplx));
             memset(p, 0, m * sizeof(orc_cplx));
             memset(v, 0, m * sizeof(orc_cplx));

@@ -107,6 +107,11 @@ typedef struct {
 int orc_bicgstab(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
                  int maxit, int precond, orc_info *info,
                  double *res_hist, int hist_cap);
+/* The same, with force_breakdown_at = K > 0 taking the breakdown branch at
+ * the start of iteration K + 1 whatever rho is (tests of the restart path). */
+int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
+                    int maxit, int precond, orc_info *info,
+                    double *res_hist, int hist_cap, int force_breakdown_at);
 
 #ifdef __cplusplus
 }

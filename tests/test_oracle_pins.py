@@ -169,6 +169,35 @@ def test_point_source_zero_initial_guess():
     assert info["vcycles"] == info["halfsteps"]
 
 
+@pytest.mark.parametrize("K", [2, 5])
+def test_forced_breakdown_restart_equals_fresh_solve(K):
+    """The breakdown branch (rhat = p = r, rho_old = alpha = omega = 1) is a
+    fresh Bi-CGSTAB from the current iterate: forcing it after iteration K
+    must give, from half step 2K on, the history of a new solve started at
+    x_K (up to the drift between the recursive and the true residual), keep
+    the first 2K half steps unchanged, and still converge.  A restart that
+    kept the old direction p, or the old omega, fails the comparison."""
+    h, k, f = _point63()
+    g = oracle.Grid(h, k, variant=oracle.SL)
+    _, plain = g.bicgstab(f, rtol=1e-6, maxit=300, history=True)
+    _, forced = g.bicgstab(f, rtol=1e-6, maxit=300, history=True, force_breakdown_at=K)
+    xK, _ = g.bicgstab(f, rtol=1e-30, maxit=K)
+    _, fresh = g.bicgstab(f, rtol=1e-6, maxit=300, x0=xK, history=True)
+    hp, hf, hr = plain["history"], forced["history"], fresh["history"]
+    assert forced["status"] == oracle.OK and forced["restarts"] == 1 and plain["restarts"] == 0
+    np.testing.assert_array_equal(hf[: 2 * K + 1], hp[: 2 * K + 1])
+    np.testing.assert_allclose(hf[2 * K: 2 * K + 8], hr[:8], rtol=1e-6)
+    assert abs(np.log(hp[2 * K + 4] / hf[2 * K + 4])) > 1e-3   # the branch changes the iteration
+
+
+def _point63():
+    n = 63
+    k = np.full((n + 2, n + 2), 10 * math.pi)
+    f = np.zeros((n + 2, n + 2), complex)
+    f[32, 32] = 1.0
+    return 1 / 64, k, f
+
+
 # ---------------------------------------------------------------------------
 # Transfers (Section 5: bilinear interpolation, full weighting)
 # ---------------------------------------------------------------------------
