@@ -107,7 +107,13 @@ typedef struct {
                                 0: run the bottom levels in one workgroup     */
     int    relax_order;      /* hmg_order, default HMG_ORDER_COLOUR; HMG_ORDER_LEX
                                 runs every level with the one-pass schedule   */
-    int    reserved[3];
+    int    breakdown_at;     /* K > 0: the Bi-CGSTAB breakdown restart (rhat =
+                                p = r, scalars reset) is taken after iteration
+                                K whatever rho is, to exercise the restart
+                                path (Section 6 names no breakdown rule; the
+                                library restarts when |rho| <= 1e-14 ||rhat||
+                                ||r||); 0: off (default)                       */
+    int    reserved[2];
 } hmg_opts;
 
 #define HMG_MAX_LEVELS 24

@@ -38,6 +38,7 @@ struct KState {
     int    stop;         // done || half_exit: later kernels of the iteration skip
     int    restarts;
     int    hist_cap;
+    int    force_bd;     // > 0: iteration after which a breakdown is forced
 };
 
 // Device pointers of one solve slot (finest-level Krylov vectors).
@@ -146,7 +147,7 @@ void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m
 // ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
 int  krylov_nblocks(const Geo &g);
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given,
-              double rtol, int maxhalf);
+              double rtol, int maxhalf, int force_bd);
 void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 // the single-block finalisations after a fused product (nb partial blocks)

@@ -354,7 +354,8 @@ __global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, c
     block_partials<2>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol, int maxhalf, int hist_cap) {
+__global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol, int maxhalf, int hist_cap,
+                                                     int force_bd) {
     double tot[2];
     finalize_sums<2>(K.partials, nb, tot);
     if (threadIdx.x || threadIdx.y) return;
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol
     s->half_exit = 0;
     s->restarts = 0;
     s->hist_cap = hist_cap;
+    s->force_bd = force_bd;
     double rel = sqrt(tot[1]) / bn;
     if (hist_cap > 0) K.hist[0] = rel;
     s->done = (rel <= rtol) ? 1 : 0;
@@ -582,8 +584,9 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
     }
     C<double> rho_new = cmk(tot[1], tot[2]);
     double mag = sqrt(rho_new.x * rho_new.x + rho_new.y * rho_new.y);
-    if (mag <= 1e-14 * sqrt(s->rhat_norm2) * rn) {
-        // breakdown: restart with rh = r
+    if (mag <= 1e-14 * sqrt(s->rhat_norm2) * rn || s->halfsteps == 2 * s->force_bd) {
+        // breakdown (or the one forced after iteration force_bd): restart
+        // with rh = r
         s->restart = 1;
         s->restarts += 1;
         s->rho[0] = tot[0]; s->rho[1] = 0.0;
@@ -651,13 +654,13 @@ int krylov_nblocks(const Geo &g) {
 static inline void hk(const Geo &g, double &H, double &ih2) { H = g.H; ih2 = 1.0 / (g.H * g.H); }
 
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given, double rtol,
-              int maxhalf) {
+              int maxhalf, int force_bd) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
     k_kry_init<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, x0_given);
     // the history buffer holds maxhalf + 2 entries (allocated by the caller)
-    k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2);
+    k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2, force_bd);
 }
 void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K) {
     k_kry_update_p<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));

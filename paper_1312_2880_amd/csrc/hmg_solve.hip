@@ -162,7 +162,7 @@ static hmg_status run_begin(SolveRun &R, int x0_given) {
     hmg_grid *g = R.g;
     hmg_status st = ensure_hist(*R.S, R.maxit);
     if (st) return st;
-    kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit);
+    kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit, g->opts.breakdown_at);
     HIPCHK(hipGetLastError());
     R.inflight = 0;
     R.issued = 0;

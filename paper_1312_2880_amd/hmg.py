@@ -50,7 +50,7 @@ class Opts(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("one_pass_kernels", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("bottom_dense", ctypes.c_int), ("relax_order", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("breakdown_at", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class Plan(ctypes.Structure):

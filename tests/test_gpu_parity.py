@@ -727,6 +727,30 @@ def test_solve_history_matches_oracle_point_source(ctx, hmg):
     assert abs(info[0]["iters"] - info_ref["iters"]) <= count_margin(info_ref["iters"])
 
 
+@pytest.mark.parametrize("K", [3, 7])
+def test_forced_breakdown_restart_matches_oracle(ctx, hmg, K):
+    """The Bi-CGSTAB breakdown restart (rhat = p = r, scalars reset), forced
+    after iteration K by the host option: the GPU history follows the
+    oracle's (forced at the same point) through the restart, both restart
+    once, converge, and the GPU solution's true residual (recomputed by the
+    oracle) meets the tolerance."""
+    say(f"case forced breakdown K={K}")
+    h, k, f = inputs.workload_const_point(63)
+    g = hmg.Grid(ctx, h, k, f, variant=0, breakdown_at=K)
+    x, info = g.solve(rtol=1e-6, maxit=300)
+    hist = g.history(0)
+    _, ref = oracle.Grid(h, k, variant=0).bicgstab(f, rtol=1e-6, maxit=300, history=True,
+                                                    force_breakdown_at=K)
+    assert info[0]["status"] == hmg.OK and ref["status"] == oracle.OK
+    assert info[0]["restarts"] == 1 and ref["restarts"] == 1
+    np.testing.assert_allclose(hist[:12], ref["history"][:12], rtol=1e-7)
+    np.testing.assert_allclose(hist[2 * K - 2: 2 * K + 6], ref["history"][2 * K - 2: 2 * K + 6], rtol=1e-6)
+    assert abs(info[0]["iters"] - ref["iters"]) <= count_margin(ref["iters"])
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+    g.close()
+
+
 def test_single_level_exact_preconditioner_half_step(ctx, hmg):
     """n = coarsest_n: the V-cycle is the exact solve of L (HYB), so
     Bi-CGSTAB stops after half an iteration."""
@@ -886,6 +910,8 @@ def test_invalid_arguments(ctx, hmg):
     assert [p["n"] for p in hmg.Grid(ctx, 1 / 80, k).plan()] == [79, 39, 19, 9, 4]
     with pytest.raises(hmg.HmgError):
         hmg.Grid(ctx, 1 / 80, k, coarsest_n=32)        # coarsest_n above 31
+    with pytest.raises(hmg.HmgError):
+        hmg.Grid(ctx, 1 / 80, k, breakdown_at=-1)      # forced breakdown index below 0
     k = np.full((65, 65), 5.0)
     k[3, 3] = 0.0
     with pytest.raises(hmg.HmgError):
