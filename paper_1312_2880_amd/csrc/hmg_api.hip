@@ -772,8 +772,8 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         // of its result when the caller asks for it
         if (mv && l == 0 && !u0 && !f64 && gs_up_mv_ok(g->prec, L.geo) &&
             gs_up_mv_blocks(L.geo) <= S.K.nblocks) {
-            launch_gs_up_mv(s, mv->kind, L.geo, L.k, pl.sigma_relax[l], f, e, dst, mv->out, mv->dot, mv->partials,
-                            skip);
+            launch_gs_up_mv(s, mv->kind, L.geo, L.k, pl.sigma_relax[l], f, e, mv->no_z ? nullptr : dst, mv->out,
+                            mv->dot, mv->partials, skip);
             mv->blocks = gs_up_mv_blocks(L.geo);
             mv->fused = true;
             return dst;
@@ -838,6 +838,14 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
     launch_prolong_add(g->prec, s, L.geo, e, u, skip);
     relax(g, l, f, u, pl.post[l], false, s, skip);
     return u;
+}
+
+// The conditions under which vc_fast hands level 0's up kernel to
+// launch_gs_up_mv for an FP64 solve.
+bool vcycle_forms_products(const hmg_grid *g, const Slot &S) {
+    const Geo &g0 = g->lev[0].geo;
+    return !one_pass(g) && g->prec == P64 && g->lb != 0 && g->lev[0].mode == LM_GS_FUSED && g0.n > 511 &&
+           gs_up_mv_ok(g->prec, g0) && gs_up_mv_blocks(g0) <= S.K.nblocks;
 }
 
 // z = B_V r on FP64 device fields r, z (finest level).

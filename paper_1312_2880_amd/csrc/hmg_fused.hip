@@ -428,6 +428,7 @@ __device__ __forceinline__ void gs_load(int tid, int ox, int oy, int N, int M, c
 //   KIND 2: (mvo, dot), (mvo, mvo)     (t = L s^, (t, s) and (t, t), for omega)
 // with (a, b) = sum conj(a) b, written to partials[q * blocks + block] as the
 // separate product kernels do.  The product kernel and its launch go away.
+// uo may be null: then only mvo and the sums leave the kernel.
 // ===========================================================================
 template <bool IN, int KIND>
 __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, int oy, int N, int M, int Mc,
@@ -502,7 +503,7 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
             } else {
                 v = U[l];
             }
-            if (TL::ring(lx, ly, 0)) uo[(size_t)j * M + i] = v;
+            if (uo && TL::ring(lx, ly, 0)) uo[(size_t)j * M + i] = v;
         }
     __syncthreads();
     // the product with L (sigma = 0) on the tile and the partial sums

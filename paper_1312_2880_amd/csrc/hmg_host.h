@@ -89,7 +89,8 @@ hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> 
 size_t     estimate_footprint(int n, const hmg_opts &o);
 // A Bi-CGSTAB product the finest up kernel may take over: out = L z with the
 // partial sums of kind 1 ((dot, out)) or kind 2 ((out, dot), (out, out)) in
-// partials, laid out for `blocks` blocks.  fused reports whether it did.
+// partials, laid out for `blocks` blocks.  fused reports whether it did; with
+// no_z the fused kernel does not store z itself.
 struct MvFuse {
     int         kind = 0;
     void       *out = nullptr;
@@ -97,6 +98,11 @@ struct MvFuse {
     double     *partials = nullptr;
     int         blocks = 0;
     bool        fused = false;
+    bool        no_z = false;
 };
+// Whether the finest up kernel of S's V-cycles forms the Krylov products
+// (then the solve keeps its x update in the preconditioner's input space:
+// kry_update_yr / kry_fold, and the V-cycle outputs are not stored).
+bool       vcycle_forms_products(const hmg_grid *g, const Slot &S);
 void       enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s,
                           const int *skip, MvFuse *mv = nullptr);

@@ -115,8 +115,8 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
 // The finest up kernel of an FP64 solve fused with the Bi-CGSTAB product
 // (kind 1: v = L uo with the partials of (dot, v); kind 2: t = L uo with the
 // partials of (t, dot) and (t, t)); partials laid out for gs_up_mv_blocks(g)
-// blocks.  Only where gs_up_mv_ok (FP64 level without a stored iterate, big
-// tiles).
+// blocks; uo may be null (the iterate is not stored).  Only where gs_up_mv_ok
+// (FP64 level without a stored iterate, big tiles).
 bool gs_up_mv_ok(Prec p, const Geo &g);
 int  gs_up_mv_blocks(const Geo &g);
 void launch_gs_up_mv(hipStream_t s, int kind, const Geo &g, const void *k, double sa, const void *f,
@@ -158,6 +158,11 @@ void kry_omega_fin(hipStream_t s, const Krylov &K, int nb);
 void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K);
+// The x update kept in the preconditioner's input space (y in K.ph):
+// y += alpha p + omega s with r and its sums as kry_update_xr; kry_fold
+// adds z = B y (in K.sh) to x and clears y.
+void kry_update_yr(hipStream_t s, const Geo &g, const Krylov &K);
+void kry_fold(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 void kry_restart_from_true(hipStream_t s, const Krylov &K);
 

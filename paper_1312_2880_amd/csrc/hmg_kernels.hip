@@ -552,6 +552,55 @@ __global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
     if (!half) block_partials<3>(v, K.partials);
 }
 
+// ---- the same with the update of x kept in the preconditioner's input space:
+// y += alpha p + omega s (y in the p^ buffer), x = x + B y formed once at the
+// end (k_kry_fold).  B is linear and fixed, so x is the same as with
+// x += alpha p^ + omega s^ in exact arithmetic, and p^, s^ need not be stored.
+__global__ __launch_bounds__(NT) void k_kry_update_yr(GeoT g, KDev K) {
+    const KState *s = K.st;
+    const int done = flag_read(&s->done);
+    const int half = s->half_exit;
+    const C<double> alpha = ld2(s->alpha), omega = ld2(s->omega);
+    C<double> *y = K.ph;
+    int i = blockIdx.x * BX + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        const bool in = i <= g.N && j <= g.N;
+        size_t p = in ? (size_t)j * g.M + i : 0;
+        // the first row's fields are requested before the flag is tested
+        const C<double> yp = y[p], pp = K.p[p];
+        if (rr == 0 && flag_set(done)) return;
+        if (!in) continue;
+        if (half) {
+            y[p] = cadd(yp, cmul(alpha, pp));
+        } else {
+            const C<double> sp = K.s[p];
+            y[p] = cadd(yp, cadd(cmul(alpha, pp), cmul(omega, sp)));
+            C<double> rp = csub(sp, cmul(omega, K.t[p]));
+            K.r[p] = rp;
+            C<double> a = K.rh[p];
+            v[0] += rp.x * rp.x + rp.y * rp.y;
+            v[1] += a.x * rp.x + a.y * rp.y;  // conj(rh) r
+            v[2] += a.x * rp.y - a.y * rp.x;
+        }
+    }
+    if (!half) block_partials<3>(v, K.partials);
+}
+
+// ---- x += z (z = B y in the s^ buffer), y = 0 --------------------------------
+__global__ __launch_bounds__(NT) void k_kry_fold(GeoT g, KDev K) {
+    int i = blockIdx.x * BX + threadIdx.x;
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
+        size_t p = (size_t)j * g.M + i;
+        K.x[p] = cadd(K.x[p], K.sh[p]);
+        K.ph[p] = cmk(0.0, 0.0);
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
     KState *s = K.st;
     const int done = flag_read(&s->done);
@@ -705,6 +754,14 @@ void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K) {
     KDev d = kdev(K);
     k_kry_update_xr<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
     k_kry_iter_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_update_yr(hipStream_t s, const Geo &g, const Krylov &K) {
+    KDev d = kdev(K);
+    k_kry_update_yr<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
+    k_kry_iter_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+}
+void kry_fold(hipStream_t s, const Geo &g, const Krylov &K) {
+    k_kry_fold<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));
 }
 void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
     double H, ih2;

@@ -79,12 +79,16 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     const int *stop = &S.K.st->stop;
     kry_update_p(s, g0, S.K);
     // v = L p^ and t = L s^ come from the V-cycle's last kernel where it can
-    // form them, else from kernels of their own
+    // form them, else from kernels of their own.  Where it can, p^ and s^
+    // are not stored either: x advances as x + B y with y += alpha p +
+    // omega s (B is linear and fixed), folded in when the solve ends.
+    const bool ym = vcycle_forms_products(g, S);
     MvFuse mv;
     mv.kind = 1;
     mv.out = S.K.v;
     mv.dot = S.K.rh;
     mv.partials = S.K.partials;
+    mv.no_z = ym;
     enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop, &mv);
     if (mv.fused) kry_alpha_fin(s, S.K, mv.blocks);
     else kry_matvec_alpha(s, g0, g->k0, S.K);
@@ -94,10 +98,12 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     mv.out = S.K.t;
     mv.dot = S.K.s;
     mv.partials = S.K.partials;
+    mv.no_z = ym;
     enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop, &mv);
     if (mv.fused) kry_omega_fin(s, S.K, mv.blocks);
     else kry_matvec_omega(s, g0, g->k0, S.K);
-    kry_update_xr(s, g0, S.K);
+    if (ym) kry_update_yr(s, g0, S.K);
+    else kry_update_xr(s, g0, S.K);
 }
 
 static hmg_status iteration_graph(hmg_grid *g, Slot &S) {
@@ -163,6 +169,8 @@ static hmg_status run_begin(SolveRun &R, int x0_given) {
     hmg_status st = ensure_hist(*R.S, R.maxit);
     if (st) return st;
     kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit, g->opts.breakdown_at);
+    if (vcycle_forms_products(g, *R.S))   // y = 0 (the x update in the preconditioner's input space)
+        launch_fill_zero(P64, R.s, R.S->K.ph, (size_t)g->lev[0].geo.M * g->lev[0].geo.M, nullptr);
     HIPCHK(hipGetLastError());
     R.inflight = 0;
     R.issued = 0;
@@ -187,6 +195,11 @@ static hmg_status run_issue(SolveRun &R) {
 static hmg_status run_finish(SolveRun &R, hmg_solve_info *info) {
     HIPCHK(hipStreamSynchronize(R.s));
     Slot &S = *R.S;
+    if (vcycle_forms_products(R.g, S)) {
+        // x += B y, y = 0
+        enqueue_vcycle(R.g, S, S.K.ph, S.K.sh, R.s, nullptr);
+        kry_fold(R.s, R.g->lev[0].geo, S.K);
+    }
     kry_true_residual(R.s, R.g->lev[0].geo, R.g->k0, S.K);
     HIPCHK(hipMemcpyAsync(&R.hs[0], S.K.st, sizeof(KState), hipMemcpyDeviceToHost, R.s));
     HIPCHK(hipStreamSynchronize(R.s));

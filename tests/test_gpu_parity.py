@@ -712,6 +712,44 @@ def test_solve_layered_1023_hyb_matches_oracle(ctx, hmg):
     assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
 
 
+def test_solve_iterate_after_fixed_iterations_1023(ctx, hmg):
+    """The FP64 1023^2 solve keeps its x update in the preconditioner's input
+    space (y += alpha p + omega s, x = x0 + B y at the end; B is linear, so
+    this is the iterate of Section 6 up to rounding).  After 5 iterations
+    (not converged) the GPU iterate equals the oracle's, which adds
+    alpha p^ + omega s^ every iteration; a second solve from that iterate
+    (x0 given) continues from it."""
+    say("case solve layered1023 iterate after 5 iterations")
+    h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=2)
+    x5, info = g.solve(rtol=1e-12, maxit=5)
+    assert info[0]["status"] == hmg.ERR_NOT_CONVERGED and info[0]["iters"] == 5.0
+    og = oracle.Grid(h, k, variant=2)
+    x5_ref, info_ref = og.bicgstab(f, rtol=1e-12, maxit=5)
+    assert rel(x5[0], x5_ref) <= 1e-9
+    assert abs(info[0]["rel_res_true"] - info_ref["rel_res"]) <= 1e-9 * info_ref["rel_res"]
+    d_x = dev(x5[0])
+    info2 = g.solve_dev(d_x, d_b=dev(f), x0=True, rtol=1e-6, maxit=400, stream=torch.cuda.current_stream())
+    assert info2["status"] == hmg.OK
+    r = oracle.residual(h, k, 0.0, f, host(d_x))
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+    g.close()
+
+
+def test_tight_tolerance_true_residual_1023(ctx, hmg):
+    """rtol = 1e-10 on the 1023^2 FP64 solve (the path whose x is folded in
+    at the end): the returned iterate meets the tolerance by the oracle's
+    residual, whatever restarts the true-residual check needed."""
+    say("case solve layered1023 rtol 1e-10")
+    h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=2)
+    x, info = g.solve(rtol=1e-10, maxit=1500)
+    assert info[0]["status"] == hmg.OK and info[0]["rel_res_true"] <= 1e-10
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1.5e-10
+    g.close()
+
+
 def test_solve_history_matches_oracle_point_source(ctx, hmg):
     """SL-V on the 63^2 point source: residual history and final count."""
     say("case solve history point63")
