@@ -48,8 +48,10 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
       gs_down     read f, k; write coarse f (+ write u0)     N (c + r) + Nc c   (+ N c)
       gs_up       read f, k, coarse e (+ read u0 on the      N (2c + r) + Nc c  (+ N c / 2)
                   black nodes); write u
-      gs_up_mv    gs_up without u0, then read the inner      N (4c + r) + Nc c
-                  product's other vector, write L u
+      gs_up_mv    gs_up without u0 and without storing u,    N (3c + r) + Nc c
+                  then read the inner product's other
+                  vector, write L u (as the FP64 solve
+                  runs it)
       kacz_tb     read f, k, u; write u                      N (3c + r)
     (FP64 levels store the pre-smoothed iterate u0 for the up kernel, which
     needs it on the black nodes only: the red half-sweep overwrites red
@@ -61,7 +63,7 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
     if kind == "gs_up":
         return nodes * (2 * c + r) + coarse_nodes * c + (nodes * c // 2 if stored_u0 else 0)
     if kind == "gs_up_mv":
-        return nodes * (4 * c + r) + coarse_nodes * c
+        return nodes * (3 * c + r) + coarse_nodes * c
     if kind == "kacz_tb":
         return nodes * (3 * c + r)
     raise KeyError(kind)
@@ -152,7 +154,7 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None, lex=False):
                     ("hbm", algorithmic_bytes("gs_down", nodes, cnodes, cb, rb, st_u0)), None))
         if mv:
             out.append(("gs_up_mv", 0, lambda q, st: g.op_gs_up_product(
-                0, sa, 1 + q % 2, bufs[q % sets]["f"], bufs[q % sets]["ec"], bufs[q % sets]["uo"],
+                0, sa, 1 + q % 2, bufs[q % sets]["f"], bufs[q % sets]["ec"], None,
                 bufs[q % sets]["mv"], bufs[q % sets]["dot"], None, st), 1,
                 ("hbm", algorithmic_bytes("gs_up_mv", nodes, cnodes, cb, rb)), None))
         else:

@@ -310,6 +310,8 @@ hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma, int confi
  *   kind 1: Re, Im of sum_p conj(dot_p) mv_p, then 0
  *   kind 2: Re, Im of sum_p conj(mv_p) dot_p, then sum_p |mv_p|^2.
  * d_sums may be NULL: the sums are then left unformed (the kernel alone).
+ * d_uo may be NULL: uo is then not stored (as in the solve, which keeps its
+ * x update in the preconditioner's input space).
  * FP64 grids only (HMG_ERR_INVALID otherwise).  Uses the grid's reduction
  * scratch, so it must not overlap a solve on the same grid.  Outputs must
  * not alias inputs or each other. */

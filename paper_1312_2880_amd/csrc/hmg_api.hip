@@ -1006,12 +1006,12 @@ extern "C" hmg_status hmg_op_gs_up_product_dev(hmg_grid *g, int level, double si
     if (st) return st;
     if (g->prec != P64) return hmg_fail(HMG_ERR_INVALID, "the fused product runs on FP64 grids only");
     if (kind != 1 && kind != 2) return hmg_fail(HMG_ERR_INVALID, "kind must be 1 or 2");
-    if (!d_f || !d_ec || !d_uo || !d_mv || !d_dot) return hmg_fail(HMG_ERR_INVALID, "null field");
+    if (!d_f || !d_ec || !d_mv || !d_dot) return hmg_fail(HMG_ERR_INVALID, "null field");
     const void *ins[] = {d_f, d_ec, d_dot};
     for (const void *in : ins)
-        if (in == d_uo || in == d_mv || (d_sums && in == d_sums))
+        if ((d_uo && in == d_uo) || in == d_mv || (d_sums && in == d_sums))
             return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs)");
-    if (d_uo == d_mv || (d_sums && (d_uo == d_sums || d_mv == d_sums)))
+    if ((d_uo && (d_uo == d_mv || d_uo == d_sums)) || (d_sums && d_mv == d_sums))
         return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias each other)");
     const Level &L = g->lev[level];
     Krylov &K = g->slot[0].K;

@@ -346,6 +346,11 @@ def test_fused_gs_up_with_product_matches_oracle(ctx, hmg, n, klo, khi, kind):
     g.op_gs_up_product(0, 0.5, kind, dev(f), dev(ec), d_uo2, d_mv2, dev(dot), None)
     assert np.array_equal(host(d_uo2), host(d_uo)) and np.array_equal(host(d_mv2), host(d_mv))
     assert np.array_equal(d_sums.cpu().numpy(), got)
+    # without d_uo (as the solve runs it) the product and the sums are the same
+    d_mv3 = dev(np.zeros_like(f))
+    d_sums3 = torch.full((3,), 7.0, dtype=torch.float64, device="cuda")
+    g.op_gs_up_product(0, 0.5, kind, dev(f), dev(ec), None, d_mv3, dev(dot), d_sums3)
+    assert np.array_equal(host(d_mv3), host(d_mv)) and np.array_equal(d_sums3.cpu().numpy(), got)
 
 
 def test_fused_gs_down_without_iterate_output(ctx, hmg):
