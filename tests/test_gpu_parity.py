@@ -741,6 +741,35 @@ def test_solve_iterate_after_fixed_iterations_1023(ctx, hmg):
     g.close()
 
 
+def test_vcycle_is_linear_1023(ctx, hmg):
+    """B (the V-cycle from a zero guess, Section 5) is a fixed linear map,
+    which the FP64 solve relies on when it forms x + B y once instead of
+    adding B p and B s every iteration: B(f1 + c f2) = B f1 + c B f2 up to
+    rounding on the 1023^2 hierarchy."""
+    say("case vcycle linearity layered1023")
+    h, k, _ = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, variant=2)
+    f1, f2 = inputs.random_field(1023, 91), inputs.random_field(1023, 92)
+    c = 0.75 - 1.5j
+    z1, z2, z12 = g.vcycle(f1), g.vcycle(f2), g.vcycle(f1 + c * f2)
+    assert rel(z12, z1 + c * z2) <= 1e-12
+    g.close()
+
+
+def test_forced_breakdown_in_the_folded_solve_1023(ctx, hmg):
+    """A breakdown restart inside the 1023^2 FP64 solve (whose x is folded in
+    at the end): the restart leaves y and x alone, and the returned iterate
+    meets the tolerance by the oracle's residual."""
+    say("case solve layered1023 forced breakdown")
+    h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=2, breakdown_at=5)
+    x, info = g.solve(rtol=1e-6, maxit=400)
+    assert info[0]["status"] == hmg.OK and info[0]["restarts"] >= 1
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+    g.close()
+
+
 def test_tight_tolerance_true_residual_1023(ctx, hmg):
     """rtol = 1e-10 on the 1023^2 FP64 solve (the path whose x is folded in
     at the end): the returned iterate meets the tolerance by the oracle's
