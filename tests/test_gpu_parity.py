@@ -741,6 +741,34 @@ def test_solve_iterate_after_fixed_iterations_1023(ctx, hmg):
     g.close()
 
 
+@pytest.mark.parametrize("n", [63, 1023])
+def test_degenerate_starts(ctx, hmg, n):
+    """Degenerate solves: b = 0 gives x = 0 with no iteration (the oracle's
+    count is 0 too), and a start at a converged iterate returns it unchanged
+    with no iteration, on the separate-product path (63^2) and on the folded
+    FP64 path (1023^2)."""
+    say(f"case degenerate starts n={n}")
+    if n == 63:
+        h, k, f = inputs.workload_const_point(63)
+    else:
+        h, k, f = inputs.workload_layered_1023()
+    zero = np.zeros_like(f)
+    g = hmg.Grid(ctx, h, k, zero, variant=2)
+    x, info = g.solve(rtol=1e-6, maxit=50)
+    _, ref = oracle.Grid(h, k, variant=2).bicgstab(zero, rtol=1e-6, maxit=50)
+    assert info[0]["status"] == hmg.OK and info[0]["iters"] == 0.0 == ref["iters"]
+    assert not np.any(x[0])
+    g.close()
+    g = hmg.Grid(ctx, h, k, f, variant=2)
+    xs, info = g.solve(rtol=1e-6, maxit=400)
+    assert info[0]["status"] == hmg.OK
+    d_x = dev(xs[0])
+    info2 = g.solve_dev(d_x, d_b=dev(f), x0=True, rtol=1e-6, maxit=400, stream=torch.cuda.current_stream())
+    assert info2["status"] == hmg.OK and info2["iters"] == 0.0
+    assert np.array_equal(host(d_x), xs[0])
+    g.close()
+
+
 def test_vcycle_is_linear_1023(ctx, hmg):
     """B (the V-cycle from a zero guess, Section 5) is a fixed linear map,
     which the FP64 solve relies on when it forms x + B y once instead of
