@@ -339,10 +339,13 @@ hmg_status hmg_op_kacz_level_dev(hmg_grid *g, int level, double sigma_relax, dou
  * the whole-level kernel (hmg_op_kacz_level_dev), or -1 when the level is
  * not a Kaczmarz level of the fused schedule. */
 int        hmg_grid_kacz_config(const hmg_grid *g, int level);
-/* Tile side, sweeps per launch and workgroup size of Kaczmarz tile
+/* Tile width, sweeps per launch and workgroup size of Kaczmarz tile
  * configuration `config` (NULL outputs are skipped); returns the number of
  * configurations, or -1 for an unknown one. */
 int        hmg_kacz_tile_config(int config, int *tile, int *sweeps, int *threads);
+/* Tile height of configuration `config` (equal to its width except for the
+ * rectangular ones), or -1 for an unknown one. */
+int        hmg_kacz_tile_height(int config);
 
 #ifdef __cplusplus
 }

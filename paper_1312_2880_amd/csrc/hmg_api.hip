@@ -286,10 +286,10 @@ static void plan_paths(hmg_grid *g) {
             g->lev[l].mode = LM_GS_FUSED;
         } else if (pl.smoother[l] == HMG_SM_KACZ) {
             g->lev[l].mode = LM_KACZ_TILED;
-            // default before tuning: the LDS-staged 16 x 16 tile with 2
+            // default before tuning: the LDS-staged 16 x 8 tile with 2
             // sweeps per launch (1024 threads) if 2 divides both sweep
-            // counts, else one sweep per launch
-            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? 4 : 5;
+            // counts, else one sweep per launch on 16 x 16 tiles
+            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? 7 : 5;
             g->lev[l].kacz_cfg = best;
         }
     }
@@ -1081,4 +1081,9 @@ extern "C" int hmg_kacz_tile_config(int config, int *tile, int *sweeps, int *thr
     if (sweeps) *sweeps = kKaczCfgs[config].sweeps;
     if (threads) *threads = kKaczCfgs[config].threads;
     return KACZ_NCFG;
+}
+
+extern "C" int hmg_kacz_tile_height(int config) {
+    if (config < 0 || config >= KACZ_NCFG) return -1;
+    return kKaczCfgs[config].ty;
 }

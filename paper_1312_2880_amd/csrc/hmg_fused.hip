@@ -685,7 +685,8 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
 }
 
 // ===========================================================================
-// k_kacz_tb: S sweeps of 5-colour Kaczmarz on a TS x TS tile held in LDS
+// k_kacz_tb: S sweeps of 5-colour Kaczmarz on a TS x TY tile (TY = TS unless
+// given) held in LDS
 // with a halo of RH = 10 S (each colour pass moves information two nodes).
 // Pass q (colour q mod 5) updates the rows on tile + (RH - 2q - 1); after it
 // u is exact on tile + (RH - 2q - 2), and after the last pass on the tile
@@ -706,35 +707,35 @@ __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, 
 // formed on tile + 1 and full-weighted to the coarse nodes of the tile (fc),
 // which replaces the separate residual and restriction kernel.
 // ===========================================================================
-template <typename T, int TS0, int S, int NT, bool RESID>
+template <typename T, int TS0, int S, int NT, bool RESID, int TY0 = TS0>
 __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, const T *__restrict__ k,
                                                 const C<double> *__restrict__ ktab, double sig,
                                                 double sigb, const C<T> *__restrict__ f,
                                                 const C<T> *__restrict__ ui, const C<T> *__restrict__ ec,
                                                 C<T> *__restrict__ uo, C<T> *__restrict__ fc, const int *skip) {
     const int sk = flag_read(skip);
-    constexpr int TS = RESID ? TS0 - 4 : TS0;
-    constexpr int RH = 10 * S + (RESID ? 2 : 0), LW = TS + 2 * RH;
+    constexpr int TS = RESID ? TS0 - 4 : TS0, TY = RESID ? TY0 - 4 : TY0;
+    constexpr int RH = 10 * S + (RESID ? 2 : 0), LW = TS + 2 * RH, LH = TY + 2 * RH;
     // f and (k, 1/||a_p||^2) of the region are staged in LDS when they fit
     // next to u
-    constexpr bool STAGE = (size_t)LW * LW * (16 + 16 + 16) <= 160 * 1024;
+    constexpr bool STAGE = (size_t)LW * LH * (16 + 16 + 16) <= 160 * 1024;
     static_assert(STAGE || !RESID, "the fused residual needs the staged region");
-    static_assert(TS % 2 == 0, "tiles start on coarse nodes");
+    static_assert(TS % 2 == 0 && TY % 2 == 0, "tiles start on coarse nodes");
     constexpr int T5 = (LW - 2 + 4) / 5;              // row slots per line and colour
-    constexpr int NSLOT = (LW - 2) * T5;              // slots per colour
+    constexpr int NSLOT = (LH - 2) * T5;              // slots per colour
     constexpr int NM = (NSLOT + NT - 1) / NT;         // slots per thread and colour
-    constexpr int NL = (LW * LW + NT - 1) / NT;       // region cells per thread
+    constexpr int NL = (LW * LH + NT - 1) / NT;       // region cells per thread
     // cells per load batch: about 28 registers each in flight, within the
     // budget of NT threads per workgroup
     constexpr int CHMAX = NT >= 1024 ? 2 : 4;
     constexpr int CH = NL < CHMAX ? NL : CHMAX;
-    __shared__ C<double> U[LW * LW];
-    __shared__ C<double> FS[STAGE ? LW * LW : 1];
-    __shared__ C<double> KS[STAGE ? LW * LW : 1];
+    __shared__ C<double> U[LW * LH];
+    __shared__ C<double> FS[STAGE ? LW * LH : 1];
+    __shared__ C<double> KS[STAGE ? LW * LH : 1];
     const int tid = threadIdx.x;
     int tx, ty;
     xcd_tile(tx, ty);
-    const int x0 = tx * TS, y0 = ty * TS;
+    const int x0 = tx * TS, y0 = ty * TY;
     const int ox = x0 - RH, oy = y0 - RH;
     const int N = g.N, M = g.M, Mc = N / 2 + 1;
     // FP64 fields with a row table: f and (k, 1/||a_p||^2) go straight from
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         const int wbase = tid & ~63;
         for (int kk = 0; kk < NL; ++kk) {
             const int q = tid + NT * kk;
-            if (q < LW * LW) {
+            if (q < LW * LH) {
                 const int i = min(max(ox + q % LW, 0), N), j = min(max(oy + q / LW, 0), N);
                 const size_t p = (size_t)j * M + i;
                 __builtin_amdgcn_global_load_lds((const void *)(f + p),
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
 #pragma unroll
         for (int s = 0; s < CH; ++s) {
             const int q = tid + NT * (b0 + s);
-            if (q >= LW * LW) continue;
+            if (q >= LW * LH) continue;
             const int i = ox + q % LW, j = oy + q / LW;
             const bool in = i >= 0 && j >= 0 && i <= N && j <= N;
             C<double> v = vu[s];
@@ -818,11 +819,12 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
 #pragma unroll
     for (int pass = 0; pass < 5 * S; ++pass) {
         const int c = pass % 5;
-        const int lo = 2 * pass + 1, hi = LW - 2 - 2 * pass;   // rows on tile + (RH - 2 pass - 1)
+        // rows on tile + (RH - 2 pass - 1)
+        const int lo = 2 * pass + 1, hi = LW - 2 - 2 * pass, hiy = LH - 2 - 2 * pass;
 #pragma unroll
         for (int m = 0; m < NM; ++m) {
             const int ly = sly[m];
-            if (ly < lo || ly > hi) continue;
+            if (ly < lo || ly > hiy) continue;
             const int j = oy + ly;
             const int ca = c + sa[m];
             const int lx = (ca >= 5 ? ca - 5 : ca) + sbase[m];
@@ -842,7 +844,7 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         }
         __syncthreads();
     }
-    for (int q = tid; q < TS * TS; q += NT) {
+    for (int q = tid; q < TS * TY; q += NT) {
         int i = x0 + q % TS, j = y0 + q / TS;
         if (i > N || j > N) continue;
         uo[(size_t)j * M + i] = st_as<T>(U[(j - oy) * LW + (i - ox)]);
@@ -850,13 +852,13 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
     if constexpr (RESID) {
         // residual f - A_{sigma_b} u on tile + 1, kept in registers until
         // every thread has read f, then stored over f
-        constexpr int W1 = TS + 2, NR = (W1 * W1 + NT - 1) / NT;
+        constexpr int W1 = TS + 2, H1 = TY + 2, NR = (W1 * H1 + NT - 1) / NT;
         C<double> res[NR];
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
             const int q = tid + NT * m;
             const int lx = RH - 1 + q % W1, ly = RH - 1 + q / W1, i = ox + lx, j = oy + ly;
-            if (q >= W1 * W1 || i < 0 || j < 0 || i > N || j > N) continue;
+            if (q >= W1 * H1 || i < 0 || j < 0 || i > N || j > N) continue;
             const int l = ly * LW + lx;
             Row<double> r = row_at<double>(i, j, N, H, ih2, KS[l].x, sigb);
             res[m] = csub(FS[l], cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, LW)));
@@ -866,15 +868,15 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
         for (int m = 0; m < NR; ++m) {
             const int q = tid + NT * m;
             const int lx = RH - 1 + q % W1, ly = RH - 1 + q / W1, i = ox + lx, j = oy + ly;
-            if (q >= W1 * W1 || i < 0 || j < 0 || i > N || j > N) continue;
+            if (q >= W1 * H1 || i < 0 || j < 0 || i > N || j > N) continue;
             FS[ly * LW + lx] = res[m];
         }
         __syncthreads();
         // full weighting (mirrored at the boundary) for the coarse nodes of
         // the tile
         const int Nc = N / 2, Mc = Nc + 1;
-        constexpr int CX = TS / 2;
-        for (int q = tid; q < CX * CX; q += NT) {
+        constexpr int CX = TS / 2, CY = TY / 2;
+        for (int q = tid; q < CX * CY; q += NT) {
             const int I = x0 / 2 + q % CX, J = y0 / 2 + q / CX;
             if (I > Nc || J > Nc) continue;
             C<double> sum = cmk(0.0, 0.0);
@@ -1379,37 +1381,41 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
     else gs_up_t<float, float, float>(s, g, k, sa, f, u0, ec, uo, skip);
 }
 
-template <typename T, int TS, int S, int NT>
+template <typename T, int TS, int S, int NT, int TY = TS>
 static void kacz_tb_t(hipStream_t s, const Geo &g, const void *k, const double *tab, double sig, const void *f,
                       const void *ui, const void *ec, void *uo, const int *skip) {
-    dim3 grid((g.M + TS - 1) / TS, (g.M + TS - 1) / TS);
-    k_kacz_tb<T, TS, S, NT, false><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
+    dim3 grid((g.M + TS - 1) / TS, (g.M + TY - 1) / TY);
+    k_kacz_tb<T, TS, S, NT, false, TY><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
                                                        (const C<double> *)tab, sig, 0.0, (const C<T> *)f,
                                                        (const C<T> *)ui, (const C<T> *)ec, (C<T> *)uo, nullptr,
                                                        skip);
 }
 
 // the RESID form of a configuration: tile TS - 4, halo 10 S + 2
-template <typename T, int TS, int S, int NT>
+template <typename T, int TS, int S, int NT, int TY = TS>
 static void kacz_tb_resid_t(hipStream_t s, const Geo &g, const void *k, const double *tab, double sig, double sigb,
                             const void *f, const void *ui, void *uo, void *fc, const int *skip) {
-    constexpr int T4 = TS - 4;
-    dim3 grid((g.M + T4 - 1) / T4, (g.M + T4 - 1) / T4);
-    k_kacz_tb<T, TS, S, NT, true><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
+    constexpr int T4 = TS - 4, Y4 = TY - 4;
+    dim3 grid((g.M + T4 - 1) / T4, (g.M + Y4 - 1) / Y4);
+    k_kacz_tb<T, TS, S, NT, true, TY><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
                                                       (const C<double> *)tab, sig, sigb, (const C<T> *)f,
                                                       (const C<T> *)ui, nullptr, (C<T> *)uo, (C<T> *)fc, skip);
 }
 
-// Tile configurations offered to the tuner: (tile side, sweeps per launch,
-// threads per workgroup).
-const KaczCfg kKaczCfgs[KACZ_NCFG] = {{32, 1, 512}, {32, 2, 1024}, {16, 2, 512}, {16, 4, 1024},
-                                      {16, 2, 1024}, {16, 1, 512}, {32, 1, 1024}};
+// Tile configurations offered to the tuner: (tile width, sweeps per launch,
+// threads per workgroup, tile height, tile height of the RESID launch before
+// its shrink by four).  The last one halves the tile height: about 20 % fewer
+// rows per colour pass and workgroup at the price of more workgroups (153
+// instead of 81 at n = 127), which the latency-bound passes favour.
+const KaczCfg kKaczCfgs[KACZ_NCFG] = {{32, 1, 512, 32, 32},  {32, 2, 1024, 32, 32}, {16, 2, 512, 16, 16},
+                                      {16, 4, 1024, 16, 16}, {16, 2, 1024, 16, 16}, {16, 1, 512, 16, 16},
+                                      {32, 1, 1024, 32, 32}, {16, 2, 1024, 8, 12}};
 
 // The LDS tile holds FP64 values in either storage precision.
 bool kacz_cfg_fits(Prec, int cfg) {
     const KaczCfg &c = kKaczCfgs[cfg];
-    int lw = c.ts + 20 * c.sweeps;
-    return (size_t)lw * lw * 16 <= 160 * 1024;
+    int lw = c.ts + 20 * c.sweeps, lh = c.ty + 20 * c.sweeps;
+    return (size_t)lw * lh * 16 <= 160 * 1024;
 }
 
 template <typename T>
@@ -1422,6 +1428,7 @@ static void kacz_tb_any(int cfg, hipStream_t s, const Geo &g, const void *k, con
     case 3: kacz_tb_t<T, 16, 4, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
     case 4: kacz_tb_t<T, 16, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
     case 5: kacz_tb_t<T, 16, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 7: kacz_tb_t<T, 16, 2, 1024, 8>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
     default: kacz_tb_t<T, 32, 1, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
     }
 }
@@ -1461,8 +1468,8 @@ void launch_kacz_table(Prec p, hipStream_t s, const Geo &g, const void *k, doubl
 // Configurations whose region is staged in LDS have a RESID form.
 bool kacz_cfg_resid(int cfg) {
     const KaczCfg &c = kKaczCfgs[cfg];
-    int lw = c.ts + 20 * c.sweeps;
-    return (size_t)lw * lw * 48 <= 160 * 1024;
+    int lw = c.ts + 20 * c.sweeps, lh = c.rty + 20 * c.sweeps;
+    return (size_t)lw * lh * 48 <= 160 * 1024;
 }
 
 template <typename T>
@@ -1473,6 +1480,7 @@ static void kacz_resid_any(int cfg, hipStream_t s, const Geo &g, const void *k, 
     case 2: kacz_tb_resid_t<T, 16, 2, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
     case 4: kacz_tb_resid_t<T, 16, 2, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
     case 5: kacz_tb_resid_t<T, 16, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
+    case 7: kacz_tb_resid_t<T, 16, 2, 1024, 12>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
     default: kacz_tb_resid_t<T, 32, 1, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
     }
 }

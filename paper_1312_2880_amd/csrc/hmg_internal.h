@@ -93,9 +93,10 @@ struct BottomDesc {
     const double   *ainv_t;
 };
 struct KaczCfg {
-    int ts, sweeps, threads;    // tile side, sweeps per launch, workgroup size
+    int ts, sweeps, threads;    // tile width, sweeps per launch, workgroup size
+    int ty, rty;                // tile height; that of the RESID form before its shrink by 4
 };
-constexpr int KACZ_NCFG = 7;
+constexpr int KACZ_NCFG = 8;
 extern const KaczCfg kKaczCfgs[KACZ_NCFG];
 bool   kacz_cfg_fits(Prec p, int cfg);
 int    bottom_complex_slots();   // LDS capacity of the bottom solver

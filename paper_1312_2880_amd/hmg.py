@@ -116,6 +116,7 @@ _SIGS = {
     "hmg_op_kacz_tiled_dev": (_i, [P, _i, _d, _i, P, P, P, P, P]),
     "hmg_op_gs_up_product_dev": (_i, [P, _i, _d, _i, P, P, P, P, P, P, P]),
     "hmg_kacz_tile_config": (_i, [_i, P, P, P]),
+    "hmg_kacz_tile_height": (_i, [_i]),
     "hmg_op_kacz_down_dev": (_i, [P, _i, _d, _d, _i, P, P, P, P, P]),
     "hmg_op_kacz_level_dev": (_i, [P, _i, _d, _d, _i, P, P, P, P, P, P]),
     "hmg_solve_history": (_i, [P, _i, P, _i]),
@@ -130,8 +131,8 @@ EXPORTED = tuple(_SIGS)
 
 
 def kacz_tile_configs():
-    """[(tile side, sweeps per launch, workgroup size)] of the tiled
-    Kaczmarz kernel."""
+    """[(tile width, sweeps per launch, workgroup size)] of the tiled
+    Kaczmarz kernel (kacz_tile_height gives the height)."""
     t, s, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     n = _lib.hmg_kacz_tile_config(0, None, None, None)
     out = []
@@ -139,6 +140,12 @@ def kacz_tile_configs():
         _lib.hmg_kacz_tile_config(c, ctypes.byref(t), ctypes.byref(s), ctypes.byref(w))
         out.append((t.value, s.value, w.value))
     return out
+
+
+def kacz_tile_height(config: int) -> int:
+    """Tile height of a Kaczmarz tile configuration (its width for square
+    tiles)."""
+    return _lib.hmg_kacz_tile_height(config)
 
 
 def _check(status, allow=(OK,)):

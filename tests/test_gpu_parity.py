@@ -365,12 +365,12 @@ def test_fused_gs_down_without_iterate_output(ctx, hmg):
     assert rel(host(d_fc), oracle.restrict_fw(oracle.residual(h, k, 0.0, f, u_ref))) <= 1e-13
 
 
-@pytest.mark.parametrize("cfg", range(7))
+@pytest.mark.parametrize("cfg", range(8))
 @pytest.mark.parametrize("start", ["zero", "u", "u+Pe"])
 @pytest.mark.parametrize("n", [63, 127])
 def test_tiled_kaczmarz_matches_oracle(ctx, hmg, cfg, start, n):
     tile, sweeps, threads = hmg.kacz_tile_configs()[cfg]
-    say(f"case kacz_tiled cfg={cfg} ({tile},{sweeps},{threads}) start={start} n={n}")
+    say(f"case kacz_tiled cfg={cfg} ({tile}x{hmg.kacz_tile_height(cfg)},{sweeps},{threads}) start={start} n={n}")
     h = 1.0 / (n + 1)
     k = rand_k(n, 7 * n + cfg, 60.0, 150.0)
     g = hmg.Grid(ctx, h, k)
@@ -393,7 +393,7 @@ def test_tiled_kaczmarz_matches_oracle(ctx, hmg, cfg, start, n):
     assert rel(host(d_uo), want) <= 1e-12
 
 
-@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 6])
+@pytest.mark.parametrize("cfg", [0, 2, 4, 5, 6, 7])
 @pytest.mark.parametrize("start", ["zero", "u"])
 @pytest.mark.parametrize("n", [63, 127])
 def test_kaczmarz_down_matches_oracle(ctx, hmg, cfg, start, n):
