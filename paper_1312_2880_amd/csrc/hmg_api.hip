@@ -640,6 +640,11 @@ hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> 
                             const hmg_c64 *f) {
     HIPCHK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void **)&g->host_state, 4 * sizeof(KState), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&g->done_host, (size_t)g->nrhs * sizeof(int), hipHostMallocDefault));
+    for (int s = 0; s < g->nrhs; ++s) {
+        g->done_host[s] = 0;
+        g->slot[s].K.done_host = &g->done_host[s];
+    }
     for (int q = 0; q < 4; ++q) HIPCHK(hipEventCreateWithFlags(&g->ev[q], hipEventDisableTiming));
     for (int l = 0; l < g->nlev; ++l) {
         size_t m = kl[l].size();
@@ -674,6 +679,7 @@ extern "C" void hmg_grid_destroy(hmg_grid *g) {
     for (int q = 0; q < 4; ++q)
         if (g->ev[q]) (void)hipEventDestroy(g->ev[q]);
     if (g->host_state) (void)hipHostFree(g->host_state);
+    if (g->done_host) (void)hipHostFree(g->done_host);
     if (g->stream) (void)hipStreamDestroy(g->stream);
     delete g;
 }

@@ -79,6 +79,7 @@ struct hmg_grid {
     size_t     bytes = 0;
     hipStream_t stream = nullptr;
     hmgk::KState *host_state = nullptr;   // pinned, 4 entries
+    int          *done_host = nullptr;    // pinned, one done flag per right-hand side
     hipEvent_t ev[4] = {};
 };
 

@@ -47,6 +47,7 @@ struct Krylov {
     double *partials;    // reduction scratch: NQ x nblocks doubles
     double *hist;        // relative residual per half step
     KState *st;
+    int    *done_host;   // pinned host copy of st->done, written by the device
     int     nblocks;
 };
 

@@ -315,12 +315,20 @@ struct KDev {
     C<double> *b, *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;
     double *partials, *hist;
     KState *st;
+    int    *done_host;
 };
 
 static inline KDev kdev(const Krylov &K) {
     return KDev{(C<double> *)K.b,  (C<double> *)K.x, (C<double> *)K.r,  (C<double> *)K.rh,
                 (C<double> *)K.p,  (C<double> *)K.v, (C<double> *)K.s,  (C<double> *)K.t,
-                (C<double> *)K.ph, (C<double> *)K.sh, K.partials, K.hist, K.st};
+                (C<double> *)K.ph, (C<double> *)K.sh, K.partials, K.hist, K.st, K.done_host};
+}
+
+// The host polls the done flag of a running solve through a pinned copy
+// that the kernels changing it write (a vector store to host memory), so no
+// copy is queued behind every iteration.
+__device__ __forceinline__ void publish_done(const KDev &K) {
+    if (K.done_host) *(volatile int *)K.done_host = K.st->done;
 }
 
 __device__ __forceinline__ C<double> cdivc(C<double> a, C<double> b) { return cdiv(a, b.x, b.y); }
@@ -383,6 +391,7 @@ __global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol
     s->done = (rel <= rtol) ? 1 : 0;
     s->stop = s->done;
     s->true_rel = -1.0;
+    publish_done(K);
 }
 
 // ---- p = r + beta (p - omega v); on restart rh = r and p = r ----------------
@@ -612,6 +621,7 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
         if (threadIdx.x == 0 && threadIdx.y == 0) {
             s->done = 1;
             s->stop = 1;
+            publish_done(K);
         }
         return;
     }
@@ -624,11 +634,13 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
     if (rel <= s->rtol) {
         s->done = 1;
         s->stop = 1;
+        publish_done(K);
         return;
     }
     if (s->halfsteps >= s->maxhalf) {
         s->done = 2;
         s->stop = 1;
+        publish_done(K);
         return;
     }
     C<double> rho_new = cmk(tot[1], tot[2]);
@@ -691,6 +703,7 @@ __global__ void k_kry_restart(KDev K) {
     s->done = 0;
     s->half_exit = 0;
     s->stop = 0;
+    publish_done(K);
 }
 
 static inline dim3 kgrid(const Geo &g) { return dim3((g.M + BX - 1) / BX, (g.M + BY * KRY - 1) / (BY * KRY)); }

@@ -178,17 +178,20 @@ static hmg_status run_begin(SolveRun &R, int x0_given) {
     return HMG_OK;
 }
 
-// Queue one iteration plus its status readback.
+// Queue one iteration and an event behind it; the iteration's kernels write
+// the done flag to pinned host memory (run_done).
 static hmg_status run_issue(SolveRun &R) {
     hmg_status st = launch_iteration(R.g, *R.S, R.s);
     if (st) return st;
     int q = R.issued & 1;
-    HIPCHK(hipMemcpyAsync(&R.hs[q], R.S->K.st, sizeof(KState), hipMemcpyDeviceToHost, R.s));
     HIPCHK(hipEventRecord(R.ev[q], R.s));
     R.issued++;
     R.inflight++;
     return HMG_OK;
 }
+
+// The device's done flag as of the last finished event (or later).
+static bool run_done(const SolveRun &R) { return __atomic_load_n(R.S->K.done_host, __ATOMIC_ACQUIRE) != 0; }
 
 // Finish after the device reported done: confirm with the FP64 true
 // residual.  Returns HMG_PENDING if the iteration must go on (restart).
@@ -239,7 +242,7 @@ static hmg_status run_solve(SolveRun &R, int x0_given, hmg_solve_info *info) {
         int q = (R.issued - 2) & 1;   // the older of the two in flight
         HIPCHK(hipEventSynchronize(R.ev[q]));
         R.inflight--;
-        if (R.hs[q].done) {
+        if (run_done(R)) {
             st = run_finish(R, info);
             if (st == HMG_PENDING) continue;
             return st;
@@ -364,7 +367,7 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
             HIPCHK(hipEventSynchronize(R.ev[e]));
             R.inflight--;
             bool over = R.issued > R.maxit + 4;
-            if (R.hs[e].done || over) {
+            if (run_done(R) || over) {
                 Item it = per_grid[q].front();
                 hmg_solve_info *inf = (info && info[q]) ? &info[q][it.r] : nullptr;
                 hmg_status sr = run_finish(R, inf);
@@ -500,7 +503,7 @@ static void server_loop(hmg_ctx *ctx) {
             }
             R.inflight--;
             bool over = R.issued > R.maxit + 4;
-            if (R.hs[e].done || over) {
+            if (run_done(R) || over) {
                 hmg_solve_info inf{};
                 hmg_status st = run_finish(R, &inf);
                 if (st == HMG_PENDING && !over) continue;
