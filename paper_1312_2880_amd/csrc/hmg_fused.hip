@@ -171,6 +171,11 @@ using GsBig2 = GsTile<64, 20, 2>;
 // tile + 1: a halo of 4
 using GsBigMV = GsTile<64, 20, 4>;
 using GsSmall2 = GsTile<32, 12, 2>;
+// levels that would get fewer small tiles than CUs (n <= 255) use tiles of
+// half the width: one node of each colour per thread, shorter dependent
+// phases, and more of the otherwise idle CUs
+using GsTiny = GsTile<16, 12>;
+using GsTiny2 = GsTile<16, 12, 2>;
 
 // ===========================================================================
 // k_gs_down: one zero-guess red-black sweep (sigma_A), residual (sigma_B) on
@@ -1309,6 +1314,9 @@ static inline GeoT geo_t(const Geo &g) { return GeoT{g.n, g.M, g.N}; }
 static bool gs_small(const Geo &g) {
     return (size_t)((g.M + GsBig::X - 1) / GsBig::X) * ((g.M + GsBig::Y - 1) / GsBig::Y) < 512;
 }
+static bool gs_tiny(const Geo &g) {
+    return (size_t)((g.M + GsSmall::X - 1) / GsSmall::X) * ((g.M + GsSmall::Y - 1) / GsSmall::Y) < 256;
+}
 
 template <class TL>
 static dim3 gs_grid(const Geo &g) { return dim3((g.M + TL::X - 1) / TL::X, (g.M + TL::Y - 1) / TL::Y); }
@@ -1316,7 +1324,11 @@ static dim3 gs_grid(const Geo &g) { return dim3((g.M + TL::X - 1) / TL::X, (g.M 
 template <typename T, typename TF>
 static void gs_down_t(hipStream_t s, const Geo &g, const void *k, double sa, double sb, const void *f, void *uo,
                       void *fc, bool uo_black, const int *skip) {
-    if (gs_small(g))
+    if (gs_tiny(g))
+        k_gs_down<GsTiny, T, TF><<<gs_grid<GsTiny>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
+            uo_black ? 1 : 0, skip);
+    else if (gs_small(g))
         k_gs_down<GsSmall, T, TF><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
             uo_black ? 1 : 0, skip);
@@ -1338,7 +1350,11 @@ static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const
                     const void *ec, void *uo, const int *skip) {
     const double ih2 = 1.0 / (g.H * g.H);
     if (u0) {
-        if (gs_small(g))
+        if (gs_tiny(g))
+            k_gs_up_u0<GsTiny2, T, TF, TU><<<gs_grid<GsTiny2>(g), GNT, 0, s>>>(
+                geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
+                (C<TU> *)uo, skip);
+        else if (gs_small(g))
             k_gs_up_u0<GsSmall2, T, TF, TU><<<gs_grid<GsSmall2>(g), GNT, 0, s>>>(
                 geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
                 (C<TU> *)uo, skip);
@@ -1348,7 +1364,10 @@ static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const
                 (C<TU> *)uo, skip);
         return;
     }
-    if (gs_small(g))
+    if (gs_tiny(g))
+        k_gs_up<GsTiny, T, TF, TU><<<gs_grid<GsTiny>(g), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
+    else if (gs_small(g))
         k_gs_up<GsSmall, T, TF, TU><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
     else
