@@ -171,9 +171,10 @@ using GsBig2 = GsTile<64, 20, 2>;
 // tile + 1: a halo of 4
 using GsBigMV = GsTile<64, 20, 4>;
 using GsSmall2 = GsTile<32, 12, 2>;
-// levels that would get fewer small tiles than CUs (n <= 255) use tiles of
-// half the width: one node of each colour per thread, shorter dependent
-// phases, and more of the otherwise idle CUs
+// levels that would get fewer than four small tiles per CU (n <= 511) use
+// tiles of half the width: one node of each colour per thread, shorter
+// dependent phases, more workgroups to overlap them (and on n <= 255 more
+// of the otherwise idle CUs)
 using GsTiny = GsTile<16, 12>;
 using GsTiny2 = GsTile<16, 12, 2>;
 
@@ -1315,7 +1316,7 @@ static bool gs_small(const Geo &g) {
     return (size_t)((g.M + GsBig::X - 1) / GsBig::X) * ((g.M + GsBig::Y - 1) / GsBig::Y) < 512;
 }
 static bool gs_tiny(const Geo &g) {
-    return (size_t)((g.M + GsSmall::X - 1) / GsSmall::X) * ((g.M + GsSmall::Y - 1) / GsSmall::Y) < 256;
+    return (size_t)((g.M + GsSmall::X - 1) / GsSmall::X) * ((g.M + GsSmall::Y - 1) / GsSmall::Y) < 1024;
 }
 
 template <class TL>
