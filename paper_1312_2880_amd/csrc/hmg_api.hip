@@ -238,7 +238,10 @@ static void layout(hmg_grid *g, Carver &c) {
         double **vecs[] = {&K.b, &K.x, &K.r, &K.rh, &K.p, &K.v, &K.s, &K.t, &K.ph, &K.sh};
         for (double **v : vecs) *v = (double *)c.take(m0 * 16);
         K.nblocks = nb;
-        K.partials = (double *)c.take((size_t)3 * nb * 8);
+        // room for the partial sums of the Krylov kernels and of the fused
+        // finest up kernel, whichever launches more blocks
+        K.pcap = std::max(nb, gs_up_mv_blocks(g->lev[0].geo));
+        K.partials = (double *)c.take((size_t)3 * K.pcap * 8);
         S.hist_cap = 0;
         K.hist = nullptr;
         K.st = (KState *)c.take(sizeof(KState));
@@ -777,7 +780,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         // the finest up kernel of an FP64 solve also forms the Krylov product
         // of its result when the caller asks for it
         if (mv && l == 0 && !u0 && !f64 && gs_up_mv_ok(g->prec, L.geo) &&
-            gs_up_mv_blocks(L.geo) <= S.K.nblocks) {
+            gs_up_mv_blocks(L.geo) <= S.K.pcap) {
             launch_gs_up_mv(s, mv->kind, L.geo, L.k, pl.sigma_relax[l], f, e, mv->no_z ? nullptr : dst, mv->out,
                             mv->dot, mv->partials, skip);
             mv->blocks = gs_up_mv_blocks(L.geo);
@@ -851,7 +854,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
 bool vcycle_forms_products(const hmg_grid *g, const Slot &S) {
     const Geo &g0 = g->lev[0].geo;
     return !one_pass(g) && g->prec == P64 && g->lb != 0 && g->lev[0].mode == LM_GS_FUSED && g0.n > 511 &&
-           gs_up_mv_ok(g->prec, g0) && gs_up_mv_blocks(g0) <= S.K.nblocks;
+           gs_up_mv_ok(g->prec, g0) && gs_up_mv_blocks(g0) <= S.K.pcap;
 }
 
 // z = B_V r on FP64 device fields r, z (finest level).
@@ -1022,7 +1025,7 @@ extern "C" hmg_status hmg_op_gs_up_product_dev(hmg_grid *g, int level, double si
     const Level &L = g->lev[level];
     Krylov &K = g->slot[0].K;
     const int nb = gs_up_mv_blocks(L.geo);
-    if (nb > K.nblocks) return hmg_fail(HMG_ERR_INVALID, "level %d too large for the reduction scratch", level);
+    if (nb > K.pcap) return hmg_fail(HMG_ERR_INVALID, "level %d too large for the reduction scratch", level);
     hipStream_t s = pick_stream(g, stream);
     launch_gs_up_mv(s, kind, L.geo, L.k, sigma_relax, d_f, d_ec, d_uo, d_mv, d_dot, K.partials, nullptr);
     if (d_sums) launch_sum_partials(s, K.partials, nb, kind == 1 ? 2 : 3, (double *)d_sums);

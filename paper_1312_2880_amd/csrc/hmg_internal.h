@@ -44,7 +44,8 @@ struct KState {
 // Device pointers of one solve slot (finest-level Krylov vectors).
 struct Krylov {
     double *b, *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;   // complex interleaved
-    double *partials;    // reduction scratch: NQ x nblocks doubles
+    double *partials;    // reduction scratch: 3 x pcap doubles
+    int     pcap;        // partial sums per quantity the scratch holds (>= nblocks)
     double *hist;        // relative residual per half step
     KState *st;
     int    *done_host;   // pinned host copy of st->done, written by the device
