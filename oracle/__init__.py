@@ -27,7 +27,8 @@ SL, HLM, HYB = 0, 1, 2
 SM_GS, SM_KACZ, SM_LU = 0, 1, 2
 ORDER_COLOUR, ORDER_LEX = 0, 1
 PREC_NONE, PREC_VCYCLE, PREC_EXACT = 0, 1, 2
-OK, NOT_CONVERGED = 0, 4
+MIX_OFF, MIX_FUSED, MIX_ONEPASS = 0, 1, 2
+OK, NOT_CONVERGED, BREAKDOWN = 0, 4, 5
 MAX_LEVELS = 24
 
 
@@ -96,7 +97,9 @@ def lib():
             "orc_vcycle": [P, P, P],
             "orc_bicgstab": [P, P, P, d, i, i, P, P, i],
             "orc_bicgstab_ex": [P, P, P, d, i, i, P, P, i, i],
+            "orc_bicgstab_ex2": [P, P, P, d, i, i, P, P, i, i, i, i],
             "orc_grid_override_level": [P, i, i, d, d, i, i],
+            "orc_grid_set_mixed": [P, i, i, i, i],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name)
@@ -106,6 +109,7 @@ def lib():
         _lib.orc_lu_factor.restype = i
         _lib.orc_bicgstab.restype = i
         _lib.orc_bicgstab_ex.restype = i
+        _lib.orc_bicgstab_ex2.restype = i
         _lib.orc_grid_override_level.restype = i
     return _lib
 
@@ -276,6 +280,17 @@ class Grid:
         if rc != 0:
             raise ValueError("invalid override")
 
+    def set_mixed(self, mode=MIX_FUSED, kacz_every=2, block_n=31, round_io=False):
+        """Precision form (O11): the V-cycle stores its fields in complex
+        float and computes in double.  MIX_FUSED rounds where the fused
+        kernels store (the Kaczmarz iterate every ``kacz_every`` sweeps;
+        levels with n <= ``block_n`` are one double block); MIX_ONEPASS after
+        every elementary step; ``round_io`` also rounds the cycle's input and
+        output.  MIX_OFF restores the double V-cycle.  The outer Bi-CGSTAB
+        stays double either way."""
+        lib().orc_grid_set_mixed(self._ptr, int(mode), int(kacz_every), int(block_n), int(bool(round_io)))
+        return self
+
     def vcycle(self, f):
         """One V-cycle from zero initial guess: returns B_V f."""
         f, fp = _c(f, np.complex128)
@@ -285,17 +300,22 @@ class Grid:
         return u
 
     def bicgstab(self, b, rtol=1e-6, maxit=500, precond=PREC_VCYCLE, x0=None,
-                 history=False, force_breakdown_at=0):
+                 history=False, force_breakdown_at=0, true_res_every=0, nan_at=0):
         # force_breakdown_at = K > 0: the breakdown restart (rhat = r) is taken
-        # at the start of iteration K + 1 whatever rho is (restart-path tests)
+        # at the start of iteration K + 1 whatever rho is (restart-path tests);
+        # true_res_every = K > 0: the residual is recomputed (and the
+        # iteration restarted from it) after every K-th full iteration;
+        # nan_at = K > 0: the residual norm after iteration K counts as NaN
+        # (the not-finite exit, status BREAKDOWN)
         b, bp = _c(b, np.complex128)
         x = np.zeros_like(b) if x0 is None else np.array(x0, np.complex128, order="C")
         info = _Info()
         cap = 4 * maxit + 8
         hist = np.zeros(cap, np.float64)
-        lib().orc_bicgstab_ex(self._ptr, bp, x.ctypes.data_as(ctypes.c_void_p), rtol,
-                              maxit, precond, ctypes.byref(info),
-                              hist.ctypes.data_as(ctypes.c_void_p), cap, int(force_breakdown_at))
+        lib().orc_bicgstab_ex2(self._ptr, bp, x.ctypes.data_as(ctypes.c_void_p), rtol,
+                               maxit, precond, ctypes.byref(info),
+                               hist.ctypes.data_as(ctypes.c_void_p), cap, int(force_breakdown_at),
+                               int(true_res_every), int(nan_at))
         out = dict(iters=info.halfsteps / 2.0, halfsteps=info.halfsteps,
                    rel_res=info.rel_res, restarts=info.restarts,
                    status=info.status, vcycles=info.vcycles)

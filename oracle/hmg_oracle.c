@@ -315,6 +315,12 @@ struct orc_grid {
     int      *piv;
     orc_cplx *exact_lu;             /* dense factor of L^h (exact preconditioner) */
     int      *exact_piv;
+    /* precision form (O11): where the preconditioner rounds to float */
+    int       mix_mode;             /* ORC_MIX_OFF / ORC_MIX_FUSED / ORC_MIX_ONEPASS */
+    int       mix_kacz_every;       /* fused: Kaczmarz sweeps between stores   */
+    int       mix_block_n;          /* fused: levels with n <= this form one FP64 block */
+    int       mix_round_io;         /* the cycle's input and output are rounded */
+    double   *kv[ORC_MAX_LEVELS];   /* k used inside the V-cycle (rounded in the precision form) */
 };
 
 void orc_opts_default(orc_opts *o)
@@ -418,6 +424,7 @@ orc_grid *orc_grid_create(int n, double h, const double *k, const orc_opts *o)
         g->r[l] = calloc(m, sizeof(orc_cplx));
         if (l == 0) memcpy(g->k[0], k, m * sizeof(double));
         else        orc_inject_k(g->plan.n[l - 1], g->k[l - 1], g->k[l]);
+        g->kv[l] = g->k[l];
         if (nl <= o->coarsest_n || nl < 3 || l == ORC_MAX_LEVELS - 1) break;
         nl = (nl - 1) / 2;
         H *= 2.0;
@@ -439,6 +446,7 @@ void orc_grid_destroy(orc_grid *g)
 {
     if (!g) return;
     for (int l = 0; l < g->plan.nlev; ++l) {
+        if (g->kv[l] != g->k[l]) free(g->kv[l]);
         free(g->k[l]); free(g->f[l]); free(g->u[l]); free(g->r[l]);
     }
     free(g->lu); free(g->piv); free(g->exact_lu); free(g->exact_piv);
@@ -477,11 +485,11 @@ static void relax(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u, int sweeps
     double H = pl->H[l], s = pl->sigma_relax[l];
     for (int it = 0; it < sweeps; ++it) {
         if (pl->smoother[l] == ORC_SM_GS) {
-            if (g->opts.gs_order == ORC_ORDER_LEX) orc_gs_lex(n, H, g->k[l], s, f, u);
-            else                                   orc_gs_rb(n, H, g->k[l], s, f, u);
+            if (g->opts.gs_order == ORC_ORDER_LEX) orc_gs_lex(n, H, g->kv[l], s, f, u);
+            else                                   orc_gs_rb(n, H, g->kv[l], s, f, u);
         } else {
-            if (g->opts.kacz_order == ORC_ORDER_LEX) orc_kacz_lex(n, H, g->k[l], s, f, u);
-            else                                     orc_kacz_5c(n, H, g->k[l], s, f, u);
+            if (g->opts.kacz_order == ORC_ORDER_LEX) orc_kacz_lex(n, H, g->kv[l], s, f, u);
+            else                                     orc_kacz_5c(n, H, g->kv[l], s, f, u);
         }
     }
 }
@@ -501,16 +509,155 @@ static void vcycle_level(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u)
     }
     memset(u, 0, m * sizeof(orc_cplx));
     relax(g, l, f, u, pl->pre[l]);
-    orc_residual(n, pl->H[l], g->k[l], pl->sigma_resid[l], f, u, g->r[l]);
+    orc_residual(n, pl->H[l], g->kv[l], pl->sigma_resid[l], f, u, g->r[l]);
     orc_restrict_fw(n, g->r[l], g->f[l + 1]);
     vcycle_level(g, l + 1, g->f[l + 1], g->u[l + 1]);
     orc_prolong_add(pl->n[l + 1], g->u[l + 1], u);
     relax(g, l, f, u, pl->post[l]);
 }
 
+/* ------------------------------------------------------------------------ */
+/* O11: the V-cycle of the precision form.  The preconditioner keeps its    */
+/* fields in complex single precision and computes in double: a value is    */
+/* rounded to float (round to nearest even) exactly where the field holding */
+/* it is stored, and every arithmetic step takes the float values widened   */
+/* to double.  The outer Bi-CGSTAB, the operator L of the outer iteration   */
+/* and the coarsest-grid operator (assembled from the unrounded k) stay     */
+/* double.  Two schedules of stores are modelled:                           */
+/*                                                                           */
+/*   ORC_MIX_FUSED: the fields passed between fused kernels.  k on every     */
+/*     level; each restricted right-hand side; each correction handed to    */
+/*     the finer level; on Kaczmarz levels the iterate after every          */
+/*     mix_kacz_every sweeps (the residual for the restriction is formed    */
+/*     from the iterate before its last store of the pre-smoothing leg);   */
+/*     Gauss-Seidel levels keep their pre-smoothed iterate in double;       */
+/*     levels with n <= mix_block_n form one double-precision block whose  */
+/*     only stored field is its result.                                     */
+/*   ORC_MIX_ONEPASS: every elementary step stores: k, each colour pass of  */
+/*     a sweep, each restriction, each prolongation-and-add, the coarsest   */
+/*     result.                                                              */
+/* With mix_round_io the cycle's input is rounded before the first step and */
+/* its output after the last (otherwise both stay double).  Only the        */
+/* coloured orders are modelled.                                            */
+/* ------------------------------------------------------------------------ */
+
+static double rnd32(double x) { return (double)(float)x; }
+
+static void round_field(size_t m, orc_cplx *a)
+{
+    double *d = (double *)a;           /* C99: a complex is an array of two reals */
+    for (size_t i = 0; i < 2 * m; ++i) d[i] = rnd32(d[i]);
+}
+
+/* one colour pass of red-black Gauss-Seidel (colour = (i + j) mod 2) */
+static void gs_colour_pass(int n, double h, const double *k, double sigma,
+                           const orc_cplx *f, orc_cplx *u, int colour)
+{
+    int M = n + 2, N = n + 1;
+    for (int j = 0; j <= N; ++j)
+        for (int i = (colour + j) & 1; i <= N; i += 2)
+            gs_point(N, M, h, k, sigma, f, u, i, j);
+}
+
+/* one colour pass of the 5-colour Kaczmarz sweep (colour = (i + 2j) mod 5) */
+static void kacz_colour_pass(int n, double h, const double *k, double sigma,
+                             const orc_cplx *f, orc_cplx *u, int colour)
+{
+    int M = n + 2, N = n + 1;
+    for (int j = 0; j <= N; ++j) {
+        int i0 = ((colour - 2 * j) % 5 + 5) % 5;
+        for (int i = i0; i <= N; i += 5)
+            kacz_row(N, M, h, k, sigma, f, u, i, j);
+    }
+}
+
+/* A relaxation leg of level l in the precision form.  last_store: round the
+ * iterate after the leg's final sweep group (the pre-smoothing leg of a
+ * fused Kaczmarz level stores it only after its residual has been formed). */
+static void relax_mixed(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u, int sweeps, int last_store)
+{
+    const orc_plan *pl = &g->plan;
+    int    n = pl->n[l];
+    size_t m = (size_t)(n + 2) * (n + 2);
+    double H = pl->H[l], s = pl->sigma_relax[l];
+    const double *k = g->kv[l];
+    int onepass = g->mix_mode == ORC_MIX_ONEPASS;
+    int kacz = pl->smoother[l] == ORC_SM_KACZ;
+    int every = g->mix_kacz_every > 0 ? g->mix_kacz_every : sweeps;
+    for (int it = 0; it < sweeps; ++it) {
+        int ncol = kacz ? 5 : 2;
+        for (int c = 0; c < ncol; ++c) {
+            if (kacz) kacz_colour_pass(n, H, k, s, f, u, c);
+            else      gs_colour_pass(n, H, k, s, f, u, c);
+            if (onepass) round_field(m, u);
+        }
+        if (!onepass && kacz && ((it + 1) % every == 0) && (it + 1 < sweeps || last_store))
+            round_field(m, u);
+    }
+}
+
+/* Level l of the mixed cycle; u is left unrounded where the caller stores
+ * it (the caller rounds the level's result). */
+static void vcycle_mixed(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u)
+{
+    const orc_plan *pl = &g->plan;
+    int    n = pl->n[l], nc;
+    size_t m = (size_t)(n + 2) * (n + 2), mc;
+    int    onepass = g->mix_mode == ORC_MIX_ONEPASS;
+    if (pl->smoother[l] == ORC_SM_LU) {
+        memcpy(u, f, m * sizeof(orc_cplx));
+        orc_lu_solve((int)m, g->lu, g->piv, u);
+        return;
+    }
+    if (!onepass && n <= g->mix_block_n) {   /* the double-precision block */
+        vcycle_level(g, l, f, u);
+        return;
+    }
+    int kacz = pl->smoother[l] == ORC_SM_KACZ;
+    nc = pl->n[l + 1];
+    mc = (size_t)(nc + 2) * (nc + 2);
+    memset(u, 0, m * sizeof(orc_cplx));
+    relax_mixed(g, l, f, u, pl->pre[l], 0);
+    orc_residual(n, pl->H[l], g->kv[l], pl->sigma_resid[l], f, u, g->r[l]);
+    if (kacz && !onepass && pl->pre[l] > 0) round_field(m, u);
+    orc_restrict_fw(n, g->r[l], g->f[l + 1]);
+    round_field(mc, g->f[l + 1]);
+    vcycle_mixed(g, l + 1, g->f[l + 1], g->u[l + 1]);
+    round_field(mc, g->u[l + 1]);
+    orc_prolong_add(nc, g->u[l + 1], u);
+    if (onepass) round_field(m, u);
+    relax_mixed(g, l, f, u, pl->post[l], 1);
+}
+
+void orc_grid_set_mixed(orc_grid *g, int mode, int kacz_every, int block_n, int round_io)
+{
+    g->mix_mode = mode;
+    g->mix_kacz_every = kacz_every;
+    g->mix_block_n = block_n;
+    g->mix_round_io = round_io;
+    for (int l = 0; l < g->plan.nlev; ++l) {
+        size_t m = (size_t)(g->plan.n[l] + 2) * (g->plan.n[l] + 2);
+        if (g->kv[l] != g->k[l]) free(g->kv[l]);
+        g->kv[l] = g->k[l];
+        if (mode == ORC_MIX_OFF) continue;
+        g->kv[l] = malloc(m * sizeof(double));
+        for (size_t q = 0; q < m; ++q) g->kv[l][q] = rnd32(g->k[l][q]);
+    }
+}
+
 void orc_vcycle(orc_grid *g, const orc_cplx *f, orc_cplx *u)
 {
-    vcycle_level(g, 0, f, u);
+    if (g->mix_mode == ORC_MIX_OFF) {
+        vcycle_level(g, 0, f, u);
+        return;
+    }
+    size_t m = (size_t)(g->n + 2) * (g->n + 2);
+    orc_cplx *fin = malloc(m * sizeof(orc_cplx));
+    memcpy(fin, f, m * sizeof(orc_cplx));
+    if (g->mix_round_io) round_field(m, fin);
+    vcycle_mixed(g, 0, fin, u);
+    if (g->mix_round_io) round_field(m, u);
+    free(fin);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -566,6 +713,21 @@ int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
                     int maxit, int precond, orc_info *info,
                     double *res_hist, int hist_cap, int force_breakdown_at)
 {
+    return orc_bicgstab_ex2(g, b, x, rtol, maxit, precond, info, res_hist, hist_cap,
+                            force_breakdown_at, 0, 0);
+}
+
+/* true_res_every = K > 0: after every K-th full iteration that has not met
+ * the tolerance, the residual is recomputed as b - A x; if that meets the
+ * tolerance the solve ends, otherwise it restarts from it (rhat = r, p = v =
+ * 0), as after a failed convergence check.  A residual norm that is not
+ * finite ends the solve with ORC_BREAKDOWN; nan_at = K > 0 treats the norm
+ * at the end of iteration K as not finite (tests of that path). */
+int orc_bicgstab_ex2(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
+                     int maxit, int precond, orc_info *info,
+                     double *res_hist, int hist_cap, int force_breakdown_at,
+                     int true_res_every, int nan_at)
+{
     int    n = g->n;
     double h = g->h;
     size_t m = (size_t)(n + 2) * (n + 2);
@@ -620,6 +782,7 @@ int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
         half++;
         double sn = nrm2(m, s);
         if (res_hist && nhist < hist_cap) res_hist[nhist++] = sn / bn;
+        if (!isfinite(sn)) { status = ORC_BREAKDOWN; break; }
         if (sn / bn <= rtol) {
             for (size_t i = 0; i < m; ++i) x[i] += alpha * ph[i];
             converged = 1;
@@ -636,8 +799,24 @@ int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
         half++;
         rho_old = rho;
         rn = nrm2(m, r);
+        if (nan_at > 0 && half == 2 * nan_at) rn = NAN;
         if (res_hist && nhist < hist_cap) res_hist[nhist++] = rn / bn;
-        if (rn / bn <= rtol) converged = 1;
+        if (!isfinite(rn)) { status = ORC_BREAKDOWN; break; }
+        if (rn / bn <= rtol) {
+            converged = 1;
+        } else if (true_res_every > 0 && half % (2 * true_res_every) == 0 && half < 2 * maxit) {
+            orc_residual(n, h, g->k[0], 0.0, b, x, r);
+            rn = nrm2(m, r);
+            if (rn / bn <= rtol) {
+                converged = 1;
+            } else {
+                memcpy(rh, r, m * sizeof(orc_cplx));
+                memset(p, 0, m * sizeof(orc_cplx));
+                memset(v, 0, m * sizeof(orc_cplx));
+                rho_old = alpha = omega = 1.0;
+                info->restarts++;
+            }
+        }
     }
     /* final true relative residual */
     orc_residual(n, h, g->k[0], 0.0, b, x, r);

@@ -93,9 +93,18 @@ void      orc_vcycle(orc_grid *g, const orc_cplx *f, orc_cplx *u);
 int       orc_grid_override_level(orc_grid *g, int l, int smoother, double sigma_relax,
                                   double sigma_resid, int pre, int post);
 
+/* ---- precision form (O11): the V-cycle with its fields stored in complex
+ * float and its arithmetic in double; mode ORC_MIX_FUSED rounds where the
+ * fused kernels store (Kaczmarz iterate every kacz_every sweeps, levels with
+ * n <= block_n one double block), ORC_MIX_ONEPASS after every elementary
+ * step; round_io rounds the cycle's input and output.  The Bi-CGSTAB of a
+ * grid in this mode keeps its own arithmetic and L in double. ---- */
+enum { ORC_MIX_OFF = 0, ORC_MIX_FUSED = 1, ORC_MIX_ONEPASS = 2 };
+void      orc_grid_set_mixed(orc_grid *g, int mode, int kacz_every, int block_n, int round_io);
+
 /* ---- Bi-CGSTAB (Section 6) ---- */
 enum { ORC_PREC_NONE = 0, ORC_PREC_VCYCLE = 1, ORC_PREC_EXACT = 2 };
-enum { ORC_OK = 0, ORC_NOT_CONVERGED = 4 };
+enum { ORC_OK = 0, ORC_NOT_CONVERGED = 4, ORC_BREAKDOWN = 5 };
 typedef struct {
     int    halfsteps;      /* iterations counted in halves               */
     double rel_res;        /* ||b - A x|| / ||b|| recomputed at exit       */
@@ -112,6 +121,16 @@ int orc_bicgstab(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
 int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
                     int maxit, int precond, orc_info *info,
                     double *res_hist, int hist_cap, int force_breakdown_at);
+/* The same with true_res_every = K > 0 (after every K-th full iteration that
+ * misses the tolerance the residual is recomputed as b - A x and the
+ * iteration restarts from it, or ends if it meets the tolerance) and nan_at
+ * = K > 0 (the residual norm at the end of iteration K is taken as NaN).  A
+ * residual norm that is not finite ends the solve with ORC_BREAKDOWN, x
+ * holding the last iterate. */
+int orc_bicgstab_ex2(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
+                     int maxit, int precond, orc_info *info,
+                     double *res_hist, int hist_cap, int force_breakdown_at,
+                     int true_res_every, int nan_at);
 
 #ifdef __cplusplus
 }

@@ -190,3 +190,91 @@ class DenseVCycle:
         e = self.apply(lev["R"] @ r, l + 1)
         u = u + lev["P"] @ e
         return self._relax(lev, f, u, lev["post"])
+
+
+def round32(a):
+    """Round a complex128 array to complex float (RNE per component) and
+    widen it back."""
+    return np.asarray(a, np.complex128).astype(np.complex64).astype(np.complex128)
+
+
+class DenseMixedVCycle(DenseVCycle):
+    """The precision form of the V-cycle written with dense matrices: fields
+    are rounded to complex float where they are stored, arithmetic is double.
+
+    mode "fused":  k on every level; each restricted right-hand side; each
+                   coarse correction; on Kaczmarz levels the iterate after
+                   every `every` sweeps (the pre-smoothing residual is formed
+                   before that leg's last rounding); levels with n <= block_n
+                   are evaluated in double as a whole.
+    mode "onepass": every colour pass, restriction, prolongation-and-add and
+                   coarsest result is rounded.
+    round_io rounds the input and the output of the whole cycle.  The
+    coarsest operator keeps the unrounded k."""
+
+    def __init__(self, h, k, plan, mode, every=2, block_n=31, round_io=False):
+        super().__init__(h, k, plan)
+        self.mode, self.every, self.block_n, self.round_io = mode, every, block_n, round_io
+        for lev in self.levels:
+            k32 = lev["k"].astype(np.float32).astype(np.float64)
+            if lev["smoother"] != "LU":
+                lev["A_relax"] = assemble_ghost(lev["n"], lev["H"], k32, lev["sigma_relax"])
+                lev["A_resid"] = assemble_ghost(lev["n"], lev["H"], k32, lev["sigma_resid"])
+            lev["A_relax32"] = assemble_ghost(lev["n"], lev["H"], k32, lev["sigma_relax"])
+            lev["A_resid32"] = assemble_ghost(lev["n"], lev["H"], k32, lev["sigma_resid"])
+
+    def _double_block(self, f, l):
+        """Levels l.. in double with the rounded k (coarsest: unrounded k)."""
+        lev = self.levels[l]
+        if lev["smoother"] == "LU":
+            return np.linalg.solve(lev["A_relax"], f)
+        u = self._relax(lev, f, np.zeros_like(f), lev["pre"])
+        r = f - lev["A_resid"] @ u
+        u = u + lev["P"] @ self._double_block(lev["R"] @ r, l + 1)
+        return self._relax(lev, f, u, lev["post"])
+
+    def _leg(self, lev, f, u, sweeps, last_store):
+        A, n = lev["A_relax"], lev["n"]
+        kacz = lev["smoother"] == "KACZ"
+        colours, ncol = (colour_5(n), 5) if kacz else (colour_rb(n), 2)
+        for it in range(sweeps):
+            for c in range(ncol):
+                S = colours == c
+                if kacz:
+                    Ac = A[S]
+                    d = np.einsum("ij,ij->i", Ac, np.conj(Ac)).real
+                    u = u + np.conj(Ac).T @ ((f[S] - Ac @ u) / d)
+                else:
+                    sub = np.diag(A[np.ix_(S, S)])
+                    u = u.copy()
+                    u[S] = (f[S] - A[S][:, ~S] @ u[~S]) / sub
+                if self.mode == "onepass":
+                    u = round32(u)
+            if (self.mode == "fused" and kacz and (it + 1) % self.every == 0
+                    and (it + 1 < sweeps or last_store)):
+                u = round32(u)
+        return u
+
+    def _level(self, f, l):
+        lev = self.levels[l]
+        if lev["smoother"] == "LU":
+            return np.linalg.solve(lev["A_relax"], f)
+        if self.mode == "fused" and lev["n"] <= self.block_n:
+            return self._double_block(f, l)
+        kacz = lev["smoother"] == "KACZ"
+        u = self._leg(lev, f, np.zeros_like(f), lev["pre"], False)
+        r = f - lev["A_resid"] @ u
+        if kacz and self.mode == "fused" and lev["pre"] > 0:
+            u = round32(u)
+        fc = round32(lev["R"] @ r)
+        e = round32(self._level(fc, l + 1))
+        u = u + lev["P"] @ e
+        if self.mode == "onepass":
+            u = round32(u)
+        return self._leg(lev, f, u, lev["post"], True)
+
+    def apply(self, f, l=0):
+        if self.round_io:
+            f = round32(f)
+        u = self._level(np.asarray(f, np.complex128), 0)
+        return round32(u) if self.round_io else u

@@ -190,6 +190,43 @@ def test_forced_breakdown_restart_equals_fresh_solve(K):
     assert abs(np.log(hp[2 * K + 4] / hf[2 * K + 4])) > 1e-3   # the branch changes the iteration
 
 
+@pytest.mark.parametrize("K", [5, 10])
+def test_true_residual_every_k_restarts_from_true_residual(K):
+    """true_res_every = K: after iteration K the residual is recomputed as
+    b - L x and the iteration restarts from it.  The first 2K half steps are
+    the plain solve's; the next ones follow a fresh solve started at x_K,
+    whose initial residual is the true residual (so the entry at 2K is the
+    true, not the recursive, relative residual); every restart is counted."""
+    h, k, f = _point63()
+    g = oracle.Grid(h, k, variant=oracle.SL)
+    _, plain = g.bicgstab(f, rtol=1e-6, maxit=300, history=True)
+    _, every = g.bicgstab(f, rtol=1e-6, maxit=300, history=True, true_res_every=K)
+    xK, _ = g.bicgstab(f, rtol=1e-30, maxit=K)
+    _, fresh = g.bicgstab(f, rtol=1e-6, maxit=300, x0=xK, history=True)
+    hp, he, hr = plain["history"], every["history"], fresh["history"]
+    assert every["status"] == oracle.OK and every["rel_res"] <= 1e-6
+    np.testing.assert_array_equal(he[: 2 * K + 1], hp[: 2 * K + 1])
+    # entries 2K+1.. of the periodic solve equal those of the fresh solve
+    np.testing.assert_allclose(he[2 * K + 1: 4 * K + 1], hr[1: 2 * K + 1], rtol=1e-9)
+    true_rel = np.linalg.norm(f - oracle.apply(h, k, 0.0, xK)) / np.linalg.norm(f)
+    assert hr[0] == pytest.approx(true_rel, rel=1e-12)
+    assert every["restarts"] == (every["halfsteps"] - 1) // (2 * K)
+
+
+def test_not_finite_residual_ends_with_breakdown():
+    """A residual norm that is not finite ends the solve with status
+    BREAKDOWN after that half step, x holding the iterate of that step (the
+    test forces the norm after iteration 4 to NaN; x then equals the iterate
+    of a solve stopped by maxit after 4 iterations)."""
+    h, k, f = _point63()
+    g = oracle.Grid(h, k, variant=oracle.SL)
+    x, info = g.bicgstab(f, rtol=1e-6, maxit=300, nan_at=4)
+    x4, info4 = g.bicgstab(f, rtol=1e-30, maxit=4)
+    assert info["status"] == oracle.BREAKDOWN and info["halfsteps"] == 8
+    assert info4["status"] == oracle.NOT_CONVERGED
+    np.testing.assert_array_equal(x, x4)
+
+
 def _point63():
     n = 63
     k = np.full((n + 2, n + 2), 10 * math.pi)
@@ -452,6 +489,65 @@ def test_vcycle_on_a_hierarchy_that_is_not_a_power_of_two(variant):
         want = ref.apply(f)
         got = g.vcycle(f.reshape(n + 2, n + 2)).reshape(-1)
         np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+MIXED_MODES = [("fused", 2, 1, False), ("fused", 1, 3, True), ("fused", 4, 0, False),
+               ("onepass", 2, 0, True), ("onepass", 2, 0, False)]
+
+
+@pytest.mark.parametrize("mode", MIXED_MODES, ids=lambda m: f"{m[0]}-e{m[1]}-b{m[2]}-io{int(m[3])}")
+@pytest.mark.parametrize("ci", [0, 1, 2, 3, 5])
+@pytest.mark.parametrize("n", [7, 15])
+def test_mixed_vcycle_equals_dense_mixed_composition(n, ci, mode):
+    """Precision form (O11): the V-cycle with its fields stored in complex
+    float and its arithmetic in double equals the same composition written
+    with dense matrices and explicit float casts at the same stores (k on
+    every level, restricted right-hand sides, coarse corrections, Kaczmarz
+    iterates every `every` sweeps or every colour pass; the coarsest operator
+    from the unrounded k).  The rounding itself is visible: the mixed cycle
+    differs from the double one by more than 1e-9 and less than 1e-5
+    relative, while the two mixed constructions agree to rounding level."""
+    case = dict(CASES_P4[ci])
+    lo, hi = case.pop("k")
+    h = 1.0 / (n + 1)
+    k = rng_k(n, 21, lo, hi) * (1 if n == 7 else 2)
+    g = oracle.Grid(h, k, **case)
+    plan = g.plan()
+    name, every, block_n, round_io = mode
+    g.set_mixed(oracle.MIX_FUSED if name == "fused" else oracle.MIX_ONEPASS, every, block_n, round_io)
+    ref = D.DenseMixedVCycle(h, k, plan, name, every, block_n, round_io)
+    ref64 = D.DenseVCycle(h, k, plan)
+    m = (n + 2) ** 2
+    effect = 0.0
+    for col in range(0, m, 13):
+        f = np.zeros(m, complex)
+        f[col] = 1.0
+        f[(col * 5 + 3) % m] = 0.5j
+        want = ref.apply(f)
+        got = g.vcycle(f.reshape(n + 2, n + 2)).reshape(-1)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+        w64 = ref64.apply(f)
+        effect = max(effect, np.linalg.norm(want - w64) / np.linalg.norm(w64))
+    assert 1e-9 < effect < 1e-5, effect
+
+
+def test_mixed_onepass_output_is_float():
+    """With every store rounded (one-pass schedule, rounded input and
+    output) the cycle's result lies on the complex-float grid, and switching
+    the precision form off restores the double cycle bit for bit."""
+    n, h = 15, 1 / 16
+    case = dict(CASES_P4[2])
+    lo, hi = case.pop("k")
+    k = rng_k(n, 21, lo, hi) * 2
+    g = oracle.Grid(h, k, **case)
+    f = rng_c((n + 2, n + 2), 5)
+    z64 = g.vcycle(f)
+    g.set_mixed(oracle.MIX_ONEPASS, 1, 0, True)
+    z = g.vcycle(f)
+    assert np.array_equal(z, z.astype(np.complex64).astype(np.complex128))
+    assert not np.array_equal(z, z64)
+    g.set_mixed(oracle.MIX_OFF)
+    assert np.array_equal(g.vcycle(f), z64)
 
 
 def test_vcycle_plans_cover_both_smoothers():
