@@ -1,17 +1,20 @@
-"""Benchmark: preconditioned Bi-CGSTAB solves of the 1023^2 layered-medium
-Helmholtz problem (HYB-V preconditioner, FP64) on one MI355X.
+"""Benchmark: preconditioned Bi-CGSTAB solves of the 2047^2 layered-medium
+Helmholtz problem (omega = 2 pi 80, HYB-V preconditioner, FP64) on one
+MI355X; the same problem with the complex-float preconditioner is reported
+beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
-                    [--variant hyb|sl] [--order colour|lex]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 2047|1023]
+                    [--precision fp64|mixed] [--variant hyb|sl] [--order colour|lex]
 
 (--order lex runs every relaxation in lexicographic order, the sweeps as
 wavefronts; the timed kernels are then one sweep per level.)
 
 One step is one full solve to relative residual 1e-6 from x0 = 0, with k, f
 and the hierarchy already resident in device memory.  Prints one JSON line
-with solves/s, the roofline figure of the dominant V-cycle kernel (timed with
-HIP events on the stream it runs on) and the CPU oracle timed on a bounded
-sample of the same workload.
+with solves/s, the roofline figure of the dominant V-cycle kernel (its share
+of the solve time is the largest; timed with HIP events on the stream it runs
+on, rated against its algorithmic HBM bytes), the mixed-precision solve of the
+same problem, and the CPU oracle timed per iteration on the same problem.
 """
 from __future__ import annotations
 
@@ -41,7 +44,7 @@ GS_NODE_FLOPS = 28            # one Gauss-Seidel node update, real flops
 
 
 def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rbytes: int,
-                      stored_u0: bool = False) -> float:
+                      stored_u0: bool = False, sweeps: int = 1) -> float:
     """Bytes the method must move per launch, every array touched once
     (c = complex size, r = real size of the level precision; per fine node,
     plus c per coarse node where a coarse field is read or written):
@@ -52,7 +55,8 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
                   then read the inner product's other
                   vector, write L u (as the FP64 solve
                   runs it)
-      kacz_tb     read f, k, u; write u                      N (3c + r)
+      kacz_tb     S sweeps, each reading f, k, u and         S N (3c + r)
+                  writing u (the per-sweep minimum)
     (FP64 levels store the pre-smoothed iterate u0 for the up kernel, which
     needs it on the black nodes only: the red half-sweep overwrites red
     values unread; complex-float levels recompute it on chip)
@@ -65,7 +69,7 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
     if kind == "gs_up_mv":
         return nodes * (3 * c + r) + coarse_nodes * c
     if kind == "kacz_tb":
-        return nodes * (3 * c + r)
+        return sweeps * nodes * (3 * c + r)
     raise KeyError(kind)
 
 
@@ -177,16 +181,16 @@ def kernel_cases(torch, g, plan, precision, sets=24, fixed=None, lex=False):
                         lambda q, st, l=l, sig=sig, p=p, kb=kb: g.op_kacz_level(
                             l, sig, 0.0, p["pre"], kb[q % 4]["f"], kb[q % 4]["u"], None, kb[q % 4]["uo"], None,
                             st),
-                        2, ("alu", KACZ_ROW_FLOPS * p["pre"] * (n + 2) ** 2,
-                            algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb)), cfg))
+                        2, ("hbm", algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb, sweeps=p["pre"]),
+                            KACZ_ROW_FLOPS * p["pre"] * (n + 2) ** 2), cfg))
             continue
         tile, sweeps, _ = hmg_configs()[cfg]
         out.append(("kacz_tb", l,
                     lambda q, st, l=l, sig=sig, cfg=cfg, kb=kb: g.op_kacz_tiled(
                         l, sig, cfg, kb[q % 4]["f"], kb[q % 4]["u"], None, kb[q % 4]["uo"], st),
                     (p["pre"] + p["post"]) // sweeps,
-                    ("alu", KACZ_ROW_FLOPS * sweeps * (n + 2) ** 2,
-                     algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb)), cfg))
+                    ("hbm", algorithmic_bytes("kacz_tb", (n + 2) ** 2, 0, cb, rb, sweeps=sweeps),
+                     KACZ_ROW_FLOPS * sweeps * (n + 2) ** 2), cfg))
     return out
 
 
@@ -198,8 +202,11 @@ def hmg_configs():
 def roofline_of(model, ms):
     if model[0] == "hbm":
         achieved = model[1] / (ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        if len(model) > 2:   # the Kaczmarz row arithmetic, for reference
+            out["fp64_tflops"] = round(model[2] / (ms * 1e-3) / 1e12, 4)
+        return out
     achieved = model[1] / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TFLOPS, 5),
@@ -237,25 +244,53 @@ def traffic_probe(torch, g, plan, precision, which, fixed, lex=False):
                       "kernel_ms": round(kt[0]["ms"], 5)}), flush=True)
 
 
-def cpu_baseline(h, k, f, variant, budget_s=10.0, max_solves=3, lex=False):
-    """The FP64 oracle on the host cores, on the same problem: full solves
-    until about `budget_s` seconds have passed (at most `max_solves`); the
-    rate is solves per second of wall time."""
+ORACLE_COUNTS = os.path.join(ROOT, "tests", "golden", "oracle_counts.json")
+
+
+def cpu_baseline(h, k, f, variant, n, lex=False, budget_s=12.0):
+    """The FP64 oracle on the host cores, on the same problem.  A full
+    oracle solve of the 2047^2 problem takes minutes, so the sample is a
+    bounded number of Bi-CGSTAB iterations from x0 = 0 (the first call also
+    builds the hierarchy, outside the timing): seconds per iteration, times
+    the oracle's own iteration count for the whole solve (stored by
+    tests/golden/make_oracle_counts.py, which calls only the oracle), gives
+    solves/s.  Timed with all host threads and with one."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     order = 1 if lex else 0
     og = oracle.Grid(h, k, variant=variant, gs_order=order, kacz_order=order)
-    t0 = time.perf_counter()
-    done, iters = 0, []
-    while done < max_solves and (done == 0 or time.perf_counter() - t0 < budget_s):
-        _, info = og.bicgstab(f, rtol=1e-6, maxit=400)
-        iters.append(info["iters"])
-        done += 1
-    dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"{done} full FP64 oracle solve(s) of the same {k.shape[0] - 2}^2 problem on {threads} threads "
-                       f"({iters[-1]} iterations each, {dt:.1f} s in total)",
-                iters=iters[-1])
+    count_key = f"layered{n}_{'hyb' if variant == oracle.HYB else 'sl'}"
+    counts = json.load(open(ORACLE_COUNTS)) if os.path.exists(ORACLE_COUNTS) else {}
+    full = counts.get(count_key, {}).get("iters")
+
+    def per_iteration(nthreads, budget):
+        oracle.set_threads(nthreads)
+        its = 2
+        t0 = time.perf_counter()
+        og.bicgstab(f, rtol=1e-30, maxit=its)
+        dt = time.perf_counter() - t0
+        # grow the sample to about `budget` seconds
+        more = max(0, min(200, int(budget / max(dt / its, 1e-6)) - its))
+        if more:
+            t0 = time.perf_counter()
+            og.bicgstab(f, rtol=1e-30, maxit=more)
+            dt, its = time.perf_counter() - t0, more
+        return dt / its, its
+
+    t_all, it_all = per_iteration(threads, budget_s)
+    t_one, it_one = per_iteration(1, budget_s / 2)
+    oracle.set_threads(threads)
+    out = dict(unit="solves/s", cores=threads, kind="oracle",
+               s_per_iter=t_all, s_per_iter_1thread=t_one, oracle_iters=full)
+    if full:
+        out["value"] = 1.0 / (t_all * full)
+        out["value_1thread"] = 1.0 / (t_one * full)
+    else:
+        out["value"] = None
+    out["sample"] = (f"{it_all} FP64 oracle Bi-CGSTAB iterations of the same {n}^2 problem on {threads} threads "
+                     f"({t_all:.3f} s each) and {it_one} on 1 thread ({t_one:.3f} s each), times the oracle's "
+                     f"full-solve count {full} (tests/golden/oracle_counts.json)")
+    return out
 
 
 def main():
@@ -265,10 +300,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--maxit", type=int, default=400)
-    ap.add_argument("--n", type=int, choices=[1023, 2047], default=1023,
-                    help="1023: the benchmark problem; 2047: the same medium at omega = 2 pi 80 "
-                         "(the precision-form problem)")
+    ap.add_argument("--maxit", type=int, default=3000)
+    ap.add_argument("--n", type=int, choices=[1023, 2047], default=2047,
+                    help="2047: the layered medium at omega = 2 pi 80 (the largest single-GPU "
+                         "configuration, the benchmark); 1023: the same medium at omega = 2 pi 40")
+    ap.add_argument("--mixed-steps", type=int, default=2,
+                    help="timed solves of the same problem with the complex-float preconditioner "
+                         "(reported beside the FP64 figure; 0: skip)")
     ap.add_argument("--traffic-probe", default=None, metavar="KERNEL@N",
                     help="only launch this kernel (e.g. kacz_tb@127) as the timing does, then "
                          "a plain copy of known size, for the FETCH_SIZE / WRITE_SIZE runs")
@@ -352,10 +390,34 @@ def main():
                      "ms_per_launch": round(dom["ms"], 5),
                      "per_launch": dom["model"][1], "share_of_solve": round(dom["share"], 3)})
 
+    x_fp64 = d_x.cpu().numpy()
+    mixed = None
+    if args.mixed_steps > 0 and args.precision == "fp64":
+        gm = hmg.Grid(ctx, h, k, f, variant=variant, precision=hmg.MIXED,
+                      relax_order=hmg.ORDER_LEX if lex else hmg.ORDER_COLOUR)
+        d_xm = torch.zeros_like(d_b)
+        minfo = [gm.solve_dev(d_xm, d_b=d_b, rtol=1e-6, maxit=args.maxit, stream=stream)]   # warm-up
+        torch.cuda.synchronize()
+        t0m = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            minfo.append(gm.solve_dev(d_xm, d_b=d_b, rtol=1e-6, maxit=args.maxit, stream=stream))
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0m
+        xm = d_xm.cpu().numpy()
+        mixed = {"value": round(args.mixed_steps / dtm, 4), "unit": "solves/s",
+                 "ms_per_step": round(1e3 * dtm / args.mixed_steps, 3),
+                 "iters": minfo[-1]["iters"], "fp64_iters": last["iters"],
+                 "rel_res_true": minfo[-1]["rel_res_true"],
+                 "all_converged": all(i["status"] == hmg.OK and i["rel_res_true"] <= 1e-6 for i in minfo),
+                 "rel_diff_vs_fp64": float(np.linalg.norm(xm - x_fp64) / np.linalg.norm(x_fp64)),
+                 "precision": "complex-float V-cycle storage, FP64 arithmetic; FP64 outer Bi-CGSTAB"}
+        gm.close()
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(h, k, f, variant, lex=lex)
-        cpu = {k_: (round(v, 5) if isinstance(v, float) else v) for k_, v in cpu.items()}
+        import oracle
+        cpu = cpu_baseline(h, k, f, oracle.HYB if args.variant == "hyb" else oracle.SL, n, lex=lex)
+        cpu = {k_: (round(v, 6) if isinstance(v, float) else v) for k_, v in cpu.items()}
 
     line = {
         "metric": "solves/s at rel. residual 1e-6",
@@ -371,7 +433,8 @@ def main():
         "dtype": "c128" if args.precision == "fp64" else "c64/c128",
         "data": "synthetic",
         "config": {"workload": (f"layered-medium Helmholtz {n}x{n}, omega = 2 pi {40 * (n + 1) // 1024}, "
-                                f"{args.variant.upper()}-V preconditioned Bi-CGSTAB to 1e-6, seed 2"
+                                f"{args.variant.upper()}-V preconditioned Bi-CGSTAB to 1e-6, "
+                                f"{'FP64' if args.precision == 'fp64' else 'complex-float V-cycle'}, seed 2"
                                 + (", lexicographic sweeps" if lex else "")),
                    "n": n, "precision": args.precision,
                    "iters": last["iters"], "mean_iters": mean_iters, "rel_res_true": last["rel_res_true"],
@@ -381,6 +444,7 @@ def main():
         "roofline": roofline,
         "kernels": {k_["key"]: {"ms_per_launch": round(k_["ms"], 5), "launches_per_iter": k_["per_iter"],
                                 "share_of_solve": round(k_["share"], 3), **k_["roofline"]} for k_ in kt},
+        "mixed": mixed,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

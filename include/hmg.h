@@ -55,10 +55,12 @@ typedef enum {
     HMG_ERR_NOMEM = 2,          /* device or host allocation failed             */
     HMG_ERR_DEVICE = 3,         /* a HIP call failed                            */
     HMG_ERR_NOT_CONVERGED = 4,  /* maxit reached; x holds the last iterate      */
-    HMG_ERR_BREAKDOWN = 5,      /* reserved: a Bi-CGSTAB breakdown (rho ~ 0)
+    HMG_ERR_BREAKDOWN = 5,      /* a residual norm of the iteration was not
+                                   finite (NaN or Inf); x holds the iterate of
+                                   that step.  (A Bi-CGSTAB breakdown rho ~ 0
                                    restarts the iteration from the current
-                                   residual instead (counted in
-                                   hmg_solve_info.restarts)                     */
+                                   residual instead, counted in
+                                   hmg_solve_info.restarts.)                    */
     HMG_PENDING = 6,            /* request not finished yet                     */
     HMG_ERR_TOO_LARGE = 7,      /* request footprint above the context budget   */
     HMG_ERR_UNKNOWN_TICKET = 8,
@@ -113,6 +115,15 @@ typedef struct {
                                 path (Section 6 names no breakdown rule; the
                                 library restarts when |rho| <= 1e-14 ||rhat||
                                 ||r||); 0: off (default)                       */
+    int    true_res_every;   /* K > 0: after every K-th full iteration that
+                                misses rtol the residual is recomputed in
+                                FP64 as b - L x and the iteration restarts
+                                from it (rhat = p = r), or ends when it meets
+                                rtol; 0: only when the recursive residual
+                                meets rtol (default)                           */
+    int    nan_at;           /* K > 0: the residual norm at the end of
+                                iteration K is taken as NaN, to exercise the
+                                not-finite exit (HMG_ERR_BREAKDOWN); 0: off    */
     int    reserved[2];
 } hmg_opts;
 
@@ -189,13 +200,14 @@ hmg_status hmg_vcycle(hmg_grid *g, const hmg_c64 *r, hmg_c64 *z);
 hmg_status hmg_vcycle_dev(hmg_grid *g, const void *d_r, void *d_z, void *stream);
 
 /* ---- solve: right-preconditioned Bi-CGSTAB (Section 6) ---------------------
- * Solves L^h x = f for every right-hand side of the grid from the zero
- * initial guess of Section 6.  x: nrhs fields of (n+2)^2, the solutions on
- * exit.  Stops when ||r|| / ||f|| <= rtol (checked at every
- * half iteration and confirmed with the recomputed FP64 residual) or after
- * maxit iterations.  info: nrhs entries (may be NULL).  Returns the worst
- * status over the right-hand sides. */
-hmg_status hmg_solve(hmg_grid *g, hmg_c64 *x, double rtol, int maxit,
+ * Solves L^h x = f for every right-hand side of the grid.  x0: nrhs initial
+ * guesses of (n+2)^2 (host, read before any device work), or NULL for the
+ * zero initial guess of Section 6.  x: nrhs fields of (n+2)^2, the
+ * solutions on exit (x may equal x0).  Stops when ||r|| / ||f|| <= rtol
+ * (checked at every half iteration and confirmed with the recomputed FP64
+ * residual) or after maxit iterations.  info: nrhs entries (may be NULL).
+ * Returns the worst status over the right-hand sides. */
+hmg_status hmg_solve(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, double rtol, int maxit,
                      hmg_solve_info *info);
 /* Device variant for right-hand side `rhs`: d_b (input, may be NULL = the
  * grid's stored f) and d_x (in: initial guess if x0_given, out: solution) are

@@ -114,6 +114,15 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's parallel loops use (results do
+    not depend on it: every reduction is sequential)."""
+    fn = lib().omp_set_num_threads
+    fn.argtypes = [ctypes.c_int]
+    fn.restype = None
+    fn(int(n))
+
+
 def _c(a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     return a, a.ctypes.data_as(ctypes.c_void_p)

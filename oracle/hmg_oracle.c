@@ -717,8 +717,8 @@ int orc_bicgstab_ex(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
                             force_breakdown_at, 0, 0);
 }
 
-/* true_res_every = K > 0: after every K-th full iteration that has not met
- * the tolerance, the residual is recomputed as b - A x; if that meets the
+/* true_res_every = K > 0: after every K-th full iteration (counted among the
+ * full iterations that miss the tolerance) the residual is recomputed as b - A x; if that meets the
  * tolerance the solve ends, otherwise it restarts from it (rhat = r, p = v =
  * 0), as after a failed convergence check.  A residual norm that is not
  * finite ends the solve with ORC_BREAKDOWN; nan_at = K > 0 treats the norm
@@ -736,7 +736,7 @@ int orc_bicgstab_ex2(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
     orc_cplx *ph = malloc(m * sizeof(orc_cplx)), *s  = malloc(m * sizeof(orc_cplx));
     orc_cplx *sh = malloc(m * sizeof(orc_cplx)), *t  = malloc(m * sizeof(orc_cplx));
     double bn = nrm2(m, b);
-    int    half = 0, nhist = 0, status = ORC_NOT_CONVERGED;
+    int    half = 0, nhist = 0, status = ORC_NOT_CONVERGED, fulls = 0;
     info->restarts = 0;
     info->vcycles  = 0;
     if (bn == 0.0) bn = 1.0;
@@ -804,7 +804,7 @@ int orc_bicgstab_ex2(orc_grid *g, const orc_cplx *b, orc_cplx *x, double rtol,
         if (!isfinite(rn)) { status = ORC_BREAKDOWN; break; }
         if (rn / bn <= rtol) {
             converged = 1;
-        } else if (true_res_every > 0 && half % (2 * true_res_every) == 0 && half < 2 * maxit) {
+        } else if (true_res_every > 0 && ++fulls % true_res_every == 0 && half < 2 * maxit) {
             orc_residual(n, h, g->k[0], 0.0, b, x, r);
             rn = nrm2(m, r);
             if (rn / bn <= rtol) {

@@ -546,6 +546,8 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     if (o.relax_order != HMG_ORDER_COLOUR && o.relax_order != HMG_ORDER_LEX)
         return hmg_fail(HMG_ERR_INVALID, "bad relax_order");
     if (o.breakdown_at < 0) return hmg_fail(HMG_ERR_INVALID, "breakdown_at must be >= 0");
+    if (o.true_res_every < 0) return hmg_fail(HMG_ERR_INVALID, "true_res_every must be >= 0");
+    if (o.nan_at < 0) return hmg_fail(HMG_ERR_INVALID, "nan_at must be >= 0");
     if (!std::isfinite(o.beta) || o.nu_pre < 0 || o.nu_post < 0 || o.kacz_pre < 0 || o.kacz_post < 0 ||
         o.nu_pre > 64 || o.nu_post > 64 || o.kacz_pre > 64 || o.kacz_post > 64)
         return hmg_fail(HMG_ERR_INVALID, "bad sweep counts or beta");

@@ -32,13 +32,18 @@ struct KState {
     double true_rel;     // ||b - L x|| / ||b|| from the last true-residual check
     int    halfsteps;
     int    maxhalf;
-    int    done;         // 0 running, 1 recursive residual met rtol, 2 maxit
+    int    done;         // 0 running, 1 recursive residual met rtol, 2 maxit,
+                         // 3 a residual norm was not finite
     int    half_exit;    // converged at the half step of this iteration
     int    restart;      // next p-update restarts with rhat = p = r
     int    stop;         // done || half_exit: later kernels of the iteration skip
     int    restarts;
     int    hist_cap;
     int    force_bd;     // > 0: iteration after which a breakdown is forced
+    int    true_every;   // > 0: true-residual check after every true_every-th full iteration
+    int    nan_at;       // > 0: the norm after iteration nan_at is taken as NaN (test hook)
+    int    fullits;      // full iterations that missed rtol (the true_every counter)
+    int    check;        // a true-residual check is due after this iteration
 };
 
 // Device pointers of one solve slot (finest-level Krylov vectors).
@@ -150,7 +155,10 @@ void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m
 // ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
 int  krylov_nblocks(const Geo &g);
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given,
-              double rtol, int maxhalf, int force_bd);
+              double rtol, int maxhalf, int force_bd, int true_every = 0, int nan_at = 0);
+// The periodic true-residual check (when due): r = b - L x; the solve ends
+// if it meets rtol, else restarts from it (rhat = p = r).
+void kry_checkpoint(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 // the single-block finalisations after a fused product (nb partial blocks)

@@ -363,7 +363,7 @@ __global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, c
 }
 
 __global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol, int maxhalf, int hist_cap,
-                                                     int force_bd) {
+                                                     int force_bd, int true_every, int nan_at) {
     double tot[2];
     finalize_sums<2>(K.partials, nb, tot);
     if (threadIdx.x || threadIdx.y) return;
@@ -386,6 +386,10 @@ __global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol
     s->restarts = 0;
     s->hist_cap = hist_cap;
     s->force_bd = force_bd;
+    s->true_every = true_every;
+    s->nan_at = nan_at;
+    s->fullits = 0;
+    s->check = 0;
     double rel = sqrt(tot[1]) / bn;
     if (hist_cap > 0) K.hist[0] = rel;
     s->done = (rel <= rtol) ? 1 : 0;
@@ -494,6 +498,12 @@ __global__ __launch_bounds__(NT) void k_kry_s_fin(KDev K, int nb) {
     s->snorm2 = tot[0];
     double rel = sqrt(tot[0]) / s->bnorm;
     if (s->halfsteps < s->hist_cap) K.hist[s->halfsteps] = rel;
+    if (!isfinite(rel)) {   // not finite: end with the iterate of the last full step
+        s->done = 3;
+        s->stop = 1;
+        publish_done(K);
+        return;
+    }
     if (rel <= s->rtol) {
         s->half_exit = 1;
         s->stop = 1;
@@ -629,8 +639,15 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
     s->halfsteps += 1;
     s->rnorm2 = tot[0];
     double rn = sqrt(tot[0]);
+    if (s->nan_at > 0 && s->halfsteps == 2 * s->nan_at) rn = __builtin_nan("");
     double rel = rn / s->bnorm;
     if (s->halfsteps < s->hist_cap) K.hist[s->halfsteps] = rel;
+    if (!isfinite(rel)) {
+        s->done = 3;
+        s->stop = 1;
+        publish_done(K);
+        return;
+    }
     if (rel <= s->rtol) {
         s->done = 1;
         s->stop = 1;
@@ -641,6 +658,11 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
         s->done = 2;
         s->stop = 1;
         publish_done(K);
+        return;
+    }
+    if (s->true_every > 0 && ++s->fullits % s->true_every == 0) {
+        // the check kernels that follow recompute r and restart from it
+        s->check = 1;
         return;
     }
     C<double> rho_new = cmk(tot[1], tot[2]);
@@ -706,6 +728,52 @@ __global__ void k_kry_restart(KDev K) {
     publish_done(K);
 }
 
+// ---- the periodic true-residual check (only when iter_fin marked it due) --
+__global__ __launch_bounds__(NT) void k_kry_check_true(GeoT g, double H, double ih2, const double *__restrict__ k,
+                                                       KDev K) {
+    if (!K.st->check) return;
+    int i = blockIdx.x * BX + threadIdx.x;
+    double v[1] = {0.0};
+    for (int rr = 0; rr < KRY; ++rr) {
+        int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
+        if (i > g.N || j > g.N) continue;
+        size_t p = (size_t)j * g.M + i;
+        Row<double> r = row_at<double>(i, j, g.N, H, ih2, k[p], 0.0);
+        C<double> rp = csub(K.b[p], row_apply(r, K.x, i, j, g.N, g.M));
+        K.r[p] = rp;
+        v[0] += rp.x * rp.x + rp.y * rp.y;
+    }
+    block_partials<1>(v, K.partials);
+}
+
+__global__ __launch_bounds__(NT) void k_kry_check_fin(KDev K, int nb) {
+    KState *s = K.st;
+    if (!s->check) return;
+    double tot[1];
+    finalize_sums<1>(K.partials, nb, tot);
+    if (threadIdx.x || threadIdx.y) return;
+    s->check = 0;
+    s->rnorm2 = tot[0];
+    const double rel = sqrt(tot[0]) / s->bnorm;
+    s->true_rel = rel;
+    if (!isfinite(rel)) {
+        s->done = 3;
+        s->stop = 1;
+    } else if (rel <= s->rtol) {
+        s->done = 1;        // confirmed again by the solve's final check
+        s->stop = 1;
+    } else {
+        s->restart = 1;
+        s->restarts += 1;
+        s->rho[0] = tot[0]; s->rho[1] = 0.0;
+        s->rho_old[0] = 1.0; s->rho_old[1] = 0.0;
+        s->alpha[0] = 1.0; s->alpha[1] = 0.0;
+        s->omega[0] = 1.0; s->omega[1] = 0.0;
+        s->rhat_norm2 = tot[0];
+    }
+    publish_done(K);
+}
+
 static inline dim3 kgrid(const Geo &g) { return dim3((g.M + BX - 1) / BX, (g.M + BY * KRY - 1) / (BY * KRY)); }
 
 int krylov_nblocks(const Geo &g) {
@@ -716,13 +784,21 @@ int krylov_nblocks(const Geo &g) {
 static inline void hk(const Geo &g, double &H, double &ih2) { H = g.H; ih2 = 1.0 / (g.H * g.H); }
 
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given, double rtol,
-              int maxhalf, int force_bd) {
+              int maxhalf, int force_bd, int true_every, int nan_at) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
     k_kry_init<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, x0_given);
     // the history buffer holds maxhalf + 2 entries (allocated by the caller)
-    k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2, force_bd);
+    k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2, force_bd, true_every,
+                                              nan_at);
+}
+void kry_checkpoint(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+    double H, ih2;
+    hk(g, H, ih2);
+    KDev d = kdev(K);
+    k_kry_check_true<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
+    k_kry_check_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
 }
 void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K) {
     k_kry_update_p<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));

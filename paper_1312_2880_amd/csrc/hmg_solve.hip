@@ -74,6 +74,14 @@ extern "C" double hmg_ctx_clock(const hmg_ctx *ctx) { return ctx ? hmg_now() - c
 // ---------------------------------------------------------------------------
 // one Bi-CGSTAB iteration
 // ---------------------------------------------------------------------------
+// Whether the solve keeps its x update in the preconditioner's input space
+// (y += alpha p + omega s, x += B y when the solve ends): where the finest
+// up kernel forms the Krylov products, unless periodic true-residual checks
+// need the current x every iteration.
+static bool y_space(const hmg_grid *g, const Slot &S) {
+    return vcycle_forms_products(g, S) && g->opts.true_res_every == 0;
+}
+
 static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     const Geo &g0 = g->lev[0].geo;
     const int *stop = &S.K.st->stop;
@@ -82,7 +90,7 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     // form them, else from kernels of their own.  Where it can, p^ and s^
     // are not stored either: x advances as x + B y with y += alpha p +
     // omega s (B is linear and fixed), folded in when the solve ends.
-    const bool ym = vcycle_forms_products(g, S);
+    const bool ym = y_space(g, S);
     MvFuse mv;
     mv.kind = 1;
     mv.out = S.K.v;
@@ -104,6 +112,7 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     else kry_matvec_omega(s, g0, g->k0, S.K);
     if (ym) kry_update_yr(s, g0, S.K);
     else kry_update_xr(s, g0, S.K);
+    if (g->opts.true_res_every > 0) kry_checkpoint(s, g0, g->k0, S.K);
 }
 
 static hmg_status iteration_graph(hmg_grid *g, Slot &S) {
@@ -168,8 +177,9 @@ static hmg_status run_begin(SolveRun &R, int x0_given) {
     hmg_grid *g = R.g;
     hmg_status st = ensure_hist(*R.S, R.maxit);
     if (st) return st;
-    kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit, g->opts.breakdown_at);
-    if (vcycle_forms_products(g, *R.S))   // y = 0 (the x update in the preconditioner's input space)
+    kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit, g->opts.breakdown_at,
+             g->opts.true_res_every, g->opts.nan_at);
+    if (y_space(g, *R.S))   // y = 0 (the x update in the preconditioner's input space)
         launch_fill_zero(P64, R.s, R.S->K.ph, (size_t)g->lev[0].geo.M * g->lev[0].geo.M, nullptr);
     HIPCHK(hipGetLastError());
     R.inflight = 0;
@@ -198,7 +208,7 @@ static bool run_done(const SolveRun &R) { return __atomic_load_n(R.S->K.done_hos
 static hmg_status run_finish(SolveRun &R, hmg_solve_info *info) {
     HIPCHK(hipStreamSynchronize(R.s));
     Slot &S = *R.S;
-    if (vcycle_forms_products(R.g, S)) {
+    if (y_space(R.g, S)) {
         // x += B y, y = 0
         enqueue_vcycle(R.g, S, S.K.ph, S.K.sh, R.s, nullptr);
         kry_fold(R.s, R.g->lev[0].geo, S.K);
@@ -210,6 +220,8 @@ static hmg_status run_finish(SolveRun &R, hmg_solve_info *info) {
     hmg_status res;
     if (k.done == 1 && k.true_rel <= R.rtol) {
         res = HMG_OK;
+    } else if (k.done == 3 || !std::isfinite(k.true_rel)) {
+        res = HMG_ERR_BREAKDOWN;   // a residual norm was not finite
     } else if (k.done == 1 && k.halfsteps < 2 * R.maxit) {
         kry_restart_from_true(R.s, S.K);
         HIPCHK(hipGetLastError());
@@ -271,20 +283,30 @@ static hmg_status check_solve_args(double rtol, int maxit) {
     return HMG_OK;
 }
 
-extern "C" hmg_status hmg_solve(hmg_grid *g, hmg_c64 *x, double rtol, int maxit, hmg_solve_info *info) {
+extern "C" hmg_status hmg_solve(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, double rtol, int maxit,
+                                hmg_solve_info *info) {
     if (!g || !x) return hmg_fail(HMG_ERR_INVALID, "null argument");
     hmg_status st = check_solve_args(rtol, maxit);
     if (st) return st;
-    HIPCHK(hipSetDevice(g->ctx->device));
     size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
+    if (x0)
+        for (size_t q = 0; q < m0 * (size_t)g->nrhs; ++q)
+            if (!std::isfinite(x0[q].re) || !std::isfinite(x0[q].im))
+                return hmg_fail(HMG_ERR_INVALID, "x0 must be finite");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    // every initial guess is on the device before x (which may alias x0) is
+    // written
+    if (x0)
+        for (int r = 0; r < g->nrhs; ++r)
+            HIPCHK(hipMemcpy(g->slot[r].K.x, x0 + m0 * r, m0 * 16, hipMemcpyHostToDevice));
     hmg_status worst = HMG_OK;
     for (int r = 0; r < g->nrhs; ++r) {
         SolveRun R;
         run_init(R, g, &g->slot[r], g->stream, rtol, maxit);
-        hmg_status sr = run_solve(R, 0, info ? &info[r] : nullptr);
-        if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED) return sr;
+        hmg_status sr = run_solve(R, x0 ? 1 : 0, info ? &info[r] : nullptr);
+        if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED && sr != HMG_ERR_BREAKDOWN) return sr;
         HIPCHK(hipMemcpy(x + m0 * r, g->slot[r].K.x, m0 * 16, hipMemcpyDeviceToHost));
-        if (sr != HMG_OK) worst = sr;
+        if (sr != HMG_OK && worst == HMG_OK) worst = sr;
     }
     return worst;
 }
@@ -303,7 +325,7 @@ extern "C" hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void 
     SolveRun R;
     run_init(R, g, &S, s, rtol, maxit);
     hmg_status sr = run_solve(R, x0_given, info);
-    if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED) return sr;
+    if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED && sr != HMG_ERR_BREAKDOWN) return sr;
     HIPCHK(hipMemcpyAsync(d_x, S.K.x, bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return sr;
@@ -373,7 +395,7 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
                 hmg_status sr = run_finish(R, inf);
                 if (sr == HMG_PENDING && !over) continue;
                 if (sr == HMG_PENDING) sr = HMG_ERR_NOT_CONVERGED;
-                if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED) return sr;
+                if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED && sr != HMG_ERR_BREAKDOWN) return sr;
                 if (sr != HMG_OK) worst = sr;
                 size_t m0 = (size_t)grids[q]->lev[0].geo.M * grids[q]->lev[0].geo.M;
                 HIPCHK(hipMemcpy(x[q] + m0 * it.r, R.S->K.x, m0 * 16, hipMemcpyDeviceToHost));

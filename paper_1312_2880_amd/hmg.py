@@ -50,7 +50,8 @@ class Opts(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("one_pass_kernels", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("bottom_dense", ctypes.c_int), ("relax_order", ctypes.c_int),
-                ("breakdown_at", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("breakdown_at", ctypes.c_int), ("true_res_every", ctypes.c_int),
+                ("nan_at", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class Plan(ctypes.Structure):
@@ -97,7 +98,7 @@ _SIGS = {
     "hmg_grid_footprint": (_sz, [P]),
     "hmg_vcycle": (_i, [P, P, P]),
     "hmg_vcycle_dev": (_i, [P, P, P, P]),
-    "hmg_solve": (_i, [P, P, _d, _i, P]),
+    "hmg_solve": (_i, [P, P, P, _d, _i, P]),
     "hmg_solve_dev": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
     "hmg_solve_batch": (_i, [P, _i, P, P, _d, _i, P]),
     "hmg_submit": (_i, [P, P, P]),
@@ -245,7 +246,7 @@ class Context:
         xp = (ctypes.c_void_p * count)(*[_ptr(x).value for x in xs])
         ip = (ctypes.c_void_p * count)(*[ctypes.addressof(i) for i in infos])
         st = _lib.hmg_solve_batch(self._h, count, handles, xp, rtol, maxit, ip)
-        _check(st, (OK, ERR_NOT_CONVERGED))
+        _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
         return xs, [[_info_dict(i) for i in inf] for inf in infos]
 
 
@@ -312,11 +313,17 @@ class Grid:
     def vcycle_dev(self, d_r, d_z, stream=None):
         _check(_lib.hmg_vcycle_dev(self._h, _dptr(d_r), _dptr(d_z), _stream(stream)))
 
-    def solve(self, rtol=1e-6, maxit=500):
+    def solve(self, rtol=1e-6, maxit=500, x0=None):
+        """Solve every right-hand side; x0: initial guesses (nrhs fields, or
+        one field for nrhs = 1), None for zero."""
         x = np.zeros((self.nrhs, self.n + 2, self.n + 2), np.complex128)
+        x0p = None
+        if x0 is not None:
+            x0 = np.ascontiguousarray(np.broadcast_to(x0, x.shape), np.complex128)
+            x0p = _ptr(x0)
         infos = (SolveInfo * self.nrhs)()
-        st = _lib.hmg_solve(self._h, _ptr(x), rtol, maxit, infos)
-        _check(st, (OK, ERR_NOT_CONVERGED))
+        st = _lib.hmg_solve(self._h, x0p, _ptr(x), rtol, maxit, infos)
+        _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
         return x, [_info_dict(i) for i in infos]
 
     def history(self, rhs=0):
@@ -332,7 +339,7 @@ class Grid:
         info = SolveInfo()
         st = _lib.hmg_solve_dev(self._h, rhs, _dptr(d_b), _dptr(d_x), int(x0), rtol, maxit,
                                 ctypes.byref(info), _stream(stream))
-        _check(st, (OK, ERR_NOT_CONVERGED))
+        _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
         return _info_dict(info)
 
     # ---- single building blocks on device fields (level precision) ----

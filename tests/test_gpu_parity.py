@@ -1000,6 +1000,78 @@ def test_vcycle_and_solve_layered_4095(ctx, hmg):
     g.close()
 
 
+@pytest.mark.parametrize("n", [63, 1023])
+def test_host_solve_from_x0_matches_oracle(ctx, hmg, n):
+    """hmg_solve with a host initial guess (Section 6 starts from x0 = 0; any
+    x0 is accepted): the first half steps follow the oracle's solve from the
+    same x0, and the solution meets the tolerance."""
+    say(f"case host x0 solve n={n}")
+    if n == 63:
+        h, k, f = inputs.workload_const_point(63)
+    else:
+        h, k, f = inputs.workload_layered_1023()
+    og = oracle.Grid(h, k, variant=0)
+    x0, _ = og.bicgstab(f, rtol=1e-30, maxit=2)
+    g = hmg.Grid(ctx, h, k, f, variant=0)
+    x, info = g.solve(rtol=1e-6, maxit=400, x0=x0)
+    _, ref = og.bicgstab(f, rtol=1e-6, maxit=400, x0=x0, history=True)
+    assert info[0]["status"] == hmg.OK
+    np.testing.assert_allclose(g.history(0)[:8], ref["history"][:8], rtol=1e-7)
+    assert abs(info[0]["iters"] - ref["iters"]) <= count_margin(ref["iters"])
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+
+
+@pytest.mark.parametrize("n,K", [(63, 5), (1023, 10)])
+def test_true_residual_every_matches_oracle(ctx, hmg, n, K):
+    """true_res_every = K: after every K-th full iteration the residual is
+    recomputed as b - L x and the iteration restarts from it.  The GPU's
+    history follows the oracle's through the first restarts (where it jumps
+    to the true residual) and both count the same restarts while the
+    iterations agree."""
+    say(f"case true_res_every n={n} K={K}")
+    if n == 63:
+        h, k, f = inputs.workload_const_point(63)
+    else:
+        h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=0, true_res_every=K)
+    x, info = g.solve(rtol=1e-6, maxit=400)
+    og = oracle.Grid(h, k, variant=0)
+    _, ref = og.bicgstab(f, rtol=1e-6, maxit=400, history=True, true_res_every=K)
+    say(f"  gpu {info[0]['iters']} ({info[0]['restarts']} restarts), oracle {ref['iters']} ({ref['restarts']})")
+    assert info[0]["status"] == hmg.OK and info[0]["rel_res_true"] <= 1e-6
+    m = 4 * K + 4
+    np.testing.assert_allclose(g.history(0)[:m], ref["history"][:m], rtol=1e-6)
+    assert info[0]["restarts"] >= 2
+    assert abs(info[0]["iters"] - ref["iters"]) <= count_margin(ref["iters"])
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+
+
+@pytest.mark.parametrize("n", [63, 1023])
+def test_not_finite_residual_ends_with_breakdown(ctx, hmg, n):
+    """A residual norm that is not finite ends the solve with
+    HMG_ERR_BREAKDOWN and x holding the iterate of that step: with the norm
+    after iteration 4 forced to NaN (nan_at, from the host) the solve stops at
+    half step 8 and x equals the iterate of a solve stopped by maxit = 4."""
+    say(f"case NaN exit n={n}")
+    if n == 63:
+        h, k, f = inputs.workload_const_point(63)
+    else:
+        h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=2, nan_at=4)
+    x, info = g.solve(rtol=1e-6, maxit=300)
+    assert info[0]["status"] == hmg.ERR_BREAKDOWN and info[0]["halfsteps"] == 8, info[0]
+    g4 = hmg.Grid(ctx, h, k, f, variant=2)
+    x4, info4 = g4.solve(rtol=1e-30, maxit=4)
+    assert info4[0]["status"] == hmg.ERR_NOT_CONVERGED
+    assert rel(x[0], x4[0]) <= 1e-14
+    og = oracle.Grid(h, k, variant=2)
+    xo, infoo = og.bicgstab(f, rtol=1e-6, maxit=300, nan_at=4)
+    assert infoo["status"] == oracle.BREAKDOWN
+    assert rel(x[0], xo) <= 1e-9
+
+
 def test_invalid_arguments(ctx, hmg):
     k = np.full((64, 64), 5.0)
     with pytest.raises(hmg.HmgError):
@@ -1012,6 +1084,10 @@ def test_invalid_arguments(ctx, hmg):
         hmg.Grid(ctx, 1 / 80, k, coarsest_n=32)        # coarsest_n above 31
     with pytest.raises(hmg.HmgError):
         hmg.Grid(ctx, 1 / 80, k, breakdown_at=-1)      # forced breakdown index below 0
+    with pytest.raises(hmg.HmgError):
+        hmg.Grid(ctx, 1 / 80, k, true_res_every=-1)
+    with pytest.raises(hmg.HmgError):
+        hmg.Grid(ctx, 1 / 80, k, nan_at=-2)
     k = np.full((65, 65), 5.0)
     k[3, 3] = 0.0
     with pytest.raises(hmg.HmgError):
@@ -1050,6 +1126,81 @@ def test_solve_dev_with_torch_buffers(ctx, hmg):
 # ---------------------------------------------------------------------------
 # mixed precision: complex-float V-cycle under the FP64 Bi-CGSTAB
 # ---------------------------------------------------------------------------
+
+def o11_grid(h, k, gpu_grid, one_pass=False, **kw):
+    """The oracle's precision-form cycle with the stores of the GPU grid's
+    schedule: fused kernels (Kaczmarz iterate stored every S sweeps of the
+    grid's tile configuration, levels with n <= 31 one double block, the
+    cycle's input and output double when the finest level runs the fused
+    Gauss-Seidel kernels) or one-pass kernels (every step stores)."""
+    og = oracle.Grid(h, k, **kw)
+    plan = gpu_grid.plan()
+    if one_pass:
+        return og.set_mixed(oracle.MIX_ONEPASS, 1, 0, True)
+    sweeps = {hmg_configs_sweeps(gpu_grid.kacz_config(l)) for l in range(len(plan))
+              if plan[l]["smoother"] == "KACZ" and plan[l]["n"] > 31}
+    assert len(sweeps) <= 1, sweeps
+    every = sweeps.pop() if sweeps else 1
+    top_fused = plan[0]["smoother"] == "GS" and plan[0]["pre"] == 1 and plan[0]["post"] == 1
+    round_io = not (top_fused or plan[0]["n"] <= 31)
+    return og.set_mixed(oracle.MIX_FUSED, every, 31, round_io)
+
+
+def hmg_configs_sweeps(cfg):
+    from paper_1312_2880_amd import hmg as mod
+    return mod.kacz_tile_configs()[cfg][1] if cfg >= 0 else 1
+
+
+MIXED_CASES = [
+    ("layered255_sl", 255, 0), ("layered255_hyb", 255, 2),
+    ("layered1023_sl", 1023, 0), ("layered1023_hyb", 1023, 2),
+]
+
+
+@pytest.mark.parametrize("one_pass", [False, True], ids=["fused", "one_pass"])
+@pytest.mark.parametrize("name,n,variant", MIXED_CASES)
+def test_mixed_vcycle_matches_o11(ctx, hmg, name, n, variant, one_pass):
+    """The complex-float V-cycle against the oracle's precision-form cycle
+    (O11) with the same stores, element by element.  The two sides round the
+    same FP64 values to float at the same points; they differ where a value's
+    double-precision rounding differences (~1e-16 relative) push it across a
+    float rounding boundary, a ~1e-8 event per stored value that flips one
+    float ulp.  Bound: the GPU-O11 difference must stay below 5 % of the
+    whole effect of the float stores (|O11 - FP64|), which a missing or extra
+    store, a float k in the wrong place or an FP32 stencil sum would exceed."""
+    say(f"case mixed vcycle vs O11 {name} one_pass={one_pass}")
+    h, k, _ = inputs.layered_problem(n, 2, 2 * math.pi * 40 * (n + 1) / 1024)
+    g = hmg.Grid(ctx, h, k, precision=hmg.MIXED, variant=variant, autotune=0,
+                 one_pass_kernels=int(one_pass))
+    og = o11_grid(h, k, g, one_pass=one_pass, variant=variant)
+    o64 = oracle.Grid(h, k, variant=variant)
+    for seed in (7, 8):
+        r = inputs.random_field(n, seed)
+        got, want, w64 = g.vcycle(r), og.vcycle(r), o64.vcycle(r)
+        d, eff = rel(got, want), rel(want, w64)
+        say(f"  seed {seed}: |gpu - O11| {d:.3e}, |O11 - FP64| {eff:.3e}")
+        assert eff > 1e-9
+        assert d <= 0.05 * eff, (d, eff)
+
+
+@pytest.mark.parametrize("name,n,variant", MIXED_CASES[:2])
+def test_mixed_solve_matches_o11(ctx, hmg, name, n, variant):
+    """The mixed solve against the oracle's Bi-CGSTAB around the O11 cycle:
+    the same count (margin of the FP64 solves), the early residual history,
+    and the oracle's residual of the GPU solution."""
+    say(f"case mixed solve vs O11 {name}")
+    h, k, f = inputs.layered_problem(n, 2, 2 * math.pi * 40 * (n + 1) / 1024)
+    g = hmg.Grid(ctx, h, k, f, precision=hmg.MIXED, variant=variant, autotune=0)
+    og = o11_grid(h, k, g, variant=variant)
+    x, info = g.solve(rtol=1e-6, maxit=400)
+    _, ref = og.bicgstab(f, rtol=1e-6, maxit=400, history=True)
+    say(f"  gpu {info[0]['iters']} O11 {ref['iters']}")
+    assert info[0]["status"] == hmg.OK
+    assert abs(info[0]["iters"] - ref["iters"]) <= count_margin(ref["iters"])
+    np.testing.assert_allclose(g.history(0)[:10], ref["history"][:10], rtol=1e-5)
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+
 
 def test_mixed_vcycle_close_to_fp64_oracle(ctx, hmg):
     say("case mixed vcycle layered1023")

@@ -95,6 +95,6 @@ def test_null_arguments_are_rejected():
     assert lib.hmg_grid_create(None, 7, 0.125, hmg._ptr(k), None, 1, None,
                                ctypes.byref(out)) == hmg.ERR_INVALID
     assert lib.hmg_vcycle(None, None, None) == hmg.ERR_INVALID
-    assert lib.hmg_solve(None, None, 1e-6, 10, None) == hmg.ERR_INVALID
+    assert lib.hmg_solve(None, None, None, 1e-6, 10, None) == hmg.ERR_INVALID
     assert lib.hmg_poll(None, 1, None, None) == hmg.ERR_INVALID
     assert b"null" in lib.hmg_last_error()
