@@ -217,6 +217,24 @@ hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void *d_x,
                          int x0_given, double rtol, int maxit,
                          hmg_solve_info *info, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of hmg_solve_dev (same arguments, results and stream behaviour) without
+ * any device allocation.  Its reduction partials and residual history live
+ * in a fixed device array of HMG_STATIC_SCRATCH_BYTES per GPU, held from the
+ * first hmg_ctx_create on that GPU until the process ends; the iteration is
+ * enqueued kernel by kernel (no graph is instantiated).  A grid and maxit
+ * whose partials (3 doubles per reduction block, at most about 17,000
+ * blocks at n = 4095) and history (2 maxit + 2 doubles) exceed the array
+ * are rejected with HMG_ERR_TOO_LARGE before any work.  Every call on one
+ * GPU shares the array and overwrites it: calls that overlap on one GPU (on
+ * different streams or threads) race, so the caller serialises them.
+ * hmg_solve_history keeps no record of these solves (it returns 0). */
+#define HMG_STATIC_SCRATCH_BYTES (4 << 20)
+hmg_status hmg_solve_dev_static(hmg_grid *g, int rhs, const void *d_b, void *d_x,
+                                int x0_given, double rtol, int maxit,
+                                hmg_solve_info *info, void *stream);
+
 /* Relative residuals ||r|| / ||b|| of the last solve of right-hand side
  * `rhs`, one per half iteration (entry 0 = the initial residual): copies up
  * to cap values into out and returns how many the solve produced (-1 on

@@ -34,6 +34,7 @@ struct hmg_ctx {
     int    device = 0;
     size_t budget = 0;      // bytes of device memory the server may admit
     double t0 = 0.0;        // clock origin
+    double *scratch = nullptr;   // device address of this GPU's static solve scratch
     std::unique_ptr<ServerState> server;
 };
 

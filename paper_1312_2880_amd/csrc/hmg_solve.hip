@@ -45,6 +45,28 @@ struct ServerState {
 
 static void server_stop(hmg_ctx *ctx);
 
+// Device memory of the allocation-free solve (hmg_solve_dev_static): the
+// reduction partials and the residual history of one solve at a time per
+// GPU.  In host code `scratch` only names the symbol; its device address on
+// each GPU comes from hipGetSymbolAddress (below), taken once per device
+// with that device current, and only that address is passed to kernels.
+static __device__ __align__(256) double scratch[HMG_STATIC_SCRATCH_BYTES / sizeof(double)];
+static std::mutex g_scratch_mu;
+static std::map<int, double *> g_scratch_addr;   // device -> address of its copy of scratch
+
+static hmg_status scratch_address(int device, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it == g_scratch_addr.end()) {
+        double *p = nullptr;
+        HIPCHK(hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)));
+        if (!p) return hmg_fail(HMG_ERR_DEVICE, "no device address for the static scratch");
+        it = g_scratch_addr.emplace(device, p).first;
+    }
+    *out = it->second;
+    return HMG_OK;
+}
+
 extern "C" hmg_status hmg_ctx_create(int device, size_t hbm_budget_bytes, hmg_ctx **out) {
     if (!out) return hmg_fail(HMG_ERR_INVALID, "null output handle");
     *out = nullptr;
@@ -54,8 +76,12 @@ extern "C" hmg_status hmg_ctx_create(int device, size_t hbm_budget_bytes, hmg_ct
     HIPCHK(hipSetDevice(device));
     size_t free_b = 0, total_b = 0;
     HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    double *scr = nullptr;
+    hmg_status sst = scratch_address(device, &scr);   // with `device` current
+    if (sst != HMG_OK) return sst;
     hmg_ctx *c = new hmg_ctx();
     c->device = device;
+    c->scratch = scr;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
     c->t0 = hmg_now();
     c->server.reset(new ServerState());
@@ -171,12 +197,15 @@ struct SolveRun {
     KState     *hs = nullptr;      // pinned, 2 records
     hipEvent_t  ev[2] = {};
     double      t_start = 0.0;
+    bool        direct = false;    // enqueue kernel by kernel (no graph, no history allocation)
 };
 
 static hmg_status run_begin(SolveRun &R, int x0_given) {
     hmg_grid *g = R.g;
-    hmg_status st = ensure_hist(*R.S, R.maxit);
-    if (st) return st;
+    if (!R.direct) {
+        hmg_status st = ensure_hist(*R.S, R.maxit);
+        if (st) return st;
+    }
     kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit, g->opts.breakdown_at,
              g->opts.true_res_every, g->opts.nan_at);
     if (y_space(g, *R.S))   // y = 0 (the x update in the preconditioner's input space)
@@ -191,8 +220,13 @@ static hmg_status run_begin(SolveRun &R, int x0_given) {
 // Queue one iteration and an event behind it; the iteration's kernels write
 // the done flag to pinned host memory (run_done).
 static hmg_status run_issue(SolveRun &R) {
-    hmg_status st = launch_iteration(R.g, *R.S, R.s);
-    if (st) return st;
+    if (R.direct) {
+        enqueue_iteration(R.g, *R.S, R.s);
+        HIPCHK(hipGetLastError());
+    } else {
+        hmg_status st = launch_iteration(R.g, *R.S, R.s);
+        if (st) return st;
+    }
     int q = R.issued & 1;
     HIPCHK(hipEventRecord(R.ev[q], R.s));
     R.issued++;
@@ -325,6 +359,45 @@ extern "C" hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void 
     SolveRun R;
     run_init(R, g, &S, s, rtol, maxit);
     hmg_status sr = run_solve(R, x0_given, info);
+    if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED && sr != HMG_ERR_BREAKDOWN) return sr;
+    HIPCHK(hipMemcpyAsync(d_x, S.K.x, bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return sr;
+}
+
+// The allocation-free form of hmg_solve_dev: the solve runs on a copy of the
+// slot whose reduction partials and residual history point into this GPU's
+// static scratch, and its iterations are enqueued kernel by kernel.
+extern "C" hmg_status hmg_solve_dev_static(hmg_grid *g, int rhs, const void *d_b, void *d_x, int x0_given,
+                                           double rtol, int maxit, hmg_solve_info *info, void *stream) {
+    if (!g || !d_x || rhs < 0 || rhs >= g->nrhs) return hmg_fail(HMG_ERR_INVALID, "bad argument");
+    hmg_status st = check_solve_args(rtol, maxit);
+    if (st) return st;
+    Slot &S = g->slot[rhs];
+    const size_t part_bytes = ((size_t)3 * S.K.pcap * sizeof(double) + 255) & ~size_t(255);
+    const size_t hist_n = 2 * (size_t)maxit + 2;
+    if (part_bytes + hist_n * sizeof(double) > HMG_STATIC_SCRATCH_BYTES)
+        return hmg_fail(HMG_ERR_TOO_LARGE,
+                        "the static scratch (%d bytes) holds %zu bytes of partial sums and %zu of history; "
+                        "this grid and maxit need %zu",
+                        (int)HMG_STATIC_SCRATCH_BYTES, part_bytes, hist_n * sizeof(double),
+                        part_bytes + hist_n * sizeof(double));
+    if (!g->ctx->scratch) return hmg_fail(HMG_ERR_DEVICE, "the context has no static scratch");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : g->stream;
+    size_t bytes = (size_t)g->lev[0].geo.M * g->lev[0].geo.M * 16;
+    if (d_b) HIPCHK(hipMemcpyAsync(S.K.b, d_b, bytes, hipMemcpyDeviceToDevice, s));
+    if (x0_given) HIPCHK(hipMemcpyAsync(S.K.x, d_x, bytes, hipMemcpyDeviceToDevice, s));
+    Slot T = S;                       // same fields and state, other scratch
+    T.iter_graph = nullptr;
+    T.K.partials = g->ctx->scratch;
+    T.K.hist = (double *)((char *)g->ctx->scratch + part_bytes);
+    T.hist_cap = (int)hist_n;
+    SolveRun R;
+    run_init(R, g, &T, s, rtol, maxit);
+    R.direct = true;
+    hmg_status sr = run_solve(R, x0_given, info);
+    S.last_halfsteps = -1;            // the history lived in the static scratch
     if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED && sr != HMG_ERR_BREAKDOWN) return sr;
     HIPCHK(hipMemcpyAsync(d_x, S.K.x, bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipStreamSynchronize(s));

@@ -100,6 +100,7 @@ _SIGS = {
     "hmg_vcycle_dev": (_i, [P, P, P, P]),
     "hmg_solve": (_i, [P, P, P, _d, _i, P]),
     "hmg_solve_dev": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
+    "hmg_solve_dev_static": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
     "hmg_solve_batch": (_i, [P, _i, P, P, _d, _i, P]),
     "hmg_submit": (_i, [P, P, P]),
     "hmg_poll": (_i, [P, ctypes.c_uint64, P, P]),
@@ -339,6 +340,15 @@ class Grid:
         info = SolveInfo()
         st = _lib.hmg_solve_dev(self._h, rhs, _dptr(d_b), _dptr(d_x), int(x0), rtol, maxit,
                                 ctypes.byref(info), _stream(stream))
+        _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
+        return _info_dict(info)
+
+    def solve_dev_static(self, d_x, d_b=None, rhs=0, x0=False, rtol=1e-6, maxit=500, stream=None):
+        """hmg_solve_dev without device allocation (partials and history in
+        the library's fixed per-GPU array; no history record afterwards)."""
+        info = SolveInfo()
+        st = _lib.hmg_solve_dev_static(self._h, rhs, _dptr(d_b), _dptr(d_x), int(x0), rtol, maxit,
+                                       ctypes.byref(info), _stream(stream))
         _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
         return _info_dict(info)
 
