@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--n", type=int, choices=[1023, 2047], default=2047,
                     help="2047: the layered medium at omega = 2 pi 80 (the largest single-GPU "
                          "configuration, the benchmark); 1023: the same medium at omega = 2 pi 40")
+    ap.add_argument("--mixed-fp64-levels", type=int, default=0,
+                    help="finest levels kept in complex double in the mixed solve (0: all float)")
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="timed solves of the same problem with the complex-float preconditioner "
                          "(reported beside the FP64 figure; 0: skip)")
@@ -394,7 +396,8 @@ def main():
     mixed = None
     if args.mixed_steps > 0 and args.precision == "fp64":
         gm = hmg.Grid(ctx, h, k, f, variant=variant, precision=hmg.MIXED,
-                      relax_order=hmg.ORDER_LEX if lex else hmg.ORDER_COLOUR)
+                      relax_order=hmg.ORDER_LEX if lex else hmg.ORDER_COLOUR,
+                      fp64_levels=args.mixed_fp64_levels)
         d_xm = torch.zeros_like(d_b)
         minfo = [gm.solve_dev(d_xm, d_b=d_b, rtol=1e-6, maxit=args.maxit, stream=stream)]   # warm-up
         torch.cuda.synchronize()
@@ -410,6 +413,7 @@ def main():
                  "rel_res_true": minfo[-1]["rel_res_true"],
                  "all_converged": all(i["status"] == hmg.OK and i["rel_res_true"] <= 1e-6 for i in minfo),
                  "rel_diff_vs_fp64": float(np.linalg.norm(xm - x_fp64) / np.linalg.norm(x_fp64)),
+                 "fp64_levels": args.mixed_fp64_levels,
                  "precision": "complex-float V-cycle storage, FP64 arithmetic; FP64 outer Bi-CGSTAB"}
         gm.close()
 

@@ -124,7 +124,17 @@ typedef struct {
     int    nan_at;           /* K > 0: the residual norm at the end of
                                 iteration K is taken as NaN, to exercise the
                                 not-finite exit (HMG_ERR_BREAKDOWN); 0: off    */
-    int    reserved[2];
+    int    fp64_levels;      /* MIXED only: the finest fp64_levels levels keep
+                                complex-double fields and k; the first level
+                                in complex float then takes its right-hand
+                                side and returns its correction in double, so
+                                it must be a Gauss-Seidel level or the bottom
+                                levels (HMG_ERR_INVALID otherwise, and with
+                                the one-pass or lexicographic schedules);
+                                values beyond the levels above the bottom
+                                levels are clamped.  0: every level in float
+                                (default)                                      */
+    int    reserved[1];
 } hmg_opts;
 
 #define HMG_MAX_LEVELS 24

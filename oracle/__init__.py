@@ -100,6 +100,7 @@ def lib():
             "orc_bicgstab_ex2": [P, P, P, d, i, i, P, P, i, i, i, i],
             "orc_grid_override_level": [P, i, i, d, d, i, i],
             "orc_grid_set_mixed": [P, i, i, i, i],
+            "orc_grid_set_mixed_ex": [P, i, i, i, i, i],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name)
@@ -289,15 +290,18 @@ class Grid:
         if rc != 0:
             raise ValueError("invalid override")
 
-    def set_mixed(self, mode=MIX_FUSED, kacz_every=2, block_n=31, round_io=False):
+    def set_mixed(self, mode=MIX_FUSED, kacz_every=2, block_n=31, round_io=False, fp64_levels=0):
         """Precision form (O11): the V-cycle stores its fields in complex
         float and computes in double.  MIX_FUSED rounds where the fused
         kernels store (the Kaczmarz iterate every ``kacz_every`` sweeps;
         levels with n <= ``block_n`` are one double block); MIX_ONEPASS after
         every elementary step; ``round_io`` also rounds the cycle's input and
         output.  MIX_OFF restores the double V-cycle.  The outer Bi-CGSTAB
-        stays double either way."""
-        lib().orc_grid_set_mixed(self._ptr, int(mode), int(kacz_every), int(block_n), int(bool(round_io)))
+        stays double either way.  ``fp64_levels`` (fused mode) keeps the
+        finest levels in double; the first float level then takes and
+        returns double fields."""
+        lib().orc_grid_set_mixed_ex(self._ptr, int(mode), int(kacz_every), int(block_n),
+                                    int(bool(round_io)), int(fp64_levels))
         return self
 
     def vcycle(self, f):

@@ -320,6 +320,7 @@ struct orc_grid {
     int       mix_kacz_every;       /* fused: Kaczmarz sweeps between stores   */
     int       mix_block_n;          /* fused: levels with n <= this form one FP64 block */
     int       mix_round_io;         /* the cycle's input and output are rounded */
+    int       mix_t;                /* first level stored in float (finer ones double) */
     double   *kv[ORC_MAX_LEVELS];   /* k used inside the V-cycle (rounded in the precision form) */
 };
 
@@ -537,8 +538,11 @@ static void vcycle_level(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u)
 /*     a sweep, each restriction, each prolongation-and-add, the coarsest   */
 /*     result.                                                              */
 /* With mix_round_io the cycle's input is rounded before the first step and */
-/* its output after the last (otherwise both stay double).  Only the        */
-/* coloured orders are modelled.                                            */
+/* its output after the last (otherwise both stay double).  With            */
+/* fp64_levels = t > 0 (fused schedule) the finest t levels keep double     */
+/* fields and k, and level t, the first in float, takes its right-hand side */
+/* and returns its correction in double (t is clamped to the first level of */
+/* the double block).  Only the coloured orders are modelled.               */
 /* ------------------------------------------------------------------------ */
 
 static double rnd32(double x) { return (double)(float)x; }
@@ -584,14 +588,15 @@ static void relax_mixed(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u, int 
     int onepass = g->mix_mode == ORC_MIX_ONEPASS;
     int kacz = pl->smoother[l] == ORC_SM_KACZ;
     int every = g->mix_kacz_every > 0 ? g->mix_kacz_every : sweeps;
+    int stores = l >= g->mix_t;          /* the level's fields are float */
     for (int it = 0; it < sweeps; ++it) {
         int ncol = kacz ? 5 : 2;
         for (int c = 0; c < ncol; ++c) {
             if (kacz) kacz_colour_pass(n, H, k, s, f, u, c);
             else      gs_colour_pass(n, H, k, s, f, u, c);
-            if (onepass) round_field(m, u);
+            if (onepass && stores) round_field(m, u);
         }
-        if (!onepass && kacz && ((it + 1) % every == 0) && (it + 1 < sweeps || last_store))
+        if (!onepass && stores && kacz && ((it + 1) % every == 0) && (it + 1 < sweeps || last_store))
             round_field(m, u);
     }
 }
@@ -614,32 +619,43 @@ static void vcycle_mixed(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u)
         return;
     }
     int kacz = pl->smoother[l] == ORC_SM_KACZ;
+    int stores = l >= g->mix_t;                 /* this level's fields are float    */
+    int cstores = l + 1 > g->mix_t;             /* the coarse fields handed over are */
     nc = pl->n[l + 1];
     mc = (size_t)(nc + 2) * (nc + 2);
     memset(u, 0, m * sizeof(orc_cplx));
     relax_mixed(g, l, f, u, pl->pre[l], 0);
     orc_residual(n, pl->H[l], g->kv[l], pl->sigma_resid[l], f, u, g->r[l]);
-    if (kacz && !onepass && pl->pre[l] > 0) round_field(m, u);
+    if (stores && kacz && !onepass && pl->pre[l] > 0) round_field(m, u);
     orc_restrict_fw(n, g->r[l], g->f[l + 1]);
-    round_field(mc, g->f[l + 1]);
+    if (cstores) round_field(mc, g->f[l + 1]);
     vcycle_mixed(g, l + 1, g->f[l + 1], g->u[l + 1]);
-    round_field(mc, g->u[l + 1]);
+    if (cstores) round_field(mc, g->u[l + 1]);
     orc_prolong_add(nc, g->u[l + 1], u);
-    if (onepass) round_field(m, u);
+    if (onepass && stores) round_field(m, u);
     relax_mixed(g, l, f, u, pl->post[l], 1);
 }
 
 void orc_grid_set_mixed(orc_grid *g, int mode, int kacz_every, int block_n, int round_io)
 {
+    orc_grid_set_mixed_ex(g, mode, kacz_every, block_n, round_io, 0);
+}
+
+void orc_grid_set_mixed_ex(orc_grid *g, int mode, int kacz_every, int block_n, int round_io,
+                           int fp64_levels)
+{
     g->mix_mode = mode;
     g->mix_kacz_every = kacz_every;
     g->mix_block_n = block_n;
     g->mix_round_io = round_io;
+    g->mix_t = (mode == ORC_MIX_FUSED) ? fp64_levels : 0;
+    for (int l = 0; l < g->plan.nlev && l < g->mix_t; ++l)
+        if (g->plan.n[l] <= block_n || g->plan.smoother[l] == ORC_SM_LU) { g->mix_t = l; break; }
     for (int l = 0; l < g->plan.nlev; ++l) {
         size_t m = (size_t)(g->plan.n[l] + 2) * (g->plan.n[l] + 2);
         if (g->kv[l] != g->k[l]) free(g->kv[l]);
         g->kv[l] = g->k[l];
-        if (mode == ORC_MIX_OFF) continue;
+        if (mode == ORC_MIX_OFF || l < g->mix_t) continue;
         g->kv[l] = malloc(m * sizeof(double));
         for (size_t q = 0; q < m; ++q) g->kv[l][q] = rnd32(g->k[l][q]);
     }
@@ -654,9 +670,10 @@ void orc_vcycle(orc_grid *g, const orc_cplx *f, orc_cplx *u)
     size_t m = (size_t)(g->n + 2) * (g->n + 2);
     orc_cplx *fin = malloc(m * sizeof(orc_cplx));
     memcpy(fin, f, m * sizeof(orc_cplx));
-    if (g->mix_round_io) round_field(m, fin);
+    int rio = g->mix_round_io && g->mix_t == 0;
+    if (rio) round_field(m, fin);
     vcycle_mixed(g, 0, fin, u);
-    if (g->mix_round_io) round_field(m, u);
+    if (rio) round_field(m, u);
     free(fin);
 }
 

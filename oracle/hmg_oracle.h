@@ -101,6 +101,11 @@ int       orc_grid_override_level(orc_grid *g, int l, int smoother, double sigma
  * grid in this mode keeps its own arithmetic and L in double. ---- */
 enum { ORC_MIX_OFF = 0, ORC_MIX_FUSED = 1, ORC_MIX_ONEPASS = 2 };
 void      orc_grid_set_mixed(orc_grid *g, int mode, int kacz_every, int block_n, int round_io);
+/* The same with the finest fp64_levels levels kept in double (fused mode;
+ * clamped to the first level of the double block); the first float level
+ * then takes and returns double fields. */
+void      orc_grid_set_mixed_ex(orc_grid *g, int mode, int kacz_every, int block_n, int round_io,
+                                int fp64_levels);
 
 /* ---- Bi-CGSTAB (Section 6) ---- */
 enum { ORC_PREC_NONE = 0, ORC_PREC_VCYCLE = 1, ORC_PREC_EXACT = 2 };

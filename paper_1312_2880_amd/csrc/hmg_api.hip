@@ -208,11 +208,10 @@ struct Carver {
 
 // Lay out (or size, when c.base is null) every device buffer of the grid.
 static void layout(hmg_grid *g, Carver &c) {
-    size_t csz = (g->prec == P64) ? 16 : 8, rsz = (g->prec == P64) ? 8 : 4;
     for (int l = 0; l < g->nlev; ++l) {
         Level &L = g->lev[l];
         size_t m = (size_t)L.geo.M * L.geo.M;
-        L.k = c.take(m * rsz);
+        L.k = c.take(m * (L.prec == P64 ? 8 : 4));
         L.ktab = (L.mode == LM_KACZ_TILED || L.mode == LM_KACZ_LEVEL) ? (double *)c.take(m * 16) : nullptr;
     }
     g->k0 = (double *)c.take((size_t)g->lev[0].geo.M * g->lev[0].geo.M * 8);
@@ -229,7 +228,11 @@ static void layout(hmg_grid *g, Carver &c) {
     for (int s = 0; s < g->nrhs; ++s) {
         Slot &S = g->slot[s];
         for (int l = 0; l < g->nlev; ++l) {
-            size_t m = (size_t)g->lev[l].geo.M * g->lev[l].geo.M;
+            const Level &L = g->lev[l];
+            size_t m = (size_t)L.geo.M * L.geo.M;
+            // the first complex-float level below double levels takes its
+            // right-hand side and returns its result in double
+            size_t csz = (L.prec == P64 || L.io64) ? 16 : 8;
             S.f[l] = c.take(m * csz);
             S.u[l] = c.take(m * csz);
             S.u2[l] = c.take(m * csz);
@@ -298,6 +301,26 @@ static void plan_paths(hmg_grid *g) {
     }
 }
 
+// Storage precision per level.  FP64 grids keep every level in double.
+// MIXED grids keep the finest t = min(fp64_levels, levels above the bottom
+// solver) levels in double and the rest in complex float; level t then
+// takes its right-hand side and returns its correction in double, which the
+// fused Gauss-Seidel kernels and the bottom solver do (the other schedules
+// are rejected).
+static hmg_status assign_precision(hmg_grid *g) {
+    const int top = (g->lb < 0) ? g->nlev : g->lb;
+    const int t = (g->prec == P64) ? g->nlev : std::min(g->opts.fp64_levels, top);
+    for (int l = 0; l < g->nlev; ++l) {
+        g->lev[l].prec = (l < t) ? P64 : g->prec;
+        g->lev[l].io64 = (g->prec == P32 && t > 0 && l == t);
+    }
+    if (g->prec == P32 && t > 0 && t < g->nlev && t != g->lb && g->lev[t].mode != LM_GS_FUSED)
+        return hmg_fail(HMG_ERR_INVALID,
+                        "fp64_levels = %d: the first complex-float level (n = %d) must be a Gauss-Seidel level "
+                        "of the fused schedule or the first bottom level", g->opts.fp64_levels, g->lev[t].geo.n);
+    return HMG_OK;
+}
+
 static void bottom_desc(hmg_grid *g) {
     if (g->lb < 0) return;
     BottomDesc &d = g->bottom;
@@ -347,7 +370,7 @@ static std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune
 
 static hmg_status tune_kacz_level(hmg_grid *g, int l) {
     const hmg_plan &pl = g->plan;
-    auto key = std::make_tuple(g->ctx->device, g->lev[l].geo.n, (int)g->prec, pl.pre[l], pl.post[l]);
+    auto key = std::make_tuple(g->ctx->device, g->lev[l].geo.n, (int)g->lev[l].prec, pl.pre[l], pl.post[l]);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -357,16 +380,24 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
             return HMG_OK;
         }
     }
+    // On complex-float levels the sweeps per launch decide where the iterate
+    // is rounded to float, so the candidates keep the default's count (tile
+    // shape and size do not change any value: each node sees the same row
+    // updates in the same order); the results then do not depend on timing.
+    const bool float_level = g->lev[l].prec == P32;
+    const int sw_default = kKaczCfgs[g->lev[l].kacz_cfg].sweeps;
     std::vector<int> cand;
     for (int cfg = 0; cfg < KACZ_NCFG; ++cfg) {
         int sw = kKaczCfgs[cfg].sweeps;
-        if (kacz_cfg_fits(g->prec, cfg) && pl.pre[l] % sw == 0 && pl.post[l] % sw == 0) cand.push_back(cfg);
+        if (float_level && sw != sw_default) continue;
+        if (kacz_cfg_fits(g->lev[l].prec, cfg) && pl.pre[l] % sw == 0 && pl.post[l] % sw == 0) cand.push_back(cfg);
     }
     if (cand.size() > 1 && pl.pre[l] > 0) {
         const Level &L = g->lev[l];
         Slot &S = g->slot[0];
-        size_t bytes = (size_t)L.geo.M * L.geo.M * (g->prec == P64 ? 16 : 8);
-        size_t cbytes = (size_t)g->lev[l + 1].geo.M * g->lev[l + 1].geo.M * (g->prec == P64 ? 16 : 8);
+        const Level &Lc = g->lev[l + 1];
+        size_t bytes = (size_t)L.geo.M * L.geo.M * (L.prec == P64 ? 16 : 8);
+        size_t cbytes = (size_t)Lc.geo.M * Lc.geo.M * ((Lc.prec == P64 || Lc.io64) ? 16 : 8);
         HIPCHK(hipMemsetAsync(S.f[l], 0, bytes, g->stream));
         HIPCHK(hipMemsetAsync(S.u[l], 0, bytes, g->stream));
         HIPCHK(hipMemsetAsync(S.u2[l], 0, bytes, g->stream));
@@ -386,16 +417,16 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                 int w = 0;
                 for (int q = 0; q < pl.pre[l]; q += sw) {
                     if (kacz_cfg_resid(cfg) && q + sw >= pl.pre[l])
-                        launch_kacz_tb_resid(g->prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l],
+                        launch_kacz_tb_resid(L.prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l],
                                              pl.sigma_resid[l], S.f[l], cur, bufs[w], S.f[l + 1], nullptr);
                     else
-                        launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l],
+                        launch_kacz_tb(L.prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l],
                                        cur, nullptr, bufs[w], nullptr);
                     cur = bufs[w];
                     w ^= 1;
                 }
                 for (int q = 0; q < pl.post[l] && cur; q += sw) {
-                    launch_kacz_tb(g->prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l], cur,
+                    launch_kacz_tb(L.prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l], cur,
                                    q == 0 ? S.u[l + 1] : nullptr, bufs[w], nullptr);
                     cur = bufs[w];
                     w ^= 1;
@@ -440,11 +471,11 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         // a level small enough for one workgroup may run whole (no halo
         // work, but one CU): same two legs, kept only if faster
         bool whole = false;
-        if (kacz_level_fits(L.geo)) {
+        if (kacz_level_fits(L.geo) && !float_level) {
             auto legs = [&]() {
-                launch_kacz_level(g->prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], pl.sigma_resid[l],
+                launch_kacz_level(L.prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], pl.sigma_resid[l],
                                   pl.pre[l], S.f[l], nullptr, nullptr, S.u[l], S.f[l + 1], nullptr);
-                launch_kacz_level(g->prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], 0.0, pl.post[l],
+                launch_kacz_level(L.prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], 0.0, pl.post[l],
                                   S.f[l], S.u[l], S.u[l + 1], S.u2[l], nullptr, nullptr);
             };
             hipGraph_t gr = nullptr;
@@ -516,6 +547,14 @@ size_t estimate_footprint(int n, const hmg_opts &o) {
     g.nlev = l + 1;
     g.opts = o;
     g.lb = find_bottom(&g);
+    {
+        const int top = (g.lb < 0) ? g.nlev : g.lb;
+        const int t = (g.prec == P64) ? g.nlev : std::min(o.fp64_levels, top);
+        for (int q = 0; q < g.nlev; ++q) {
+            g.lev[q].prec = (q < t) ? P64 : g.prec;
+            g.lev[q].io64 = (g.prec == P32 && t > 0 && q == t);
+        }
+    }
     // the Kaczmarz levels depend on k: count a row table on every level
     // below the finest
     for (int q = 1; q < g.nlev; ++q) g.lev[q].mode = LM_KACZ_TILED;
@@ -548,6 +587,9 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     if (o.breakdown_at < 0) return hmg_fail(HMG_ERR_INVALID, "breakdown_at must be >= 0");
     if (o.true_res_every < 0) return hmg_fail(HMG_ERR_INVALID, "true_res_every must be >= 0");
     if (o.nan_at < 0) return hmg_fail(HMG_ERR_INVALID, "nan_at must be >= 0");
+    if (o.fp64_levels < 0) return hmg_fail(HMG_ERR_INVALID, "fp64_levels must be >= 0");
+    if (o.fp64_levels > 0 && o.precision == HMG_MIXED && (o.one_pass_kernels || o.relax_order == HMG_ORDER_LEX))
+        return hmg_fail(HMG_ERR_INVALID, "fp64_levels needs the fused schedule with coloured sweeps");
     if (!std::isfinite(o.beta) || o.nu_pre < 0 || o.nu_post < 0 || o.kacz_pre < 0 || o.kacz_post < 0 ||
         o.nu_pre > 64 || o.nu_post > 64 || o.kacz_pre > 64 || o.kacz_post > 64)
         return hmg_fail(HMG_ERR_INVALID, "bad sweep counts or beta");
@@ -602,6 +644,13 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     }
 
     plan_paths(g);
+    {
+        hmg_status pst = assign_precision(g);
+        if (pst != HMG_OK) {
+            delete g;
+            return pst;
+        }
+    }
     g->slot.resize(nrhs);
     Carver sizer;
     layout(g, sizer);
@@ -620,14 +669,14 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     if (st == HMG_OK) {
         for (int l = 0; l < g->nlev; ++l)
             if (g->lev[l].ktab)
-                launch_kacz_table(g->prec, g->stream, g->lev[l].geo, g->lev[l].k, g->plan.sigma_relax[l],
+                launch_kacz_table(g->lev[l].prec, g->stream, g->lev[l].geo, g->lev[l].k, g->plan.sigma_relax[l],
                                   g->lev[l].ktab);
         hipError_t le = hipGetLastError();
         if (le != hipSuccess) st = hmg_fail(HMG_ERR_DEVICE, "Kaczmarz tables: %s", hipGetErrorString(le));
     }
     if (st == HMG_OK && g->bop) {
         // the bottom cycle on every unit vector: its matrix, column by column
-        launch_bottom_basis(g->prec, g->stream, g->bottom, g->bop);
+        launch_bottom_basis(g->lev[g->lb].prec, g->stream, g->bottom, g->bop);
         hipError_t le = hipGetLastError();
         if (le == hipSuccess) le = hipStreamSynchronize(g->stream);
         if (le != hipSuccess) st = hmg_fail(HMG_ERR_DEVICE, "bottom matrix: %s", hipGetErrorString(le));
@@ -653,7 +702,7 @@ hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> 
     for (int q = 0; q < 4; ++q) HIPCHK(hipEventCreateWithFlags(&g->ev[q], hipEventDisableTiming));
     for (int l = 0; l < g->nlev; ++l) {
         size_t m = kl[l].size();
-        if (g->prec == P64) {
+        if (g->lev[l].prec == P64) {
             HIPCHK(hipMemcpy(g->lev[l].k, kl[l].data(), m * 8, hipMemcpyHostToDevice));
         } else {
             std::vector<float> kf(m);
@@ -736,20 +785,20 @@ static void sweep(Prec p, int sm, int order, hipStream_t s, const Geo &geo, cons
 static void relax(hmg_grid *g, int l, const void *f, void *u, int sweeps, bool zero_guess, hipStream_t s,
                   const int *skip) {
     const Level &L = g->lev[l];
-    sweep(g->prec, g->plan.smoother[l], g->opts.relax_order, s, L.geo, L.k, g->plan.sigma_relax[l], f, u, sweeps,
+    sweep(L.prec, g->plan.smoother[l], g->opts.relax_order, s, L.geo, L.k, g->plan.sigma_relax[l], f, u, sweeps,
           zero_guess, skip);
 }
 
 static void vcycle_level(hmg_grid *g, Slot &S, int l, const void *f, void *u, hipStream_t s, const int *skip) {
     const Level &L = g->lev[l];
     if (g->plan.smoother[l] == HMG_SM_LU) {
-        launch_coarsest(g->prec, s, L.geo.M * L.geo.M, g->ainv_t, f, u, skip);
+        launch_coarsest(L.prec, s, L.geo.M * L.geo.M, g->ainv_t, f, u, skip);
         return;
     }
     relax(g, l, f, u, g->plan.pre[l], true, s, skip);
-    launch_residual_fw(g->prec, s, L.geo, L.k, g->plan.sigma_resid[l], f, u, S.f[l + 1], skip);
+    launch_residual_fw(L.prec, s, L.geo, L.k, g->plan.sigma_resid[l], f, u, S.f[l + 1], skip);
     vcycle_level(g, S, l + 1, S.f[l + 1], S.u[l + 1], s, skip);
-    launch_prolong_add(g->prec, s, L.geo, S.u[l + 1], u, skip);
+    launch_prolong_add(L.prec, s, L.geo, S.u[l + 1], u, skip);
     relax(g, l, f, u, g->plan.post[l], false, s, skip);
 }
 
@@ -762,8 +811,8 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
     const hmg_plan &pl = g->plan;
     if (l == g->lb) {
         void *dst = out ? out : S.u[l];
-        if (g->bop) launch_dense_apply(g->prec, f64, s, g->bop, g->bop_m, f, dst, skip);
-        else launch_bottom(g->prec, f64, s, g->bottom, f, dst, skip);
+        if (g->bop) launch_dense_apply(L.prec, f64, s, g->bop, g->bop_m, f, dst, skip);
+        else launch_bottom(L.prec, f64, s, g->bottom, f, dst, skip);
         return dst;
     }
     if (L.mode == LM_GS_FUSED) {
@@ -774,14 +823,14 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         // fewer); on larger levels the extra HBM traffic costs as much as the
         // phase saves, and complex-float levels must not round it: both
         // recompute it from f.
-        void *u0 = (g->prec == P64 && L.geo.n <= 511) ? S.u[l] : nullptr;
-        launch_gs_down(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, u0, S.f[l + 1],
+        void *u0 = (L.prec == P64 && L.geo.n <= 511) ? S.u[l] : nullptr;
+        launch_gs_down(L.prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, u0, S.f[l + 1],
                        skip, true);
-        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
         void *dst = out ? out : S.u2[l];
         // the finest up kernel of an FP64 solve also forms the Krylov product
         // of its result when the caller asks for it
-        if (mv && l == 0 && !u0 && !f64 && gs_up_mv_ok(g->prec, L.geo) &&
+        if (mv && l == 0 && !u0 && !f64 && gs_up_mv_ok(L.prec, L.geo) &&
             gs_up_mv_blocks(L.geo) <= S.K.pcap) {
             launch_gs_up_mv(s, mv->kind, L.geo, L.k, pl.sigma_relax[l], f, e, mv->no_z ? nullptr : dst, mv->out,
                             mv->dot, mv->partials, skip);
@@ -789,18 +838,18 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
             mv->fused = true;
             return dst;
         }
-        launch_gs_up(g->prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip);
+        launch_gs_up(L.prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip);
         return dst;
     }
     size_t m = (size_t)L.geo.M * L.geo.M;
     if (L.mode == LM_KACZ_LEVEL) {
         // pre-smoothing + restriction, coarser levels, correction + post-smoothing
         double sig = pl.sigma_relax[l];
-        launch_kacz_level(g->prec, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], pl.pre[l], f, nullptr, nullptr,
+        launch_kacz_level(L.prec, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], pl.pre[l], f, nullptr, nullptr,
                           S.u[l], S.f[l + 1], skip);
-        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
         void *dst = out ? out : S.u2[l];
-        launch_kacz_level(g->prec, s, L.geo, L.k, L.ktab, sig, 0.0, pl.post[l], f, S.u[l], e, dst, nullptr, skip);
+        launch_kacz_level(L.prec, s, L.geo, L.k, L.ktab, sig, 0.0, pl.post[l], f, S.u[l], e, dst, nullptr, skip);
         return dst;
     }
     if (L.mode == LM_KACZ_TILED) {
@@ -813,30 +862,30 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         const bool fuse = pl.pre[l] > 0 && kacz_cfg_resid(cfg);
         for (int q = 0; q < pl.pre[l]; q += sw) {
             if (fuse && q + sw >= pl.pre[l])
-                launch_kacz_tb_resid(g->prec, cfg, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], f, cur, bufs[w],
+                launch_kacz_tb_resid(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], f, cur, bufs[w],
                                      S.f[l + 1], skip);
             else
-                launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, nullptr, bufs[w], skip);
+                launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, nullptr, bufs[w], skip);
             cur = bufs[w];
             w ^= 1;
         }
         if (!cur) {
-            launch_fill_zero(g->prec, s, bufs[w], m, skip);
+            launch_fill_zero(L.prec, s, bufs[w], m, skip);
             cur = bufs[w];
             w ^= 1;
         }
-        if (!fuse) launch_residual_fw(g->prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip);
-        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
+        if (!fuse) launch_residual_fw(L.prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
         if (pl.post[l] == 0) {
-            launch_prolong_add(g->prec, s, L.geo, e, (void *)cur, skip);
+            launch_prolong_add(L.prec, s, L.geo, e, (void *)cur, skip);
         }
         for (int q = 0; q < pl.post[l]; q += sw) {
-            launch_kacz_tb(g->prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip);
+            launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip);
             cur = bufs[w];
             w ^= 1;
         }
         if (out) {
-            (void)hipMemcpyAsync(out, cur, m * (g->prec == P64 ? 16 : 8), hipMemcpyDeviceToDevice, s);
+            (void)hipMemcpyAsync(out, cur, m * (L.prec == P64 ? 16 : 8), hipMemcpyDeviceToDevice, s);
             return out;
         }
         return cur;
@@ -844,9 +893,9 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
     // one-pass kernels, in place
     void *u = out ? out : S.u[l];
     relax(g, l, f, u, pl.pre[l], true, s, skip);
-    launch_residual_fw(g->prec, s, L.geo, L.k, pl.sigma_resid[l], f, u, S.f[l + 1], skip);
-    const void *e = vc_fast(g, S, l + 1, S.f[l + 1], false, nullptr, s, skip);
-    launch_prolong_add(g->prec, s, L.geo, e, u, skip);
+    launch_residual_fw(L.prec, s, L.geo, L.k, pl.sigma_resid[l], f, u, S.f[l + 1], skip);
+    const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
+    launch_prolong_add(L.prec, s, L.geo, e, u, skip);
     relax(g, l, f, u, pl.post[l], false, s, skip);
     return u;
 }
@@ -855,15 +904,15 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
 // launch_gs_up_mv for an FP64 solve.
 bool vcycle_forms_products(const hmg_grid *g, const Slot &S) {
     const Geo &g0 = g->lev[0].geo;
-    return !one_pass(g) && g->prec == P64 && g->lb != 0 && g->lev[0].mode == LM_GS_FUSED && g0.n > 511 &&
-           gs_up_mv_ok(g->prec, g0) && gs_up_mv_blocks(g0) <= S.K.pcap;
+    return !one_pass(g) && g->lev[0].prec == P64 && g->lb != 0 && g->lev[0].mode == LM_GS_FUSED && g0.n > 511 &&
+           gs_up_mv_ok(P64, g0) && gs_up_mv_blocks(g0) <= S.K.pcap;
 }
 
 // z = B_V r on FP64 device fields r, z (finest level).
 void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip,
                     MvFuse *mv) {
     if (!one_pass(g)) {
-        bool mixed = g->prec == P32;
+        bool mixed = g->lev[0].prec == P32;
         if (!mixed || g->lb == 0 || g->lev[0].mode == LM_GS_FUSED) {
             vc_fast(g, S, 0, r, mixed, z, s, skip, mv);
         } else {
@@ -874,7 +923,7 @@ void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_
         }
         return;
     }
-    if (g->prec == P64) {
+    if (g->lev[0].prec == P64) {
         vcycle_level(g, S, 0, r, z, s, skip);
     } else {
         size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
@@ -926,7 +975,7 @@ extern "C" hmg_status hmg_op_apply_dev(hmg_grid *g, int level, double sigma, con
     if (st) return st;
     if (!d_u || !d_out) return hmg_fail(HMG_ERR_INVALID, "null field");
     const Level &L = g->lev[level];
-    launch_apply(g->prec, pick_stream(g, stream), L.geo, L.k, sigma, d_u, d_out);
+    launch_apply(L.prec, pick_stream(g, stream), L.geo, L.k, sigma, d_u, d_out);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }
@@ -938,7 +987,7 @@ extern "C" hmg_status hmg_op_smooth_dev(hmg_grid *g, int level, int smoother, do
     if (!d_f || !d_u || sweeps < 0) return hmg_fail(HMG_ERR_INVALID, "bad argument");
     if (smoother != HMG_SM_GS && smoother != HMG_SM_KACZ) return hmg_fail(HMG_ERR_INVALID, "bad smoother");
     const Level &L = g->lev[level];
-    sweep(g->prec, smoother, HMG_ORDER_COLOUR, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, sweeps,
+    sweep(L.prec, smoother, HMG_ORDER_COLOUR, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, sweeps,
           zero_guess != 0, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
@@ -951,7 +1000,7 @@ extern "C" hmg_status hmg_op_smooth_lex_dev(hmg_grid *g, int level, int smoother
     if (!d_f || !d_u || sweeps < 0) return hmg_fail(HMG_ERR_INVALID, "bad argument");
     if (smoother != HMG_SM_GS && smoother != HMG_SM_KACZ) return hmg_fail(HMG_ERR_INVALID, "bad smoother");
     const Level &L = g->lev[level];
-    sweep(g->prec, smoother, HMG_ORDER_LEX, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, sweeps,
+    sweep(L.prec, smoother, HMG_ORDER_LEX, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, sweeps,
           zero_guess != 0, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
@@ -963,7 +1012,7 @@ extern "C" hmg_status hmg_op_restrict_dev(hmg_grid *g, int level, double sigma, 
     if (st) return st;
     if (!d_f || !d_u || !d_fc) return hmg_fail(HMG_ERR_INVALID, "null field");
     const Level &L = g->lev[level];
-    launch_residual_fw(g->prec, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, d_fc, nullptr);
+    launch_residual_fw(L.prec, pick_stream(g, stream), L.geo, L.k, sigma, d_f, d_u, d_fc, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }
@@ -972,7 +1021,7 @@ extern "C" hmg_status hmg_op_prolong_dev(hmg_grid *g, int level, const void *d_e
     hmg_status st = check_level(g, level, true);
     if (st) return st;
     if (!d_ec || !d_u) return hmg_fail(HMG_ERR_INVALID, "null field");
-    launch_prolong_add(g->prec, pick_stream(g, stream), g->lev[level].geo, d_ec, d_u, nullptr);
+    launch_prolong_add(g->lev[level].prec, pick_stream(g, stream), g->lev[level].geo, d_ec, d_u, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }
@@ -981,7 +1030,7 @@ extern "C" hmg_status hmg_op_coarsest_dev(hmg_grid *g, const void *d_f, void *d_
     if (!g || !d_f || !d_u) return hmg_fail(HMG_ERR_INVALID, "null argument");
     HIPCHK(hipSetDevice(g->ctx->device));
     const Level &L = g->lev[g->nlev - 1];
-    launch_coarsest(g->prec, pick_stream(g, stream), L.geo.M * L.geo.M, g->ainv_t, d_f, d_u, nullptr);
+    launch_coarsest(L.prec, pick_stream(g, stream), L.geo.M * L.geo.M, g->ainv_t, d_f, d_u, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }
@@ -992,7 +1041,7 @@ extern "C" hmg_status hmg_op_gs_down_dev(hmg_grid *g, int level, double sigma_re
     if (st) return st;
     if (!d_f || !d_fc || d_u == d_f || d_fc == d_f) return hmg_fail(HMG_ERR_INVALID, "bad fields");
     const Level &L = g->lev[level];
-    launch_gs_down(g->prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, sigma_resid, d_f, d_u, d_fc,
+    launch_gs_down(L.prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, sigma_resid, d_f, d_u, d_fc,
                    nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
@@ -1005,7 +1054,7 @@ extern "C" hmg_status hmg_op_gs_up_dev(hmg_grid *g, int level, double sigma_rela
     if (!d_f || !d_ec || !d_uo || d_uo == d_f || d_uo == d_ec || d_uo == d_u0)
         return hmg_fail(HMG_ERR_INVALID, "bad fields (the output must not alias an input)");
     const Level &L = g->lev[level];
-    launch_gs_up(g->prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, d_f, d_u0, d_ec, d_uo, nullptr);
+    launch_gs_up(L.prec, false, pick_stream(g, stream), L.geo, L.k, sigma_relax, d_f, d_u0, d_ec, d_uo, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
 }
@@ -1015,7 +1064,7 @@ extern "C" hmg_status hmg_op_gs_up_product_dev(hmg_grid *g, int level, double si
                                                const void *d_dot, void *d_sums, void *stream) {
     hmg_status st = check_level(g, level, true);
     if (st) return st;
-    if (g->prec != P64) return hmg_fail(HMG_ERR_INVALID, "the fused product runs on FP64 grids only");
+    if (g->lev[level].prec != P64) return hmg_fail(HMG_ERR_INVALID, "the fused product runs on FP64 levels only");
     if (kind != 1 && kind != 2) return hmg_fail(HMG_ERR_INVALID, "kind must be 1 or 2");
     if (!d_f || !d_ec || !d_mv || !d_dot) return hmg_fail(HMG_ERR_INVALID, "null field");
     const void *ins[] = {d_f, d_ec, d_dot};
@@ -1039,13 +1088,13 @@ extern "C" hmg_status hmg_op_kacz_tiled_dev(hmg_grid *g, int level, double sigma
                                             const void *d_ui, const void *d_ec, void *d_uo, void *stream) {
     hmg_status st = check_level(g, level, false);
     if (st) return st;
-    if (config < 0 || config >= KACZ_NCFG || !kacz_cfg_fits(g->prec, config))
+    if (config < 0 || config >= KACZ_NCFG || !kacz_cfg_fits(g->lev[level].prec, config))
         return hmg_fail(HMG_ERR_INVALID, "tile configuration %d not available", config);
     if (!d_f || !d_uo || d_uo == d_ui || d_uo == d_f || d_uo == d_ec)
         return hmg_fail(HMG_ERR_INVALID, "bad fields (the output must not alias an input)");
     if (d_ec && level >= g->nlev - 1) return hmg_fail(HMG_ERR_INVALID, "no coarser level");
     const Level &L = g->lev[level];
-    launch_kacz_tb(g->prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma, d_f, d_ui, d_ec, d_uo,
+    launch_kacz_tb(L.prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma, d_f, d_ui, d_ec, d_uo,
                    nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
@@ -1062,7 +1111,7 @@ extern "C" hmg_status hmg_op_kacz_down_dev(hmg_grid *g, int level, double sigma_
     if (!d_f || !d_uo || !d_fc || d_uo == d_ui || d_uo == d_f || d_fc == d_f || d_fc == d_ui || d_fc == d_uo)
         return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs or each other)");
     const Level &L = g->lev[level];
-    launch_kacz_tb_resid(g->prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid,
+    launch_kacz_tb_resid(L.prec, config, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid,
                          d_f, d_ui, d_uo, d_fc, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;
@@ -1080,7 +1129,7 @@ extern "C" hmg_status hmg_op_kacz_level_dev(hmg_grid *g, int level, double sigma
     if (!d_f || !d_uo || d_uo == d_f || d_uo == d_ui || d_uo == d_ec || (d_fc && (d_fc == d_f || d_fc == d_uo)))
         return hmg_fail(HMG_ERR_INVALID, "bad fields (outputs must not alias inputs or each other)");
     const Level &L = g->lev[level];
-    launch_kacz_level(g->prec, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid, sweeps, d_f,
+    launch_kacz_level(L.prec, pick_stream(g, stream), L.geo, L.k, nullptr, sigma_relax, sigma_resid, sweeps, d_f,
                       d_ui, d_ec, d_uo, d_fc, nullptr);
     HIPCHK(hipGetLastError());
     return HMG_OK;

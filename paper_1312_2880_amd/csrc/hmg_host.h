@@ -43,7 +43,10 @@ enum LevelMode { LM_SIMPLE = 0, LM_GS_FUSED = 1, LM_KACZ_TILED = 2, LM_BOTTOM = 
 
 struct Level {
     hmgk::Geo geo;
-    void     *k = nullptr;  // wavenumber in the V-cycle precision
+    hmgk::Prec prec = hmgk::P64;  // storage precision of the level's fields and k
+    bool      io64 = false;  // first complex-float level below double levels: its right-hand
+                             // side and result are double
+    void     *k = nullptr;  // wavenumber in the level's precision
     int       mode = LM_SIMPLE;
     int       kacz_cfg = 1; // index into hmgk::kKaczCfgs
     double   *ktab = nullptr;  // Kaczmarz levels: (k_p, 1 / ||a_p||^2), complex-interleaved FP64

@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
                 ("one_pass_kernels", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("bottom_dense", ctypes.c_int), ("relax_order", ctypes.c_int),
                 ("breakdown_at", ctypes.c_int), ("true_res_every", ctypes.c_int),
-                ("nan_at", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("nan_at", ctypes.c_int), ("fp64_levels", ctypes.c_int),
+                ("reserved", ctypes.c_int * 1)]
 
 
 class Plan(ctypes.Structure):

@@ -210,12 +210,24 @@ class DenseMixedVCycle(DenseVCycle):
     mode "onepass": every colour pass, restriction, prolongation-and-add and
                    coarsest result is rounded.
     round_io rounds the input and the output of the whole cycle.  The
-    coarsest operator keeps the unrounded k."""
+    coarsest operator keeps the unrounded k.  fp64_levels = t ("fused"):
+    levels finer than t (clamped to the first double-block or coarsest level)
+    keep double fields and k, and level t takes its right-hand side and
+    returns its correction unrounded."""
 
-    def __init__(self, h, k, plan, mode, every=2, block_n=31, round_io=False):
+    def __init__(self, h, k, plan, mode, every=2, block_n=31, round_io=False, fp64_levels=0):
         super().__init__(h, k, plan)
         self.mode, self.every, self.block_n, self.round_io = mode, every, block_n, round_io
-        for lev in self.levels:
+        t = fp64_levels if mode == "fused" else 0
+        for l, p in enumerate(plan[:t]):
+            if p["n"] <= block_n or p["smoother"] == "LU":
+                t = l
+                break
+        self.t = t
+        for l, lev in enumerate(self.levels):
+            lev["level"] = l
+            if l < t:
+                continue
             k32 = lev["k"].astype(np.float32).astype(np.float64)
             if lev["smoother"] != "LU":
                 lev["A_relax"] = assemble_ghost(lev["n"], lev["H"], k32, lev["sigma_relax"])
@@ -236,6 +248,8 @@ class DenseMixedVCycle(DenseVCycle):
     def _leg(self, lev, f, u, sweeps, last_store):
         A, n = lev["A_relax"], lev["n"]
         kacz = lev["smoother"] == "KACZ"
+        if lev["level"] < self.t:
+            return self._relax(lev, f, u, sweeps)
         colours, ncol = (colour_5(n), 5) if kacz else (colour_rb(n), 2)
         for it in range(sweeps):
             for c in range(ncol):
@@ -262,19 +276,23 @@ class DenseMixedVCycle(DenseVCycle):
         if self.mode == "fused" and lev["n"] <= self.block_n:
             return self._double_block(f, l)
         kacz = lev["smoother"] == "KACZ"
+        stores, cstores = l >= self.t, l + 1 > self.t
+        keep = lambda a: a
+        rc = round32 if cstores else keep
         u = self._leg(lev, f, np.zeros_like(f), lev["pre"], False)
         r = f - lev["A_resid"] @ u
-        if kacz and self.mode == "fused" and lev["pre"] > 0:
+        if stores and kacz and self.mode == "fused" and lev["pre"] > 0:
             u = round32(u)
-        fc = round32(lev["R"] @ r)
-        e = round32(self._level(fc, l + 1))
+        fc = rc(lev["R"] @ r)
+        e = rc(self._level(fc, l + 1))
         u = u + lev["P"] @ e
         if self.mode == "onepass":
             u = round32(u)
         return self._leg(lev, f, u, lev["post"], True)
 
     def apply(self, f, l=0):
-        if self.round_io:
+        rio = self.round_io and self.t == 0
+        if rio:
             f = round32(f)
         u = self._level(np.asarray(f, np.complex128), 0)
-        return round32(u) if self.round_io else u
+        return round32(u) if rio else u

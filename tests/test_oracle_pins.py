@@ -531,6 +531,36 @@ def test_mixed_vcycle_equals_dense_mixed_composition(n, ci, mode):
     assert 1e-9 < effect < 1e-5, effect
 
 
+@pytest.mark.parametrize("t", [1, 2])
+@pytest.mark.parametrize("ci", [1, 3, 5])
+def test_mixed_vcycle_with_double_fine_levels(ci, t):
+    """Precision form with the finest t levels kept in double (their fields
+    and k unrounded; level t takes and returns double fields): equals the
+    dense construction with the same stores and differs from both the
+    all-float and the all-double cycles."""
+    n, h = 31, 1 / 32
+    case = dict(CASES_P4[ci])
+    lo, hi = case.pop("k")
+    k = rng_k(n, 21, lo, hi) * 4
+    g = oracle.Grid(h, k, **case)
+    plan = g.plan()
+    ref = D.DenseMixedVCycle(h, k, plan, "fused", 2, 3, False, fp64_levels=t)
+    ref32 = D.DenseMixedVCycle(h, k, plan, "fused", 2, 3, False)
+    ref64 = D.DenseVCycle(h, k, plan)
+    g.set_mixed(oracle.MIX_FUSED, 2, 3, False, fp64_levels=t)
+    m = (n + 2) ** 2
+    for col in range(0, m, 97):
+        f = np.zeros(m, complex)
+        f[col] = 1.0
+        f[(col * 5 + 3) % m] = 0.5j
+        want = ref.apply(f)
+        got = g.vcycle(f.reshape(n + 2, n + 2)).reshape(-1)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+        w64, w32 = ref64.apply(f), ref32.apply(f)
+        assert np.linalg.norm(want - w64) > 1e-12 * np.linalg.norm(w64)
+        assert np.linalg.norm(want - w32) > 1e-12 * np.linalg.norm(w64)
+
+
 def test_mixed_onepass_output_is_float():
     """With every store rounded (one-pass schedule, rounded input and
     output) the cycle's result lies on the complex-float grid, and switching
