@@ -470,8 +470,10 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         }
         // a level small enough for one workgroup may run whole (no halo
         // work, but one CU): same two legs, kept only if faster
+        // (with several right-hand sides the tiles are kept: only they run
+        // every right-hand side in one launch)
         bool whole = false;
-        if (kacz_level_fits(L.geo) && !float_level) {
+        if (kacz_level_fits(L.geo) && !float_level && g->nrhs == 1) {
             auto legs = [&]() {
                 launch_kacz_level(L.prec, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], pl.sigma_resid[l],
                                   pl.pre[l], S.f[l], nullptr, nullptr, S.u[l], S.f[l + 1], nullptr);
@@ -512,6 +514,39 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = std::make_pair(g->lev[l].kacz_cfg, g->lev[l].mode);
     return HMG_OK;
+}
+
+// The byte distance between the buffers of consecutive slots when it is the
+// same for every per-slot buffer (the carver lays the slots out alike), else 0.
+static long slot_stride(const hmg_grid *g) {
+    if (g->nrhs < 2) return 0;
+    auto ptrs = [&](const Slot &S) {
+        std::vector<const char *> v;
+        for (int l = 0; l < g->nlev; ++l) {
+            v.push_back((const char *)S.f[l]);
+            v.push_back((const char *)S.u[l]);
+            v.push_back((const char *)S.u2[l]);
+        }
+        const Krylov &K = S.K;
+        const void *kv[] = {K.b, K.x, K.r, K.rh, K.p, K.v, K.s, K.t, K.ph, K.sh, K.partials, K.st};
+        for (const void *q : kv) v.push_back((const char *)q);
+        return v;
+    };
+    const std::vector<const char *> p0 = ptrs(g->slot[0]), p1 = ptrs(g->slot[1]);
+    const long zs = (long)(p1[0] - p0[0]);
+    for (int r = 1; r < g->nrhs; ++r) {
+        const std::vector<const char *> pr = ptrs(g->slot[r]);
+        for (size_t q = 0; q < p0.size(); ++q)
+            if (pr[q] - p0[q] != (long)r * zs) return 0;
+    }
+    return zs;
+}
+
+bool grid_batchable(const hmg_grid *g) {
+    if (g->nrhs < 2 || g->zs == 0 || one_pass(g) || g->lb < 0 || !g->bop) return false;
+    for (int l = 0; l < g->lb; ++l)
+        if (g->lev[l].mode != LM_GS_FUSED && g->lev[l].mode != LM_KACZ_TILED) return false;
+    return true;
 }
 
 static hmg_status tune_levels(hmg_grid *g) {
@@ -665,6 +700,7 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     c.base = g->mem;
     layout(g, c);
     bottom_desc(g);
+    g->zs = slot_stride(g);
     hmg_status st = grid_init_device(g, kl, inv, f);
     if (st == HMG_OK) {
         for (int l = 0; l < g->nlev; ++l)
@@ -725,10 +761,10 @@ extern "C" void hmg_grid_destroy(hmg_grid *g) {
     if (!g) return;
     (void)hipSetDevice(g->ctx->device);
     if (g->stream) (void)hipStreamSynchronize(g->stream);
-    for (Slot &S : g->slot) {
+    for (Slot &S : g->slot)
         if (S.iter_graph) (void)hipGraphExecDestroy(S.iter_graph);
-        if (S.K.hist) (void)hipFree(S.K.hist);
-    }
+    if (g->hist_all) (void)hipFree(g->hist_all);
+    if (g->batch_graph) (void)hipGraphExecDestroy(g->batch_graph);
     if (g->mem) (void)hipFree(g->mem);
     for (int q = 0; q < 4; ++q)
         if (g->ev[q]) (void)hipEventDestroy(g->ev[q]);
@@ -806,13 +842,13 @@ static void vcycle_level(hmg_grid *g, Slot &S, int l, const void *f, void *u, hi
 // `out` when given (else to a level buffer, whose pointer is returned).  f64
 // marks the FP64 level-0 input / output of the mixed precision.
 static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64, void *out, hipStream_t s,
-                           const int *skip, MvFuse *mv = nullptr) {
+                           const int *skip, MvFuse *mv = nullptr, Bz bz = {}) {
     const Level &L = g->lev[l];
     const hmg_plan &pl = g->plan;
     if (l == g->lb) {
         void *dst = out ? out : S.u[l];
-        if (g->bop) launch_dense_apply(L.prec, f64, s, g->bop, g->bop_m, f, dst, skip);
-        else launch_bottom(L.prec, f64, s, g->bottom, f, dst, skip);
+        if (g->bop) launch_dense_apply(L.prec, f64, s, g->bop, g->bop_m, f, dst, skip, bz);
+        else launch_bottom(L.prec, f64, s, g->bottom, f, dst, skip);   // single right-hand side only
         return dst;
     }
     if (L.mode == LM_GS_FUSED) {
@@ -825,20 +861,20 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         // recompute it from f.
         void *u0 = (L.prec == P64 && L.geo.n <= 511) ? S.u[l] : nullptr;
         launch_gs_down(L.prec, f64, s, L.geo, L.k, pl.sigma_relax[l], pl.sigma_resid[l], f, u0, S.f[l + 1],
-                       skip, true);
-        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
+                       skip, true, bz);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip, nullptr, bz);
         void *dst = out ? out : S.u2[l];
         // the finest up kernel of an FP64 solve also forms the Krylov product
         // of its result when the caller asks for it
         if (mv && l == 0 && !u0 && !f64 && gs_up_mv_ok(L.prec, L.geo) &&
             gs_up_mv_blocks(L.geo) <= S.K.pcap) {
             launch_gs_up_mv(s, mv->kind, L.geo, L.k, pl.sigma_relax[l], f, e, mv->no_z ? nullptr : dst, mv->out,
-                            mv->dot, mv->partials, skip);
+                            mv->dot, mv->partials, skip, bz);
             mv->blocks = gs_up_mv_blocks(L.geo);
             mv->fused = true;
             return dst;
         }
-        launch_gs_up(L.prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip);
+        launch_gs_up(L.prec, f64, s, L.geo, L.k, pl.sigma_relax[l], f, u0, e, dst, skip, bz);
         return dst;
     }
     size_t m = (size_t)L.geo.M * L.geo.M;
@@ -847,7 +883,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         double sig = pl.sigma_relax[l];
         launch_kacz_level(L.prec, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], pl.pre[l], f, nullptr, nullptr,
                           S.u[l], S.f[l + 1], skip);
-        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip, nullptr, bz);
         void *dst = out ? out : S.u2[l];
         launch_kacz_level(L.prec, s, L.geo, L.k, L.ktab, sig, 0.0, pl.post[l], f, S.u[l], e, dst, nullptr, skip);
         return dst;
@@ -863,29 +899,32 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         for (int q = 0; q < pl.pre[l]; q += sw) {
             if (fuse && q + sw >= pl.pre[l])
                 launch_kacz_tb_resid(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], f, cur, bufs[w],
-                                     S.f[l + 1], skip);
+                                     S.f[l + 1], skip, bz);
             else
-                launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, nullptr, bufs[w], skip);
+                launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, nullptr, bufs[w], skip, bz);
             cur = bufs[w];
             w ^= 1;
         }
         if (!cur) {
-            launch_fill_zero(L.prec, s, bufs[w], m, skip);
+            launch_fill_zero(L.prec, s, bufs[w], m, skip, bz);
             cur = bufs[w];
             w ^= 1;
         }
-        if (!fuse) launch_residual_fw(L.prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip);
-        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
+        if (!fuse) launch_residual_fw(L.prec, s, L.geo, L.k, pl.sigma_resid[l], f, cur, S.f[l + 1], skip, bz);
+        const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip, nullptr, bz);
         if (pl.post[l] == 0) {
-            launch_prolong_add(L.prec, s, L.geo, e, (void *)cur, skip);
+            launch_prolong_add(L.prec, s, L.geo, e, (void *)cur, skip, bz);
         }
         for (int q = 0; q < pl.post[l]; q += sw) {
-            launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip);
+            launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, q == 0 ? e : nullptr, bufs[w], skip,
+                           bz);
             cur = bufs[w];
             w ^= 1;
         }
         if (out) {
-            (void)hipMemcpyAsync(out, cur, m * (L.prec == P64 ? 16 : 8), hipMemcpyDeviceToDevice, s);
+            for (int z = 0; z < bz.nz; ++z)
+                (void)hipMemcpyAsync((char *)out + z * bz.zs, (const char *)cur + z * bz.zs,
+                                     m * (L.prec == P64 ? 16 : 8), hipMemcpyDeviceToDevice, s);
             return out;
         }
         return cur;
@@ -894,7 +933,7 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
     void *u = out ? out : S.u[l];
     relax(g, l, f, u, pl.pre[l], true, s, skip);
     launch_residual_fw(L.prec, s, L.geo, L.k, pl.sigma_resid[l], f, u, S.f[l + 1], skip);
-    const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);
+    const void *e = vc_fast(g, S, l + 1, S.f[l + 1], g->lev[l + 1].io64, nullptr, s, skip);   // single only
     launch_prolong_add(L.prec, s, L.geo, e, u, skip);
     relax(g, l, f, u, pl.post[l], false, s, skip);
     return u;
@@ -908,18 +947,19 @@ bool vcycle_forms_products(const hmg_grid *g, const Slot &S) {
            gs_up_mv_ok(P64, g0) && gs_up_mv_blocks(g0) <= S.K.pcap;
 }
 
-// z = B_V r on FP64 device fields r, z (finest level).
+// z = B_V r on FP64 device fields r, z (finest level); batched (bz.nz > 1)
+// on the right-hand sides of S and the slots after it.
 void enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip,
-                    MvFuse *mv) {
+                    MvFuse *mv, Bz bz) {
     if (!one_pass(g)) {
         bool mixed = g->lev[0].prec == P32;
         if (!mixed || g->lb == 0 || g->lev[0].mode == LM_GS_FUSED) {
-            vc_fast(g, S, 0, r, mixed, z, s, skip, mv);
+            vc_fast(g, S, 0, r, mixed, z, s, skip, mv, bz);
         } else {
             size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
-            launch_convert(s, 1, r, S.f[0], m0, skip);
-            const void *res = vc_fast(g, S, 0, S.f[0], false, nullptr, s, skip);
-            launch_convert(s, 0, res, z, m0, skip);
+            launch_convert(s, 1, r, S.f[0], m0, skip, bz);
+            const void *res = vc_fast(g, S, 0, S.f[0], false, nullptr, s, skip, nullptr, bz);
+            launch_convert(s, 0, res, z, m0, skip, bz);
         }
         return;
     }

@@ -14,6 +14,8 @@
 
 #include "hmg_internal.h"
 
+#include <type_traits>
+
 namespace hmgk {
 
 
@@ -109,6 +111,16 @@ __device__ __forceinline__ C<R> row_apply(const Row<R> &r, const C<T> *u, int i,
 struct GeoT {
     int n, M, N;
 };
+
+// Pointer p of right-hand side blockIdx.z in a batched launch (zs bytes
+// between right-hand sides; null stays null).  The offset is applied to a
+// byte pointer, not an integer, so the compiler keeps knowing that p points
+// to global memory (global, not flat, loads and stores).
+template <typename T>
+__device__ __forceinline__ T *zsh(T *p, long zs) {
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return p ? reinterpret_cast<T *>(reinterpret_cast<B *>(p) + (size_t)blockIdx.z * (size_t)zs) : p;
+}
 
 // Launches queued past convergence see a device flag and return.  The flag
 // is read together with a kernel's first loads instead of before them (one

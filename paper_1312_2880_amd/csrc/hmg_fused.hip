@@ -309,7 +309,11 @@ __device__ __forceinline__ void k_gs_down_body(GeoT g, double H, double ih2, con
 template <class TL, typename T, typename TF>
 __global__ __launch_bounds__(GNT) void k_gs_down(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                  double sb, const C<TF> *__restrict__ f, C<T> *uo,
-                                                 C<T> *__restrict__ fc, int uo_black, const int *skip) {
+                                                 C<T> *__restrict__ fc, int uo_black, const int *skip, long zs) {
+    f = zsh(f, zs);
+    uo = zsh(uo, zs);
+    fc = zsh(fc, zs);
+    skip = zsh(skip, zs);
     const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];      // the iterate, then the residual on tile + 1
     const int tid = threadIdx.x;
@@ -554,8 +558,15 @@ __global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, 
                                                   double sa, const C<double> *__restrict__ f,
                                                   const C<double> *__restrict__ ec, C<double> *__restrict__ uo,
                                                   C<double> *__restrict__ mvo, const C<double> *__restrict__ dot,
-                                                  double *partials, const int *skip) {
+                                                  double *partials, const int *skip, long zs) {
     using TL = GsBigMV;
+    f = zsh(f, zs);
+    ec = zsh(ec, zs);
+    uo = zsh(uo, zs);
+    mvo = zsh(mvo, zs);
+    dot = zsh(dot, zs);
+    partials = zsh(partials, zs);
+    skip = zsh(skip, zs);
     const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
@@ -576,7 +587,11 @@ __global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, 
 template <class TL, typename T, typename TF, typename TU>
 __global__ __launch_bounds__(GNT) void k_gs_up(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                const C<TF> *__restrict__ f, const C<T> *__restrict__ ec,
-                                               C<TU> *__restrict__ uo, const int *skip) {
+                                               C<TU> *__restrict__ uo, const int *skip, long zs) {
+    f = zsh(f, zs);
+    ec = zsh(ec, zs);
+    uo = zsh(uo, zs);
+    skip = zsh(skip, zs);
     const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
@@ -675,8 +690,13 @@ template <class TL, typename T, typename TF, typename TU>
 __global__ __launch_bounds__(GNT) void k_gs_up_u0(GeoT g, double H, double ih2, const T *__restrict__ k, double sa,
                                                   const C<TF> *__restrict__ f, const C<T> *__restrict__ u0,
                                                   const C<T> *__restrict__ ec, C<TU> *__restrict__ uo,
-                                                  const int *skip) {
+                                                  const int *skip, long zs) {
     static_assert(TL::RH == 2, "halo of two");
+    f = zsh(f, zs);
+    u0 = zsh(u0, zs);
+    ec = zsh(ec, zs);
+    uo = zsh(uo, zs);
+    skip = zsh(skip, zs);
     const int sk = flag_read(skip);
     __shared__ C<double> U[TL::LW * TL::LH];
     const int tid = threadIdx.x;
@@ -719,7 +739,14 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
                                                 const C<double> *__restrict__ ktab, double sig,
                                                 double sigb, const C<T> *__restrict__ f,
                                                 const C<T> *__restrict__ ui, const C<T> *__restrict__ ec,
-                                                C<T> *__restrict__ uo, C<T> *__restrict__ fc, const int *skip) {
+                                                C<T> *__restrict__ uo, C<T> *__restrict__ fc, const int *skip,
+                                                long zs) {
+    f = zsh(f, zs);
+    ui = zsh(ui, zs);
+    ec = zsh(ec, zs);
+    uo = zsh(uo, zs);
+    fc = zsh(fc, zs);
+    skip = zsh(skip, zs);
     const int sk = flag_read(skip);
     constexpr int TS = RESID ? TS0 - 4 : TS0, TY = RESID ? TY0 - 4 : TY0;
     constexpr int RH = 10 * S + (RESID ? 2 : 0), LW = TS + 2 * RH, LH = TY + 2 * RH;
@@ -1267,7 +1294,10 @@ constexpr int DNT = 256, DMAX = 33 * 33, DPT = (DMAX + DNT - 1) / DNT;
 template <typename TF, typename TU>
 __global__ __launch_bounds__(DNT) void k_dense_apply(const C<double> *__restrict__ B, int m,
                                                      const C<TF> *__restrict__ f, C<TU> *__restrict__ u,
-                                                     const int *skip) {
+                                                     const int *skip, long zs) {
+    f = zsh(f, zs);
+    u = zsh(u, zs);
+    skip = zsh(skip, zs);
     const int sk = flag_read(skip);
     __shared__ double part[2][DNT / 64];
     const int tid = threadIdx.x, r = blockIdx.x;
@@ -1321,60 +1351,65 @@ static bool gs_tiny(const Geo &g) {
 }
 
 template <class TL>
-static dim3 gs_grid(const Geo &g) { return dim3((g.M + TL::X - 1) / TL::X, (g.M + TL::Y - 1) / TL::Y); }
+static dim3 gs_grid(const Geo &g, int nz = 1) {
+    return dim3((g.M + TL::X - 1) / TL::X, (g.M + TL::Y - 1) / TL::Y, nz);
+}
 
 template <typename T, typename TF>
 static void gs_down_t(hipStream_t s, const Geo &g, const void *k, double sa, double sb, const void *f, void *uo,
-                      void *fc, bool uo_black, const int *skip) {
+                      void *fc, bool uo_black, const int *skip, Bz bz) {
     if (gs_tiny(g))
-        k_gs_down<GsTiny, T, TF><<<gs_grid<GsTiny>(g), GNT, 0, s>>>(
+        k_gs_down<GsTiny, T, TF><<<gs_grid<GsTiny>(g, bz.nz), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
-            uo_black ? 1 : 0, skip);
+            uo_black ? 1 : 0, skip, bz.zs);
     else if (gs_small(g))
-        k_gs_down<GsSmall, T, TF><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
+        k_gs_down<GsSmall, T, TF><<<gs_grid<GsSmall>(g, bz.nz), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
-            uo_black ? 1 : 0, skip);
+            uo_black ? 1 : 0, skip, bz.zs);
     else
-        k_gs_down<GsDownBig, T, TF><<<gs_grid<GsDownBig>(g), GNT, 0, s>>>(
+        k_gs_down<GsDownBig, T, TF><<<gs_grid<GsDownBig>(g, bz.nz), GNT, 0, s>>>(
             geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, sb, (const C<TF> *)f, (C<T> *)uo, (C<T> *)fc,
-            uo_black ? 1 : 0, skip);
+            uo_black ? 1 : 0, skip, bz.zs);
 }
 
 void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void *k, double sa, double sb,
-                    const void *f, void *uo, void *fc, const int *skip, bool uo_black) {
-    if (p == P64) gs_down_t<double, double>(s, g, k, sa, sb, f, uo, fc, uo_black, skip);
-    else if (f64in) gs_down_t<float, double>(s, g, k, sa, sb, f, uo, fc, uo_black, skip);
-    else gs_down_t<float, float>(s, g, k, sa, sb, f, uo, fc, uo_black, skip);
+                    const void *f, void *uo, void *fc, const int *skip, bool uo_black, Bz bz) {
+    if (p == P64) gs_down_t<double, double>(s, g, k, sa, sb, f, uo, fc, uo_black, skip, bz);
+    else if (f64in) gs_down_t<float, double>(s, g, k, sa, sb, f, uo, fc, uo_black, skip, bz);
+    else gs_down_t<float, float>(s, g, k, sa, sb, f, uo, fc, uo_black, skip, bz);
 }
 
 template <typename T, typename TF, typename TU>
 static void gs_up_t(hipStream_t s, const Geo &g, const void *k, double sa, const void *f, const void *u0,
-                    const void *ec, void *uo, const int *skip) {
+                    const void *ec, void *uo, const int *skip, Bz bz) {
     const double ih2 = 1.0 / (g.H * g.H);
     if (u0) {
         if (gs_tiny(g))
-            k_gs_up_u0<GsTiny2, T, TF, TU><<<gs_grid<GsTiny2>(g), GNT, 0, s>>>(
+            k_gs_up_u0<GsTiny2, T, TF, TU><<<gs_grid<GsTiny2>(g, bz.nz), GNT, 0, s>>>(
                 geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
-                (C<TU> *)uo, skip);
+                (C<TU> *)uo, skip, bz.zs);
         else if (gs_small(g))
-            k_gs_up_u0<GsSmall2, T, TF, TU><<<gs_grid<GsSmall2>(g), GNT, 0, s>>>(
+            k_gs_up_u0<GsSmall2, T, TF, TU><<<gs_grid<GsSmall2>(g, bz.nz), GNT, 0, s>>>(
                 geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
-                (C<TU> *)uo, skip);
+                (C<TU> *)uo, skip, bz.zs);
         else
-            k_gs_up_u0<GsBig2, T, TF, TU><<<gs_grid<GsBig2>(g), GNT, 0, s>>>(
+            k_gs_up_u0<GsBig2, T, TF, TU><<<gs_grid<GsBig2>(g, bz.nz), GNT, 0, s>>>(
                 geo_t(g), g.H, ih2, (const T *)k, sa, (const C<TF> *)f, (const C<T> *)u0, (const C<T> *)ec,
-                (C<TU> *)uo, skip);
+                (C<TU> *)uo, skip, bz.zs);
         return;
     }
     if (gs_tiny(g))
-        k_gs_up<GsTiny, T, TF, TU><<<gs_grid<GsTiny>(g), GNT, 0, s>>>(
-            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
+        k_gs_up<GsTiny, T, TF, TU><<<gs_grid<GsTiny>(g, bz.nz), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip,
+            bz.zs);
     else if (gs_small(g))
-        k_gs_up<GsSmall, T, TF, TU><<<gs_grid<GsSmall>(g), GNT, 0, s>>>(
-            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
+        k_gs_up<GsSmall, T, TF, TU><<<gs_grid<GsSmall>(g, bz.nz), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip,
+            bz.zs);
     else
-        k_gs_up<GsBig, T, TF, TU><<<gs_grid<GsBig>(g), GNT, 0, s>>>(
-            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip);
+        k_gs_up<GsBig, T, TF, TU><<<gs_grid<GsBig>(g, bz.nz), GNT, 0, s>>>(
+            geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k, sa, (const C<TF> *)f, (const C<T> *)ec, (C<TU> *)uo, skip,
+            bz.zs);
 }
 
 bool gs_up_mv_ok(Prec p, const Geo &g) { return p == P64 && !gs_small(g) && g.n > 511; }
@@ -1383,44 +1418,46 @@ int gs_up_mv_blocks(const Geo &g) {
     return (int)(tg.x * tg.y);
 }
 void launch_gs_up_mv(hipStream_t s, int kind, const Geo &g, const void *k, double sa, const void *f,
-                     const void *ec, void *uo, void *mvo, const void *dot, double *partials, const int *skip) {
+                     const void *ec, void *uo, void *mvo, const void *dot, double *partials, const int *skip,
+                     Bz bz) {
     const double ih2 = 1.0 / (g.H * g.H);
     if (kind == 1)
-        k_gs_up_mv<1><<<gs_grid<GsBigMV>(g), GNT, 0, s>>>(
+        k_gs_up_mv<1><<<gs_grid<GsBigMV>(g, bz.nz), GNT, 0, s>>>(
             geo_t(g), g.H, ih2, (const double *)k, sa, (const C<double> *)f, (const C<double> *)ec,
-            (C<double> *)uo, (C<double> *)mvo, (const C<double> *)dot, partials, skip);
+            (C<double> *)uo, (C<double> *)mvo, (const C<double> *)dot, partials, skip, bz.zs);
     else
-        k_gs_up_mv<2><<<gs_grid<GsBigMV>(g), GNT, 0, s>>>(
+        k_gs_up_mv<2><<<gs_grid<GsBigMV>(g, bz.nz), GNT, 0, s>>>(
             geo_t(g), g.H, ih2, (const double *)k, sa, (const C<double> *)f, (const C<double> *)ec,
-            (C<double> *)uo, (C<double> *)mvo, (const C<double> *)dot, partials, skip);
+            (C<double> *)uo, (C<double> *)mvo, (const C<double> *)dot, partials, skip, bz.zs);
 }
 
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
-                  const void *u0, const void *ec, void *uo, const int *skip) {
-    if (p == P64) gs_up_t<double, double, double>(s, g, k, sa, f, u0, ec, uo, skip);
-    else if (io64) gs_up_t<float, double, double>(s, g, k, sa, f, u0, ec, uo, skip);
-    else gs_up_t<float, float, float>(s, g, k, sa, f, u0, ec, uo, skip);
+                  const void *u0, const void *ec, void *uo, const int *skip, Bz bz) {
+    if (p == P64) gs_up_t<double, double, double>(s, g, k, sa, f, u0, ec, uo, skip, bz);
+    else if (io64) gs_up_t<float, double, double>(s, g, k, sa, f, u0, ec, uo, skip, bz);
+    else gs_up_t<float, float, float>(s, g, k, sa, f, u0, ec, uo, skip, bz);
 }
 
 template <typename T, int TS, int S, int NT, int TY = TS>
 static void kacz_tb_t(hipStream_t s, const Geo &g, const void *k, const double *tab, double sig, const void *f,
-                      const void *ui, const void *ec, void *uo, const int *skip) {
-    dim3 grid((g.M + TS - 1) / TS, (g.M + TY - 1) / TY);
+                      const void *ui, const void *ec, void *uo, const int *skip, Bz bz) {
+    dim3 grid((g.M + TS - 1) / TS, (g.M + TY - 1) / TY, bz.nz);
     k_kacz_tb<T, TS, S, NT, false, TY><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
                                                        (const C<double> *)tab, sig, 0.0, (const C<T> *)f,
                                                        (const C<T> *)ui, (const C<T> *)ec, (C<T> *)uo, nullptr,
-                                                       skip);
+                                                       skip, bz.zs);
 }
 
 // the RESID form of a configuration: tile TS - 4, halo 10 S + 2
 template <typename T, int TS, int S, int NT, int TY = TS>
 static void kacz_tb_resid_t(hipStream_t s, const Geo &g, const void *k, const double *tab, double sig, double sigb,
-                            const void *f, const void *ui, void *uo, void *fc, const int *skip) {
+                            const void *f, const void *ui, void *uo, void *fc, const int *skip, Bz bz) {
     constexpr int T4 = TS - 4, Y4 = TY - 4;
-    dim3 grid((g.M + T4 - 1) / T4, (g.M + Y4 - 1) / Y4);
+    dim3 grid((g.M + T4 - 1) / T4, (g.M + Y4 - 1) / Y4, bz.nz);
     k_kacz_tb<T, TS, S, NT, true, TY><<<grid, NT, 0, s>>>(geo_t(g), g.H, 1.0 / (g.H * g.H), (const T *)k,
                                                       (const C<double> *)tab, sig, sigb, (const C<T> *)f,
-                                                      (const C<T> *)ui, nullptr, (C<T> *)uo, (C<T> *)fc, skip);
+                                                      (const C<T> *)ui, nullptr, (C<T> *)uo, (C<T> *)fc, skip,
+                                                      bz.zs);
 }
 
 // Tile configurations offered to the tuner: (tile width, sweeps per launch,
@@ -1441,23 +1478,23 @@ bool kacz_cfg_fits(Prec, int cfg) {
 
 template <typename T>
 static void kacz_tb_any(int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
-                        const void *f, const void *ui, const void *ec, void *uo, const int *skip) {
+                        const void *f, const void *ui, const void *ec, void *uo, const int *skip, Bz bz) {
     switch (cfg) {
-    case 0: kacz_tb_t<T, 32, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    case 1: kacz_tb_t<T, 32, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    case 2: kacz_tb_t<T, 16, 2, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    case 3: kacz_tb_t<T, 16, 4, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    case 4: kacz_tb_t<T, 16, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    case 5: kacz_tb_t<T, 16, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    case 7: kacz_tb_t<T, 16, 2, 1024, 8>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
-    default: kacz_tb_t<T, 32, 1, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip); break;
+    case 0: kacz_tb_t<T, 32, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    case 1: kacz_tb_t<T, 32, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    case 2: kacz_tb_t<T, 16, 2, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    case 3: kacz_tb_t<T, 16, 4, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    case 4: kacz_tb_t<T, 16, 2, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    case 5: kacz_tb_t<T, 16, 1, 512>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    case 7: kacz_tb_t<T, 16, 2, 1024, 8>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
+    default: kacz_tb_t<T, 32, 1, 1024>(s, g, k, tab, sig, f, ui, ec, uo, skip, bz); break;
     }
 }
 
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
-                    const void *f, const void *ui, const void *ec, void *uo, const int *skip) {
-    if (p == P64) kacz_tb_any<double>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip);
-    else kacz_tb_any<float>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip);
+                    const void *f, const void *ui, const void *ec, void *uo, const int *skip, Bz bz) {
+    if (p == P64) kacz_tb_any<double>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip, bz);
+    else kacz_tb_any<float>(cfg, s, g, k, tab, sig, f, ui, ec, uo, skip, bz);
 }
 
 bool kacz_level_fits(const Geo &g) { return g.M <= LMAX; }
@@ -1495,22 +1532,22 @@ bool kacz_cfg_resid(int cfg) {
 
 template <typename T>
 static void kacz_resid_any(int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
-                           double sigb, const void *f, const void *ui, void *uo, void *fc, const int *skip) {
+                           double sigb, const void *f, const void *ui, void *uo, void *fc, const int *skip, Bz bz) {
     switch (cfg) {
-    case 0: kacz_tb_resid_t<T, 32, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
-    case 2: kacz_tb_resid_t<T, 16, 2, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
-    case 4: kacz_tb_resid_t<T, 16, 2, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
-    case 5: kacz_tb_resid_t<T, 16, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
-    case 7: kacz_tb_resid_t<T, 16, 2, 1024, 12>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
-    default: kacz_tb_resid_t<T, 32, 1, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip); break;
+    case 0: kacz_tb_resid_t<T, 32, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz); break;
+    case 2: kacz_tb_resid_t<T, 16, 2, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz); break;
+    case 4: kacz_tb_resid_t<T, 16, 2, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz); break;
+    case 5: kacz_tb_resid_t<T, 16, 1, 512>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz); break;
+    case 7: kacz_tb_resid_t<T, 16, 2, 1024, 12>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz); break;
+    default: kacz_tb_resid_t<T, 32, 1, 1024>(s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz); break;
     }
 }
 
 void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab,
                           double sig, double sigb, const void *f, const void *ui, void *uo, void *fc,
-                          const int *skip) {
-    if (p == P64) kacz_resid_any<double>(cfg, s, g, k, tab, sig, sigb, f, ui, uo, fc, skip);
-    else kacz_resid_any<float>(cfg, s, g, k, tab, sig, sigb, f, ui, uo, fc, skip);
+                          const int *skip, Bz bz) {
+    if (p == P64) kacz_resid_any<double>(cfg, s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz);
+    else kacz_resid_any<float>(cfg, s, g, k, tab, sig, sigb, f, ui, uo, fc, skip, bz);
 }
 
 int bottom_complex_slots() { return BOT_C_ELEMS; }
@@ -1562,11 +1599,13 @@ void launch_bottom_basis(Prec p, hipStream_t s, const BottomDesc &d, double *B) 
 }
 
 void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m, const void *f, void *u,
-                        const int *skip) {
-    dim3 grid(m);
+                        const int *skip, Bz bz) {
+    dim3 grid(m, 1, bz.nz);
     const C<double> *b = (const C<double> *)B;
-    if (p == P64 || io64) k_dense_apply<double, double><<<grid, DNT, 0, s>>>(b, m, (const C<double> *)f, (C<double> *)u, skip);
-    else k_dense_apply<float, float><<<grid, DNT, 0, s>>>(b, m, (const C<float> *)f, (C<float> *)u, skip);
+    if (p == P64 || io64)
+        k_dense_apply<double, double><<<grid, DNT, 0, s>>>(b, m, (const C<double> *)f, (C<double> *)u, skip, bz.zs);
+    else
+        k_dense_apply<float, float><<<grid, DNT, 0, s>>>(b, m, (const C<float> *)f, (C<float> *)u, skip, bz.zs);
 }
 
 void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo, const int *skip) {

@@ -82,6 +82,10 @@ struct hmg_grid {
     char      *mem = nullptr;
     size_t     bytes = 0;
     hipStream_t stream = nullptr;
+    long       zs = 0;            // bytes between the buffers of consecutive slots (0: not uniform)
+    double    *hist_all = nullptr;  // residual histories of every slot, hist_cap doubles each
+    int        hist_cap = 0;
+    hipGraphExec_t batch_graph = nullptr;  // one iteration of every right-hand side, batched
     hmgk::KState *host_state = nullptr;   // pinned, 4 entries
     int          *done_host = nullptr;    // pinned, one done flag per right-hand side
     hipEvent_t ev[4] = {};
@@ -110,4 +114,8 @@ struct MvFuse {
 // kry_update_yr / kry_fold, and the V-cycle outputs are not stored).
 bool       vcycle_forms_products(const hmg_grid *g, const Slot &S);
 void       enqueue_vcycle(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s,
-                          const int *skip, MvFuse *mv = nullptr);
+                          const int *skip, MvFuse *mv = nullptr, hmgk::Bz bz = {});
+// Whether every right-hand side of the grid can run in one batched launch
+// per kernel (fused schedule with the dense bottom matrix, no whole-level
+// Kaczmarz kernel, slots at one stride); then g->zs is that stride.
+bool       grid_batchable(const hmg_grid *g);

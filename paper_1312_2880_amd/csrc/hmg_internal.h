@@ -46,6 +46,16 @@ struct KState {
     int    check;        // a true-residual check is due after this iteration
 };
 
+// A batched launch runs one kernel on nz right-hand sides of a grid at once
+// (blockIdx.z): every per-right-hand-side buffer of slot z lies zs bytes
+// after the same buffer of slot z - 1 (the slots of a grid are carved with
+// one layout), so a kernel offsets those pointers by blockIdx.z * zs and
+// leaves the shared ones (k, row tables, the bottom matrix) alone.
+struct Bz {
+    long zs = 0;
+    int  nz = 1;
+};
+
 // Device pointers of one solve slot (finest-level Krylov vectors).
 struct Krylov {
     double *b, *x, *r, *rh, *p, *v, *s, *t, *ph, *sh;   // complex interleaved
@@ -65,15 +75,15 @@ void launch_gs_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double
                       const void *f, void *u, int colour, int zero_guess, const int *skip);
 void launch_kacz_colour(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma,
                         const void *f, void *u, int colour, const int *skip);
-void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *skip);
+void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *skip, Bz bz = {});
 void launch_residual_fw(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma,
-                        const void *f, const void *u, void *fc, const int *skip);
+                        const void *f, const void *u, void *fc, const int *skip, Bz bz = {});
 void launch_prolong_add(Prec p, hipStream_t s, const Geo &gfine, const void *ec, void *u,
-                        const int *skip);
+                        const int *skip, Bz bz = {});
 void launch_coarsest(Prec p, hipStream_t s, int m, const double *ainv_t, const void *f,
                      void *u, const int *skip);
 void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, size_t count,
-                    const int *skip);
+                    const int *skip, Bz bz = {});
 
 // ---- lexicographic sweeps (hmg_lex.hip) -------------------------------------
 // One sweep in lexicographic order (x fastest) of Gauss-Seidel (kacz = 0) or
@@ -112,14 +122,14 @@ int    bottom_real_slots();
 // f64in / io64: the level-0 input (and output) are FP64 while the level
 // computes in float (mixed precision).
 void launch_gs_down(Prec p, bool f64in, hipStream_t s, const Geo &g, const void *k, double sa, double sb,
-                    const void *f, void *uo, void *fc, const int *skip, bool uo_black = false);
+                    const void *f, void *uo, void *fc, const int *skip, bool uo_black = false, Bz bz = {});
 // uo may be null in launch_gs_down (the smoothed iterate is not stored);
 // uo_black: store it on the black nodes only (all that launch_gs_up reads);
 // launch_gs_up recomputes it from f.
 // u0: the pre-smoothed iterate stored by launch_gs_down, or null (recomputed
 // from f)
 void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k, double sa, const void *f,
-                  const void *u0, const void *ec, void *uo, const int *skip);
+                  const void *u0, const void *ec, void *uo, const int *skip, Bz bz = {});
 // The finest up kernel of an FP64 solve fused with the Bi-CGSTAB product
 // (kind 1: v = L uo with the partials of (dot, v); kind 2: t = L uo with the
 // partials of (t, dot) and (t, t)); partials laid out for gs_up_mv_blocks(g)
@@ -128,11 +138,12 @@ void launch_gs_up(Prec p, bool io64, hipStream_t s, const Geo &g, const void *k,
 bool gs_up_mv_ok(Prec p, const Geo &g);
 int  gs_up_mv_blocks(const Geo &g);
 void launch_gs_up_mv(hipStream_t s, int kind, const Geo &g, const void *k, double sa, const void *f,
-                     const void *ec, void *uo, void *mvo, const void *dot, double *partials, const int *skip);
+                     const void *ec, void *uo, void *mvo, const void *dot, double *partials, const int *skip,
+                     Bz bz = {});
 // tab: (k_p, 1 / ||a_p||^2) for sigma from launch_kacz_table, or null (the
 // kernel forms them)
 void launch_kacz_tb(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab, double sig,
-                    const void *f, const void *ui, const void *ec, void *uo, const int *skip);
+                    const void *f, const void *ui, const void *ec, void *uo, const int *skip, Bz bz = {});
 void launch_kacz_table(Prec p, hipStream_t s, const Geo &g, const void *k, double sig, double *tab);
 // a whole level (n <= 63) in one workgroup: `sweeps` sweeps from ui (null:
 // zero) + P ec (null: none) into uo, then fc = R (f - A_{sigb} uo) if fc
@@ -144,35 +155,43 @@ bool kacz_cfg_resid(int cfg);   // configuration has the fused residual form
 // S sweeps (configuration cfg) from ui (null: zero), then fc = R (f - A_{sigb} u)
 void launch_kacz_tb_resid(Prec p, int cfg, hipStream_t s, const Geo &g, const void *k, const double *tab,
                           double sig, double sigb, const void *f, const void *ui, void *uo, void *fc,
-                          const int *skip);
+                          const int *skip, Bz bz = {});
 void launch_bottom(Prec p, bool io64, hipStream_t s, const BottomDesc &d, const void *f, void *uo,
                    const int *skip);
 int  bottom_matrix_size(const BottomDesc &d);
 void launch_bottom_basis(Prec p, hipStream_t s, const BottomDesc &d, double *B);
 void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m, const void *f, void *u,
-                        const int *skip);
+                        const int *skip, Bz bz = {});
 
 // ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
+// Every launcher runs on one slot K, or batched (kb.nz > 1) on the kb.nz
+// slots from K on: their vectors, partial sums and scalars kb.zs bytes apart,
+// their residual histories kb.hz bytes apart.
+struct Kz {
+    long zs = 0, hz = 0;
+    int  nz = 1;
+};
 int  krylov_nblocks(const Geo &g);
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given,
-              double rtol, int maxhalf, int force_bd, int true_every = 0, int nan_at = 0);
+              double rtol, int maxhalf, int force_bd, int true_every = 0, int nan_at = 0,
+              Kz kb = {});
 // The periodic true-residual check (when due): r = b - L x; the solve ends
 // if it meets rtol, else restarts from it (rhat = p = r).
-void kry_checkpoint(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
-void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K);
-void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
+void kry_checkpoint(hipStream_t s, const Geo &g, const double *k, const Krylov &K, Kz kb = {});
+void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K, Kz kb = {});
+void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K, Kz kb = {});
 // the single-block finalisations after a fused product (nb partial blocks)
-void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb);
+void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb, Kz kb = {});
 // out[0..2] = the totals of nv (2 or 3) block partials, zero-padded
 void launch_sum_partials(hipStream_t s, const double *partials, int nb, int nv, double *out);
-void kry_omega_fin(hipStream_t s, const Krylov &K, int nb);
-void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K);
-void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
-void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K);
+void kry_omega_fin(hipStream_t s, const Krylov &K, int nb, Kz kb = {});
+void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K, Kz kb = {});
+void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K, Kz kb = {});
+void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K, Kz kb = {});
 // The x update kept in the preconditioner's input space (y in K.ph):
 // y += alpha p + omega s with r and its sums as kry_update_xr; kry_fold
 // adds z = B y (in K.sh) to x and clears y.
-void kry_update_yr(hipStream_t s, const Geo &g, const Krylov &K);
+void kry_update_yr(hipStream_t s, const Geo &g, const Krylov &K, Kz kb = {});
 void kry_fold(hipStream_t s, const Geo &g, const Krylov &K);
 void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K);
 void kry_restart_from_true(hipStream_t s, const Krylov &K);

@@ -11,6 +11,8 @@
 
 #include "hmg_device.h"
 
+#include <cstring>
+
 namespace hmgk {
 
 // ---------------------------------------------------------------------------
@@ -77,7 +79,9 @@ __global__ __launch_bounds__(NT) void k_kacz_colour(GeoT g, double H, double ih2
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_fill_zero(C<T> *u, size_t count, const int *skip) {
+__global__ __launch_bounds__(256) void k_fill_zero(C<T> *u, size_t count, const int *skip, long zs) {
+    u = zsh(u, zs);
+    skip = zsh(skip, zs);
     if (skip && *skip) return;
     size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (q < count) u[q] = cmk(T(0), T(0));
@@ -92,7 +96,11 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_residual_fw(GeoT g, double H, double ih2, const T *__restrict__ k,
                                                     double sigma, const C<T> *__restrict__ f,
                                                     const C<T> *__restrict__ u, C<T> *__restrict__ fc,
-                                                    const int *skip) {
+                                                    const int *skip, long zs) {
+    f = zsh(f, zs);
+    u = zsh(u, zs);
+    fc = zsh(fc, zs);
+    skip = zsh(skip, zs);
     if (skip && *skip) return;
     int Nc = g.N / 2, Mc = Nc + 1;
     int I = blockIdx.x * BX + threadIdx.x;
@@ -120,7 +128,10 @@ __global__ __launch_bounds__(NT) void k_residual_fw(GeoT g, double H, double ih2
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(NT) void k_prolong_add(GeoT g, const C<T> *__restrict__ ec, C<T> *u,
-                                                    const int *skip) {
+                                                    const int *skip, long zs) {
+    ec = zsh(ec, zs);
+    u = zsh(u, zs);
+    skip = zsh(skip, zs);
     if (skip && *skip) return;
     int i = blockIdx.x * BX + threadIdx.x;
     int j = blockIdx.y * BY + threadIdx.y;
@@ -166,14 +177,20 @@ __global__ __launch_bounds__(256) void k_coarsest(int m, const C<double> *__rest
 }
 
 __global__ __launch_bounds__(256) void k_to_float(const C<double> *__restrict__ src, C<float> *__restrict__ dst,
-                                                  size_t count, const int *skip) {
+                                                  size_t count, const int *skip, long zs) {
+    src = zsh(src, zs);
+    dst = zsh(dst, zs);
+    skip = zsh(skip, zs);
     if (skip && *skip) return;
     size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (q < count) dst[q] = cmk((float)src[q].x, (float)src[q].y);
 }
 
 __global__ __launch_bounds__(256) void k_to_double(const C<float> *__restrict__ src, C<double> *__restrict__ dst,
-                                                   size_t count, const int *skip) {
+                                                   size_t count, const int *skip, long zs) {
+    src = zsh(src, zs);
+    dst = zsh(dst, zs);
+    skip = zsh(skip, zs);
     if (skip && *skip) return;
     size_t q = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (q < count) dst[q] = cmk((double)src[q].x, (double)src[q].y);
@@ -183,7 +200,7 @@ __global__ __launch_bounds__(256) void k_to_double(const C<float> *__restrict__ 
 // Launchers
 // ---------------------------------------------------------------------------
 static inline GeoT geot(const Geo &g) { return GeoT{g.n, g.M, g.N}; }
-static inline dim3 grid2(int nx, int ny) { return dim3((nx + BX - 1) / BX, (ny + BY - 1) / BY); }
+static inline dim3 grid2(int nx, int ny, int nz = 1) { return dim3((nx + BX - 1) / BX, (ny + BY - 1) / BY, nz); }
 
 template <typename T>
 static void apply_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *u, void *out) {
@@ -222,33 +239,34 @@ void launch_kacz_colour(Prec p, hipStream_t s, const Geo &g, const void *k, doub
     else kacz_t<float>(s, g, k, sigma, f, u, colour, skip);
 }
 
-void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *skip) {
-    unsigned nb = (unsigned)((count + 255) / 256);
-    if (p == P64) k_fill_zero<double><<<nb, 256, 0, s>>>((C<double> *)u, count, skip);
-    else k_fill_zero<float><<<nb, 256, 0, s>>>((C<float> *)u, count, skip);
+void launch_fill_zero(Prec p, hipStream_t s, void *u, size_t count, const int *skip, Bz bz) {
+    dim3 nb((unsigned)((count + 255) / 256), 1, bz.nz);
+    if (p == P64) k_fill_zero<double><<<nb, 256, 0, s>>>((C<double> *)u, count, skip, bz.zs);
+    else k_fill_zero<float><<<nb, 256, 0, s>>>((C<float> *)u, count, skip, bz.zs);
 }
 
 template <typename T>
 static void rfw_t(hipStream_t s, const Geo &g, const void *k, double sigma, const void *f, const void *u, void *fc,
-                  const int *skip) {
+                  const int *skip, Bz bz) {
     double H = g.H, ih2 = 1.0 / (g.H * g.H);
     int Mc = g.N / 2 + 1;
-    k_residual_fw<T><<<grid2(Mc, Mc), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, sigma,
-                                                             (const C<T> *)f, (const C<T> *)u, (C<T> *)fc, skip);
+    k_residual_fw<T><<<grid2(Mc, Mc, bz.nz), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, (const T *)k, sigma,
+                                                                    (const C<T> *)f, (const C<T> *)u, (C<T> *)fc,
+                                                                    skip, bz.zs);
 }
 void launch_residual_fw(Prec p, hipStream_t s, const Geo &g, const void *k, double sigma, const void *f,
-                        const void *u, void *fc, const int *skip) {
-    if (p == P64) rfw_t<double>(s, g, k, sigma, f, u, fc, skip);
-    else rfw_t<float>(s, g, k, sigma, f, u, fc, skip);
+                        const void *u, void *fc, const int *skip, Bz bz) {
+    if (p == P64) rfw_t<double>(s, g, k, sigma, f, u, fc, skip, bz);
+    else rfw_t<float>(s, g, k, sigma, f, u, fc, skip, bz);
 }
 
-void launch_prolong_add(Prec p, hipStream_t s, const Geo &g, const void *ec, void *u, const int *skip) {
+void launch_prolong_add(Prec p, hipStream_t s, const Geo &g, const void *ec, void *u, const int *skip, Bz bz) {
     if (p == P64)
-        k_prolong_add<double><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), (const C<double> *)ec,
-                                                                       (C<double> *)u, skip);
+        k_prolong_add<double><<<grid2(g.M, g.M, bz.nz), dim3(BX, BY), 0, s>>>(geot(g), (const C<double> *)ec,
+                                                                              (C<double> *)u, skip, bz.zs);
     else
-        k_prolong_add<float><<<grid2(g.M, g.M), dim3(BX, BY), 0, s>>>(geot(g), (const C<float> *)ec,
-                                                                      (C<float> *)u, skip);
+        k_prolong_add<float><<<grid2(g.M, g.M, bz.nz), dim3(BX, BY), 0, s>>>(geot(g), (const C<float> *)ec,
+                                                                             (C<float> *)u, skip, bz.zs);
 }
 
 void launch_coarsest(Prec p, hipStream_t s, int m, const double *ainv_t, const void *f, void *u, const int *skip) {
@@ -260,10 +278,10 @@ void launch_coarsest(Prec p, hipStream_t s, int m, const double *ainv_t, const v
                                             skip);
 }
 
-void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, size_t count, const int *skip) {
-    unsigned nb = (unsigned)((count + 255) / 256);
-    if (to_float) k_to_float<<<nb, 256, 0, s>>>((const C<double> *)src, (C<float> *)dst, count, skip);
-    else k_to_double<<<nb, 256, 0, s>>>((const C<float> *)src, (C<double> *)dst, count, skip);
+void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, size_t count, const int *skip, Bz bz) {
+    dim3 nb((unsigned)((count + 255) / 256), 1, bz.nz);
+    if (to_float) k_to_float<<<nb, 256, 0, s>>>((const C<double> *)src, (C<float> *)dst, count, skip, bz.zs);
+    else k_to_double<<<nb, 256, 0, s>>>((const C<float> *)src, (C<double> *)dst, count, skip, bz.zs);
 }
 
 // ===========================================================================
@@ -324,6 +342,27 @@ static inline KDev kdev(const Krylov &K) {
                 (C<double> *)K.ph, (C<double> *)K.sh, K.partials, K.hist, K.st, K.done_host};
 }
 
+// The pointers of right-hand side blockIdx.z in a batched launch: the
+// vectors, partial sums and scalars of the slots lie zs bytes apart, the
+// residual histories hz bytes, the pinned done flags one int.
+__device__ __forceinline__ KDev kz(KDev K, long zs, long hz) {
+    K.b = zsh(K.b, zs);
+    K.x = zsh(K.x, zs);
+    K.r = zsh(K.r, zs);
+    K.rh = zsh(K.rh, zs);
+    K.p = zsh(K.p, zs);
+    K.v = zsh(K.v, zs);
+    K.s = zsh(K.s, zs);
+    K.t = zsh(K.t, zs);
+    K.ph = zsh(K.ph, zs);
+    K.sh = zsh(K.sh, zs);
+    K.partials = zsh(K.partials, zs);
+    K.hist = zsh(K.hist, hz);
+    K.st = zsh(K.st, zs);
+    K.done_host = zsh(K.done_host, zs ? (long)sizeof(int) : 0L);
+    return K;
+}
+
 // The host polls the done flag of a running solve through a pinned copy
 // that the kernels changing it write (a vector store to host memory), so no
 // copy is queued behind every iteration.
@@ -337,7 +376,8 @@ __device__ __forceinline__ void st2(double *p, C<double> z) { p[0] = z.x; p[1] =
 
 // ---- init: r = b - L x (or r = b, x = 0), rh = r, p = v = 0 --------------
 __global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, const double *__restrict__ k,
-                                                 KDev K, int x0_given) {
+                                                 KDev K_, long zs, long hz, int x0_given) {
+    const KDev K = kz(K_, zs, hz);
     int i = blockIdx.x * BX + threadIdx.x;
     double v[2] = {0.0, 0.0};
     for (int rr = 0; rr < KRY; ++rr) {
@@ -362,8 +402,9 @@ __global__ __launch_bounds__(NT) void k_kry_init(GeoT g, double H, double ih2, c
     block_partials<2>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol, int maxhalf, int hist_cap,
+__global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K_, long zs, long hz, int nb, double rtol, int maxhalf, int hist_cap,
                                                      int force_bd, int true_every, int nan_at) {
+    const KDev K = kz(K_, zs, hz);
     double tot[2];
     finalize_sums<2>(K.partials, nb, tot);
     if (threadIdx.x || threadIdx.y) return;
@@ -399,7 +440,8 @@ __global__ __launch_bounds__(NT) void k_kry_init_fin(KDev K, int nb, double rtol
 }
 
 // ---- p = r + beta (p - omega v); on restart rh = r and p = r ----------------
-__global__ __launch_bounds__(NT) void k_kry_update_p(GeoT g, KDev K) {
+__global__ __launch_bounds__(NT) void k_kry_update_p(GeoT g, KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     const KState *s = K.st;
     const int done = flag_read(&s->done);
     int i = blockIdx.x * BX + threadIdx.x;
@@ -432,7 +474,8 @@ __global__ __launch_bounds__(NT) void k_kry_update_p(GeoT g, KDev K) {
 
 // ---- v = L ph, partial (rh, v) ----------------------------------------------
 __global__ __launch_bounds__(NT) void k_kry_matvec_alpha(GeoT g, double H, double ih2, const double *__restrict__ k,
-                                                         KDev K) {
+                                                         KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     if (K.st->done) return;
     int i = blockIdx.x * BX + threadIdx.x;
     double v[2] = {0.0, 0.0};
@@ -450,7 +493,8 @@ __global__ __launch_bounds__(NT) void k_kry_matvec_alpha(GeoT g, double H, doubl
     block_partials<2>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K, int nb) {
+__global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K_, long zs, long hz, int nb) {
+    const KDev K = kz(K_, zs, hz);
     const int done = flag_read(&K.st->done);
     double tot[2];
     finalize_sums<2>(K.partials, nb, tot);
@@ -461,7 +505,8 @@ __global__ __launch_bounds__(NT) void k_kry_alpha_fin(KDev K, int nb) {
 }
 
 // ---- s = r - alpha v, partial ||s||^2 ----------------------------------------
-__global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K) {
+__global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     const int done = flag_read(&K.st->done);
     int i = blockIdx.x * BX + threadIdx.x;
     const C<double> alpha = ld2(K.st->alpha);
@@ -488,7 +533,8 @@ __global__ __launch_bounds__(NT) void k_kry_update_s(GeoT g, KDev K) {
     block_partials<1>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_s_fin(KDev K, int nb) {
+__global__ __launch_bounds__(NT) void k_kry_s_fin(KDev K_, long zs, long hz, int nb) {
+    const KDev K = kz(K_, zs, hz);
     const int done = flag_read(&K.st->done);
     double tot[1];
     finalize_sums<1>(K.partials, nb, tot);
@@ -512,7 +558,8 @@ __global__ __launch_bounds__(NT) void k_kry_s_fin(KDev K, int nb) {
 
 // ---- t = L sh, partials (t, s), (t, t) -----------------------------------------
 __global__ __launch_bounds__(NT) void k_kry_matvec_omega(GeoT g, double H, double ih2, const double *__restrict__ k,
-                                                         KDev K) {
+                                                         KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     if (K.st->stop) return;
     int i = blockIdx.x * BX + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
@@ -531,7 +578,8 @@ __global__ __launch_bounds__(NT) void k_kry_matvec_omega(GeoT g, double H, doubl
     block_partials<3>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_omega_fin(KDev K, int nb) {
+__global__ __launch_bounds__(NT) void k_kry_omega_fin(KDev K_, long zs, long hz, int nb) {
+    const KDev K = kz(K_, zs, hz);
     const int stop = flag_read(&K.st->stop);
     double tot[3];
     finalize_sums<3>(K.partials, nb, tot);
@@ -540,7 +588,8 @@ __global__ __launch_bounds__(NT) void k_kry_omega_fin(KDev K, int nb) {
 }
 
 // ---- x += alpha ph + omega sh; r = s - omega t; partials ||r||^2, (rh, r) -----
-__global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
+__global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     const KState *s = K.st;
     const int done = flag_read(&s->done);
     const int half = s->half_exit;
@@ -575,7 +624,8 @@ __global__ __launch_bounds__(NT) void k_kry_update_xr(GeoT g, KDev K) {
 // y += alpha p + omega s (y in the p^ buffer), x = x + B y formed once at the
 // end (k_kry_fold).  B is linear and fixed, so x is the same as with
 // x += alpha p^ + omega s^ in exact arithmetic, and p^, s^ need not be stored.
-__global__ __launch_bounds__(NT) void k_kry_update_yr(GeoT g, KDev K) {
+__global__ __launch_bounds__(NT) void k_kry_update_yr(GeoT g, KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     const KState *s = K.st;
     const int done = flag_read(&s->done);
     const int half = s->half_exit;
@@ -609,7 +659,8 @@ __global__ __launch_bounds__(NT) void k_kry_update_yr(GeoT g, KDev K) {
 }
 
 // ---- x += z (z = B y in the s^ buffer), y = 0 --------------------------------
-__global__ __launch_bounds__(NT) void k_kry_fold(GeoT g, KDev K) {
+__global__ __launch_bounds__(NT) void k_kry_fold(GeoT g, KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     int i = blockIdx.x * BX + threadIdx.x;
     for (int rr = 0; rr < KRY; ++rr) {
         int j = (blockIdx.y * KRY + rr) * BY + threadIdx.y;
@@ -620,7 +671,8 @@ __global__ __launch_bounds__(NT) void k_kry_fold(GeoT g, KDev K) {
     }
 }
 
-__global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
+__global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K_, long zs, long hz, int nb) {
+    const KDev K = kz(K_, zs, hz);
     KState *s = K.st;
     const int done = flag_read(&s->done);
     const int half = s->half_exit;
@@ -688,7 +740,8 @@ __global__ __launch_bounds__(NT) void k_kry_iter_fin(KDev K, int nb) {
 
 // ---- true residual r = b - L x, ||r||^2 ----------------------------------------
 __global__ __launch_bounds__(NT) void k_kry_true(GeoT g, double H, double ih2, const double *__restrict__ k,
-                                                 KDev K) {
+                                                 KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     int i = blockIdx.x * BX + threadIdx.x;
     double v[1] = {0.0};
     for (int rr = 0; rr < KRY; ++rr) {
@@ -703,7 +756,8 @@ __global__ __launch_bounds__(NT) void k_kry_true(GeoT g, double H, double ih2, c
     block_partials<1>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_true_fin(KDev K, int nb) {
+__global__ __launch_bounds__(NT) void k_kry_true_fin(KDev K_, long zs, long hz, int nb) {
+    const KDev K = kz(K_, zs, hz);
     double tot[1];
     finalize_sums<1>(K.partials, nb, tot);
     if (threadIdx.x || threadIdx.y) return;
@@ -713,7 +767,8 @@ __global__ __launch_bounds__(NT) void k_kry_true_fin(KDev K, int nb) {
 }
 
 // restart from the recomputed residual: rh = r, p = r on the next update
-__global__ void k_kry_restart(KDev K) {
+__global__ void k_kry_restart(KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     KState *s = K.st;
     s->restart = 1;
     s->restarts += 1;
@@ -730,7 +785,8 @@ __global__ void k_kry_restart(KDev K) {
 
 // ---- the periodic true-residual check (only when iter_fin marked it due) --
 __global__ __launch_bounds__(NT) void k_kry_check_true(GeoT g, double H, double ih2, const double *__restrict__ k,
-                                                       KDev K) {
+                                                       KDev K_, long zs, long hz) {
+    const KDev K = kz(K_, zs, hz);
     if (!K.st->check) return;
     int i = blockIdx.x * BX + threadIdx.x;
     double v[1] = {0.0};
@@ -746,7 +802,8 @@ __global__ __launch_bounds__(NT) void k_kry_check_true(GeoT g, double H, double 
     block_partials<1>(v, K.partials);
 }
 
-__global__ __launch_bounds__(NT) void k_kry_check_fin(KDev K, int nb) {
+__global__ __launch_bounds__(NT) void k_kry_check_fin(KDev K_, long zs, long hz, int nb) {
+    const KDev K = kz(K_, zs, hz);
     KState *s = K.st;
     if (!s->check) return;
     double tot[1];
@@ -774,7 +831,9 @@ __global__ __launch_bounds__(NT) void k_kry_check_fin(KDev K, int nb) {
     publish_done(K);
 }
 
-static inline dim3 kgrid(const Geo &g) { return dim3((g.M + BX - 1) / BX, (g.M + BY * KRY - 1) / (BY * KRY)); }
+static inline dim3 kgrid(const Geo &g, int nz = 1) {
+    return dim3((g.M + BX - 1) / BX, (g.M + BY * KRY - 1) / (BY * KRY), nz);
+}
 
 int krylov_nblocks(const Geo &g) {
     dim3 gr = kgrid(g);
@@ -783,32 +842,36 @@ int krylov_nblocks(const Geo &g) {
 
 static inline void hk(const Geo &g, double &H, double &ih2) { H = g.H; ih2 = 1.0 / (g.H * g.H); }
 
+// Every launcher below runs on one solve slot K, or batched (kb.nz > 1) on the
+// kb.nz slots from K on.
+static inline dim3 one(int nz) { return dim3(1, 1, nz); }
+
 void kry_init(hipStream_t s, const Geo &g, const double *k, const Krylov &K, int x0_given, double rtol,
-              int maxhalf, int force_bd, int true_every, int nan_at) {
+              int maxhalf, int force_bd, int true_every, int nan_at, Kz kb) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_init<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, x0_given);
+    k_kry_init<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, kb.zs, kb.hz, x0_given);
     // the history buffer holds maxhalf + 2 entries (allocated by the caller)
-    k_kry_init_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks, rtol, maxhalf, maxhalf + 2, force_bd, true_every,
-                                              nan_at);
+    k_kry_init_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks, rtol, maxhalf, maxhalf + 2, force_bd,
+                                                    true_every, nan_at);
 }
-void kry_checkpoint(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+void kry_checkpoint(hipStream_t s, const Geo &g, const double *k, const Krylov &K, Kz kb) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_check_true<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
-    k_kry_check_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_check_true<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, kb.zs, kb.hz);
+    k_kry_check_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks);
 }
-void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K) {
-    k_kry_update_p<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));
+void kry_update_p(hipStream_t s, const Geo &g, const Krylov &K, Kz kb) {
+    k_kry_update_p<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), kdev(K), kb.zs, kb.hz);
 }
-void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+void kry_matvec_alpha(hipStream_t s, const Geo &g, const double *k, const Krylov &K, Kz kb) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_matvec_alpha<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
-    k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_matvec_alpha<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, kb.zs, kb.hz);
+    k_kry_alpha_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks);
 }
 // partial sums of nv quantities over nb blocks -> out[0..2] (zero-padded)
 __global__ __launch_bounds__(NT) void k_sum_partials(const double *partials, int nb, int nv, double *out) {
@@ -821,44 +884,44 @@ __global__ __launch_bounds__(NT) void k_sum_partials(const double *partials, int
 void launch_sum_partials(hipStream_t s, const double *partials, int nb, int nv, double *out) {
     k_sum_partials<<<1, dim3(BX, BY), 0, s>>>(partials, nb, nv, out);
 }
-void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb) {
-    k_kry_alpha_fin<<<1, dim3(BX, BY), 0, s>>>(kdev(K), nb);
+void kry_alpha_fin(hipStream_t s, const Krylov &K, int nb, Kz kb) {
+    k_kry_alpha_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(kdev(K), kb.zs, kb.hz, nb);
 }
-void kry_omega_fin(hipStream_t s, const Krylov &K, int nb) {
-    k_kry_omega_fin<<<1, dim3(BX, BY), 0, s>>>(kdev(K), nb);
+void kry_omega_fin(hipStream_t s, const Krylov &K, int nb, Kz kb) {
+    k_kry_omega_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(kdev(K), kb.zs, kb.hz, nb);
 }
-void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K) {
+void kry_update_s(hipStream_t s, const Geo &g, const Krylov &K, Kz kb) {
     KDev d = kdev(K);
-    k_kry_update_s<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
-    k_kry_s_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_update_s<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), d, kb.zs, kb.hz);
+    k_kry_s_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks);
 }
-void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
+void kry_matvec_omega(hipStream_t s, const Geo &g, const double *k, const Krylov &K, Kz kb) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_matvec_omega<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
-    k_kry_omega_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_matvec_omega<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, kb.zs, kb.hz);
+    k_kry_omega_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks);
 }
-void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K) {
+void kry_update_xr(hipStream_t s, const Geo &g, const Krylov &K, Kz kb) {
     KDev d = kdev(K);
-    k_kry_update_xr<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
-    k_kry_iter_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_update_xr<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), d, kb.zs, kb.hz);
+    k_kry_iter_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks);
 }
-void kry_update_yr(hipStream_t s, const Geo &g, const Krylov &K) {
+void kry_update_yr(hipStream_t s, const Geo &g, const Krylov &K, Kz kb) {
     KDev d = kdev(K);
-    k_kry_update_yr<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), d);
-    k_kry_iter_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_update_yr<<<kgrid(g, kb.nz), dim3(BX, BY), 0, s>>>(geot(g), d, kb.zs, kb.hz);
+    k_kry_iter_fin<<<one(kb.nz), dim3(BX, BY), 0, s>>>(d, kb.zs, kb.hz, K.nblocks);
 }
 void kry_fold(hipStream_t s, const Geo &g, const Krylov &K) {
-    k_kry_fold<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K));
+    k_kry_fold<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), kdev(K), 0L, 0L);
 }
 void kry_true_residual(hipStream_t s, const Geo &g, const double *k, const Krylov &K) {
     double H, ih2;
     hk(g, H, ih2);
     KDev d = kdev(K);
-    k_kry_true<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d);
-    k_kry_true_fin<<<1, dim3(BX, BY), 0, s>>>(d, K.nblocks);
+    k_kry_true<<<kgrid(g), dim3(BX, BY), 0, s>>>(geot(g), H, ih2, k, d, 0L, 0L);
+    k_kry_true_fin<<<1, dim3(BX, BY), 0, s>>>(d, 0L, 0L, K.nblocks);
 }
-void kry_restart_from_true(hipStream_t s, const Krylov &K) { k_kry_restart<<<1, 1, 0, s>>>(kdev(K)); }
+void kry_restart_from_true(hipStream_t s, const Krylov &K) { k_kry_restart<<<1, 1, 0, s>>>(kdev(K), 0L, 0L); }
 
 }  // namespace hmgk

@@ -108,10 +108,15 @@ static bool y_space(const hmg_grid *g, const Slot &S) {
     return vcycle_forms_products(g, S) && g->opts.true_res_every == 0;
 }
 
-static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
+// One iteration of slot S, or batched (bz.nz > 1) of slots S .. S + nz - 1:
+// each kernel then runs once for all of them with blockIdx.z selecting the
+// right-hand side, and a right-hand side whose solve has ended sees its own
+// stop flags and returns.
+static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s, Bz bz = {}) {
     const Geo &g0 = g->lev[0].geo;
     const int *stop = &S.K.st->stop;
-    kry_update_p(s, g0, S.K);
+    const Kz kb{bz.zs, (long)g->hist_cap * 8, bz.nz};
+    kry_update_p(s, g0, S.K, kb);
     // v = L p^ and t = L s^ come from the V-cycle's last kernel where it can
     // form them, else from kernels of their own.  Where it can, p^ and s^
     // are not stored either: x advances as x + B y with y += alpha p +
@@ -123,22 +128,22 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     mv.dot = S.K.rh;
     mv.partials = S.K.partials;
     mv.no_z = ym;
-    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop, &mv);
-    if (mv.fused) kry_alpha_fin(s, S.K, mv.blocks);
-    else kry_matvec_alpha(s, g0, g->k0, S.K);
-    kry_update_s(s, g0, S.K);
+    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop, &mv, bz);
+    if (mv.fused) kry_alpha_fin(s, S.K, mv.blocks, kb);
+    else kry_matvec_alpha(s, g0, g->k0, S.K, kb);
+    kry_update_s(s, g0, S.K, kb);
     mv = MvFuse();
     mv.kind = 2;
     mv.out = S.K.t;
     mv.dot = S.K.s;
     mv.partials = S.K.partials;
     mv.no_z = ym;
-    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop, &mv);
-    if (mv.fused) kry_omega_fin(s, S.K, mv.blocks);
-    else kry_matvec_omega(s, g0, g->k0, S.K);
-    if (ym) kry_update_yr(s, g0, S.K);
-    else kry_update_xr(s, g0, S.K);
-    if (g->opts.true_res_every > 0) kry_checkpoint(s, g0, g->k0, S.K);
+    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop, &mv, bz);
+    if (mv.fused) kry_omega_fin(s, S.K, mv.blocks, kb);
+    else kry_matvec_omega(s, g0, g->k0, S.K, kb);
+    if (ym) kry_update_yr(s, g0, S.K, kb);
+    else kry_update_xr(s, g0, S.K, kb);
+    if (g->opts.true_res_every > 0) kry_checkpoint(s, g0, g->k0, S.K, kb);
 }
 
 static hmg_status iteration_graph(hmg_grid *g, Slot &S) {
@@ -169,17 +174,33 @@ static hmg_status launch_iteration(hmg_grid *g, Slot &S, hipStream_t s) {
     return HMG_OK;
 }
 
-static hmg_status ensure_hist(Slot &S, int maxit) {
+// The residual histories of all right-hand sides of a grid: one allocation,
+// the same capacity per slot (so batched kernels find slot z's history at a
+// fixed stride), grown when a solve asks for more iterations.
+static hmg_status ensure_hist(hmg_grid *g, int maxit) {
     int cap = 2 * maxit + 2;
-    if (S.hist_cap >= cap) return HMG_OK;
-    if (S.K.hist) (void)hipFree(S.K.hist);
-    S.K.hist = nullptr;
-    S.hist_cap = 0;
-    HIPCHK(hipMalloc((void **)&S.K.hist, (size_t)cap * 8));
-    S.hist_cap = cap;
-    if (S.iter_graph) {  // the graph captured the old pointer
-        (void)hipGraphExecDestroy(S.iter_graph);
-        S.iter_graph = nullptr;
+    if (g->hist_cap >= cap) return HMG_OK;
+    if (g->hist_all) (void)hipFree(g->hist_all);
+    g->hist_all = nullptr;
+    g->hist_cap = 0;
+    for (Slot &S : g->slot) {
+        S.K.hist = nullptr;
+        S.hist_cap = 0;
+    }
+    HIPCHK(hipMalloc((void **)&g->hist_all, (size_t)cap * 8 * g->nrhs));
+    g->hist_cap = cap;
+    for (int r = 0; r < g->nrhs; ++r) {
+        Slot &S = g->slot[r];
+        S.K.hist = g->hist_all + (size_t)r * cap;
+        S.hist_cap = cap;
+        if (S.iter_graph) {  // the graphs captured the old pointers
+            (void)hipGraphExecDestroy(S.iter_graph);
+            S.iter_graph = nullptr;
+        }
+    }
+    if (g->batch_graph) {
+        (void)hipGraphExecDestroy(g->batch_graph);
+        g->batch_graph = nullptr;
     }
     return HMG_OK;
 }
@@ -203,7 +224,7 @@ struct SolveRun {
 static hmg_status run_begin(SolveRun &R, int x0_given) {
     hmg_grid *g = R.g;
     if (!R.direct) {
-        hmg_status st = ensure_hist(*R.S, R.maxit);
+        hmg_status st = ensure_hist(g, R.maxit);
         if (st) return st;
     }
     kry_init(R.s, g->lev[0].geo, g->k0, R.S->K, x0_given, R.rtol, 2 * R.maxit, g->opts.breakdown_at,
@@ -300,6 +321,109 @@ static hmg_status run_solve(SolveRun &R, int x0_given, hmg_solve_info *info) {
     }
 }
 
+static void run_init(SolveRun &R, hmg_grid *g, Slot *S, hipStream_t s, double rtol, int maxit);
+
+// ---------------------------------------------------------------------------
+// Every right-hand side of a grid in one batched iteration (grid_batchable):
+// the slots are started one by one, then advance together, one launch per
+// kernel for all of them; a slot whose done flag appears is finished alone
+// (FP64 true-residual check, a restart or its result) while the others go on.
+// ---------------------------------------------------------------------------
+struct BatchRun {
+    hmg_grid              *g = nullptr;
+    std::vector<SolveRun>  runs;
+    std::vector<int>       live;      // 1 while the slot's solve runs
+    std::vector<hmg_status> status;
+    hmg_solve_info        *info = nullptr;   // nrhs entries or null
+    int                    inflight = 0, issued = 0, left = 0;
+};
+
+static hmg_status batch_graph(hmg_grid *g) {
+    if (g->batch_graph) return HMG_OK;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed));
+    enqueue_iteration(g, g->slot[0], g->stream, Bz{g->zs, g->nrhs});
+    hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    if (e != hipSuccess) return hmg_fail(HMG_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&g->batch_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        g->batch_graph = nullptr;
+        return hmg_fail(HMG_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    return HMG_OK;
+}
+
+static hmg_status run_begin(SolveRun &R, int x0_given);
+static hmg_status run_finish(SolveRun &R, hmg_solve_info *info);
+static bool run_done(const SolveRun &R);
+
+static hmg_status batch_begin(BatchRun &B, hmg_grid *g, double rtol, int maxit, int x0_given,
+                              hmg_solve_info *info) {
+    B.g = g;
+    B.info = info;
+    B.runs.assign(g->nrhs, SolveRun());
+    B.live.assign(g->nrhs, 1);
+    B.status.assign(g->nrhs, HMG_OK);
+    B.inflight = B.issued = 0;
+    B.left = g->nrhs;
+    for (int r = 0; r < g->nrhs; ++r) {
+        run_init(B.runs[r], g, &g->slot[r], g->stream, rtol, maxit);
+        hmg_status st = run_begin(B.runs[r], x0_given);
+        if (st) return st;
+    }
+    if (g->opts.use_graph) return batch_graph(g);
+    return HMG_OK;
+}
+
+static hmg_status batch_issue(BatchRun &B) {
+    hmg_grid *g = B.g;
+    if (g->opts.use_graph) {
+        HIPCHK(hipGraphLaunch(g->batch_graph, g->stream));
+    } else {
+        enqueue_iteration(g, g->slot[0], g->stream, Bz{g->zs, g->nrhs});
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipEventRecord(g->ev[2 + (B.issued & 1)], g->stream));
+    B.issued++;
+    B.inflight++;
+    return HMG_OK;
+}
+
+// Wait for the older iteration in flight, then finish every slot whose done
+// flag is up (finishing drains the stream).
+static hmg_status batch_observe(BatchRun &B) {
+    hmg_grid *g = B.g;
+    HIPCHK(hipEventSynchronize(g->ev[2 + ((B.issued - B.inflight) & 1)]));
+    B.inflight--;
+    const bool over = B.issued > B.runs[0].maxit + 4;   // the device stops each slot at maxit; guard only
+    for (int r = 0; r < g->nrhs; ++r) {
+        if (!B.live[r] || !(run_done(B.runs[r]) || over)) continue;
+        hmg_status st = run_finish(B.runs[r], B.info ? &B.info[r] : nullptr);
+        B.inflight = 0;   // run_finish synchronised the stream
+        if (st == HMG_PENDING && !over) continue;   // restarted from the true residual
+        if (st == HMG_PENDING) st = HMG_ERR_NOT_CONVERGED;
+        if (st != HMG_OK && st != HMG_ERR_NOT_CONVERGED && st != HMG_ERR_BREAKDOWN) return st;
+        B.status[r] = st;
+        B.live[r] = 0;
+        B.left--;
+    }
+    return HMG_OK;
+}
+
+static hmg_status batch_run(BatchRun &B) {
+    while (B.left > 0) {
+        while (B.inflight < 2) {
+            hmg_status st = batch_issue(B);
+            if (st) return st;
+        }
+        hmg_status st = batch_observe(B);
+        if (st) return st;
+    }
+    HIPCHK(hipStreamSynchronize(B.g->stream));
+    return HMG_OK;
+}
+
 static void run_init(SolveRun &R, hmg_grid *g, Slot *S, hipStream_t s, double rtol, int maxit) {
     R.g = g;
     R.S = S;
@@ -334,6 +458,18 @@ extern "C" hmg_status hmg_solve(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, doub
         for (int r = 0; r < g->nrhs; ++r)
             HIPCHK(hipMemcpy(g->slot[r].K.x, x0 + m0 * r, m0 * 16, hipMemcpyHostToDevice));
     hmg_status worst = HMG_OK;
+    if (grid_batchable(g)) {
+        // every right-hand side in one batched iteration
+        BatchRun B;
+        hmg_status st2 = batch_begin(B, g, rtol, maxit, x0 ? 1 : 0, info);
+        if (st2 == HMG_OK) st2 = batch_run(B);
+        if (st2 != HMG_OK) return st2;
+        for (int r = 0; r < g->nrhs; ++r) {
+            HIPCHK(hipMemcpy(x + m0 * r, g->slot[r].K.x, m0 * 16, hipMemcpyDeviceToHost));
+            if (B.status[r] != HMG_OK && worst == HMG_OK) worst = B.status[r];
+        }
+        return worst;
+    }
     for (int r = 0; r < g->nrhs; ++r) {
         SolveRun R;
         run_init(R, g, &g->slot[r], g->stream, rtol, maxit);
@@ -405,9 +541,10 @@ extern "C" hmg_status hmg_solve_dev_static(hmg_grid *g, int rhs, const void *d_b
 }
 
 // ---------------------------------------------------------------------------
-// batched solves: every right-hand side of every grid advances one iteration
-// per round, each slot on the stream of its grid, so that the work of
-// different instances overlaps on the device.
+// batched solves of many grids: each grid advances every right-hand side one
+// iteration per round on its own stream (one batched launch per kernel where
+// the grid allows it, else its right-hand sides one after another), so that
+// the work of different instances overlaps on the device.
 // ---------------------------------------------------------------------------
 extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *grids, hmg_c64 *const *x,
                                       double rtol, int maxit, hmg_solve_info *const *info) {
@@ -416,15 +553,17 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
     if (st) return st;
     for (int q = 0; q < count; ++q)
         if (!grids[q] || !x[q] || grids[q]->ctx != ctx) return hmg_fail(HMG_ERR_INVALID, "bad grid %d", q);
+    for (int q = 0; q < count; ++q)
+        for (int p = 0; p < q; ++p)
+            if (grids[p] == grids[q]) return hmg_fail(HMG_ERR_INVALID, "grid %d appears twice", q);
     HIPCHK(hipSetDevice(ctx->device));
-    // one pending solve per (grid, rhs); solves of one grid share its events,
-    // so right-hand sides of one grid run one after the other
+    // per grid: a batched run, or one pending solve per right-hand side
     struct Item {
         int q, r;
     };
+    std::vector<char> batched(count, 0);
+    std::vector<BatchRun> bruns(count);
     std::vector<std::deque<Item>> per_grid(count);
-    for (int q = 0; q < count; ++q)
-        for (int r = 0; r < grids[q]->nrhs; ++r) per_grid[q].push_back(Item{q, r});
     std::vector<SolveRun> runs(count);
     std::vector<int> live(count, 0);
     hmg_status worst = HMG_OK;
@@ -439,7 +578,14 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
         return run_begin(runs[q], 0);
     };
     for (int q = 0; q < count; ++q) {
-        st = start_next(q);
+        batched[q] = grid_batchable(grids[q]);
+        if (batched[q]) {
+            st = batch_begin(bruns[q], grids[q], rtol, maxit, 0, info ? info[q] : nullptr);
+            live[q] = 1;
+        } else {
+            for (int r = 0; r < grids[q]->nrhs; ++r) per_grid[q].push_back(Item{q, r});
+            st = start_next(q);
+        }
         if (st) return st;
     }
     for (;;) {
@@ -447,15 +593,35 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
         for (int q = 0; q < count; ++q) {
             if (!live[q]) continue;
             any = true;
-            SolveRun &R = runs[q];
-            if (R.inflight < 2) {
-                st = run_issue(R);
+            if (batched[q]) {
+                while (bruns[q].inflight < 2) {
+                    st = batch_issue(bruns[q]);
+                    if (st) return st;
+                }
+            } else if (runs[q].inflight < 2) {
+                st = run_issue(runs[q]);
                 if (st) return st;
             }
         }
         if (!any) break;
         for (int q = 0; q < count; ++q) {
             if (!live[q]) continue;
+            if (batched[q]) {
+                BatchRun &B = bruns[q];
+                if (B.inflight < 2) continue;
+                st = batch_observe(B);
+                if (st) return st;
+                if (B.left == 0) {
+                    HIPCHK(hipStreamSynchronize(grids[q]->stream));
+                    size_t m0 = (size_t)grids[q]->lev[0].geo.M * grids[q]->lev[0].geo.M;
+                    for (int r = 0; r < grids[q]->nrhs; ++r) {
+                        HIPCHK(hipMemcpy(x[q] + m0 * r, grids[q]->slot[r].K.x, m0 * 16, hipMemcpyDeviceToHost));
+                        if (B.status[r] != HMG_OK && worst == HMG_OK) worst = B.status[r];
+                    }
+                    live[q] = 0;
+                }
+                continue;
+            }
             SolveRun &R = runs[q];
             if (R.inflight < 2) continue;
             int e = (R.issued - 2) & 1;
@@ -469,7 +635,7 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
                 if (sr == HMG_PENDING && !over) continue;
                 if (sr == HMG_PENDING) sr = HMG_ERR_NOT_CONVERGED;
                 if (sr != HMG_OK && sr != HMG_ERR_NOT_CONVERGED && sr != HMG_ERR_BREAKDOWN) return sr;
-                if (sr != HMG_OK) worst = sr;
+                if (sr != HMG_OK && worst == HMG_OK) worst = sr;
                 size_t m0 = (size_t)grids[q]->lev[0].geo.M * grids[q]->lev[0].geo.M;
                 HIPCHK(hipMemcpy(x[q] + m0 * it.r, R.S->K.x, m0 * 16, hipMemcpyDeviceToHost));
                 per_grid[q].pop_front();

@@ -1290,6 +1290,72 @@ def test_batch_equals_individual_solves(ctx, hmg):
             assert np.linalg.norm(r) / np.linalg.norm(it["f"][q]) <= 1e-6
 
 
+def _sources(n, seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in rng.choice(n * n, size=count, replace=False):
+        j, i = divmod(int(q), n)
+        out.append(inputs.point_source(n, i + 1, j + 1))
+    return out
+
+
+@pytest.mark.parametrize("name,n,variant,precision", [("layered1023_hyb_fp64", 1023, 2, 0),
+                                                      ("layered255_sl_mixed", 255, 0, 1),
+                                                      ("layered63_sl_fp64", 63, 0, 0)])
+def test_batched_rhs_equal_single_rhs_solves(ctx, hmg, name, n, variant, precision):
+    """Four right-hand sides of one grid advance together, every kernel of
+    an iteration launched once for all of them (blockIdx.z = right-hand side);
+    each result equals the solve of that right-hand side alone on a
+    single-right-hand-side grid, bit for bit, with the same count, although
+    the right-hand sides finish at different iterations (one is zero and
+    ends at once).  The oracle recomputes every residual."""
+    say(f"case batched rhs {name}")
+    h, k, _ = inputs.layered_problem(n, 2, 2 * math.pi * 40 * (n + 1) / 1024)
+    fs = _sources(n, 11, 3) + [np.zeros((n + 2, n + 2), complex)]
+    g = hmg.Grid(ctx, h, k, np.stack(fs), variant=variant, precision=precision)
+    x, info = g.solve(rtol=1e-6, maxit=600)
+    for q, fq in enumerate(fs):
+        g1 = hmg.Grid(ctx, h, k, fq, variant=variant, precision=precision)
+        x1, i1 = g1.solve(rtol=1e-6, maxit=600)
+        say(f"  rhs {q}: batched {info[q]['iters']} alone {i1[0]['iters']}")
+        assert info[q]["status"] == hmg.OK and i1[0]["status"] == hmg.OK
+        assert info[q]["iters"] == i1[0]["iters"] and info[q]["restarts"] == i1[0]["restarts"]
+        assert np.array_equal(x[q], x1[0])
+        np.testing.assert_array_equal(g.history(q), g1.history(0))
+        g1.close()
+        if q < 3:
+            r = oracle.residual(h, k, 0.0, fq, x[q])
+            assert np.linalg.norm(r) / np.linalg.norm(fq) <= 1e-6
+        else:
+            assert info[q]["iters"] == 0 and not np.any(x[q])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_of_16_instances_by_4_rhs(ctx, hmg, precision):
+    """hmg_solve_batch on 16 constant-k instances of mixed size (n in {63,
+    127, 255}, kh in [0.3, 0.45]), 4 point sources each: every grid runs its
+    four right-hand sides in batched launches, the grids overlap on their own
+    streams, and every result equals the right-hand side solved alone, bit
+    for bit; the oracle recomputes all 64 residuals."""
+    say(f"case batch 16x4 precision={precision}")
+    insts = inputs.batch_instances(seed=7, count=16, nrhs=4, sizes=(63, 127, 255), kh_range=(0.3, 0.45))
+    grids = [hmg.Grid(ctx, it["h"], it["k"], np.stack(it["f"]), precision=precision, variant=hmg.SL)
+             for it in insts]
+    xb, ib = ctx.solve_batch(grids, rtol=1e-6, maxit=600)
+    for q, (it, xs, infos) in enumerate(zip(insts, xb, ib)):
+        for r in range(4):
+            g1 = hmg.Grid(ctx, it["h"], it["k"], it["f"][r], precision=precision, variant=hmg.SL)
+            x1, i1 = g1.solve(rtol=1e-6, maxit=600)
+            g1.close()
+            assert infos[r]["status"] == hmg.OK and infos[r]["rel_res_true"] <= 1e-6, (q, r, infos[r])
+            assert infos[r]["iters"] == i1[0]["iters"], (q, r)
+            assert np.array_equal(xs[r], x1[0]), (q, r)
+            res = oracle.residual(it["h"], it["k"], 0.0, it["f"][r], xs[r])
+            assert np.linalg.norm(res) / np.linalg.norm(it["f"][r]) <= 1e-6
+    for g in grids:
+        g.close()
+
+
 def _serve_all(c, reqs, timeout=120.0):
     import time
     tickets = [c.submit(**r) for r in reqs]
