@@ -101,6 +101,9 @@ def lib():
             "orc_grid_override_level": [P, i, i, d, d, i, i],
             "orc_grid_set_mixed": [P, i, i, i, i],
             "orc_grid_set_mixed_ex": [P, i, i, i, i, i],
+            "orc_grid_set_ray": [P, i],
+            "orc_ray_correct": [P, P, P],
+            "orc_cycles": [P, P, P, d, i, P],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name)
@@ -111,6 +114,8 @@ def lib():
         _lib.orc_bicgstab.restype = i
         _lib.orc_bicgstab_ex.restype = i
         _lib.orc_bicgstab_ex2.restype = i
+        _lib.orc_grid_set_ray.restype = i
+        _lib.orc_cycles.restype = i
         _lib.orc_grid_override_level.restype = i
     return _lib
 
@@ -303,6 +308,39 @@ class Grid:
         lib().orc_grid_set_mixed_ex(self._ptr, int(mode), int(kacz_every), int(block_n),
                                     int(bool(round_io)), int(fp64_levels))
         return self
+
+    def set_ray(self, ray_n):
+        """Ray correction (Section 6.1) on a ray grid of ray_n interior nodes
+        per side (0: off); the grid's preconditioner then is the V-cycle
+        followed by the Galerkin correction over the 8 plane waves times
+        bilinear ray functions."""
+        if lib().orc_grid_set_ray(self._ptr, int(ray_n)) != 0:
+            raise ValueError("singular ray Galerkin matrix")
+        return self
+
+    def ray_correct(self, f, u):
+        """u + P (P^H L P)^{-1} P^H (f - L u)."""
+        f, fp = _c(f, np.complex128)
+        u = np.array(u, dtype=np.complex128, order="C", copy=True)
+        lib().orc_ray_correct(self._ptr, fp, u.ctypes.data_as(ctypes.c_void_p))
+        return u
+
+    def precondition(self, r):
+        """The grid's preconditioner: the V-cycle, then the ray correction of
+        its residual when one is set."""
+        r, rp = _c(r, np.complex128)
+        z = self.vcycle(r)
+        return self.ray_correct(r, z)
+
+    def cycles(self, f, rtol=1e-7, maxit=200, x0=None):
+        """Stationary iteration x <- x + B (f - L x) with the preconditioner as
+        the solver; returns (x, cycles, history of relative residuals)."""
+        f, fp = _c(f, np.complex128)
+        x = np.zeros_like(f) if x0 is None else np.array(x0, np.complex128, order="C")
+        hist = np.zeros(maxit + 1, np.float64)
+        it = lib().orc_cycles(self._ptr, fp, x.ctypes.data_as(ctypes.c_void_p), rtol, maxit,
+                              hist.ctypes.data_as(ctypes.c_void_p))
+        return x, it, hist[: it + 1].copy()
 
     def vcycle(self, f):
         """One V-cycle from zero initial guess: returns B_V f."""

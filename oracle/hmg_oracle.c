@@ -18,6 +18,7 @@
 #include <string.h>
 
 #define IDX(M, i, j) ((size_t)(j) * (size_t)(M) + (size_t)(i))
+#define ORC_PI 3.14159265358979323846
 
 /* ------------------------------------------------------------------------ */
 /* Discrete operator.                                                        */
@@ -322,6 +323,11 @@ struct orc_grid {
     int       mix_round_io;         /* the cycle's input and output are rounded */
     int       mix_t;                /* first level stored in float (finer ones double) */
     double   *kv[ORC_MAX_LEVELS];   /* k used inside the V-cycle (rounded in the precision form) */
+    /* ray correction (Section 6.1): 8 plane waves times bilinear ray functions */
+    int       ray_n;                /* interior nodes per side of the ray grid (0: off) */
+    orc_cplx *ray_P;                /* basis, dense (n+2)^2 x 8 (ray_n+2)^2, row-major   */
+    orc_cplx *ray_A;                /* Galerkin matrix P^H L P, LU-factored              */
+    int      *ray_piv;
 };
 
 void orc_opts_default(orc_opts *o)
@@ -451,6 +457,7 @@ void orc_grid_destroy(orc_grid *g)
         free(g->k[l]); free(g->f[l]); free(g->u[l]); free(g->r[l]);
     }
     free(g->lu); free(g->piv); free(g->exact_lu); free(g->exact_piv);
+    free(g->ray_P); free(g->ray_A); free(g->ray_piv);
     free(g);
 }
 
@@ -678,6 +685,135 @@ void orc_vcycle(orc_grid *g, const orc_cplx *f, orc_cplx *u)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ray correction (Section 6.1).  Near-kernel error is written as a sum of  */
+/* the 8 plane waves exp(i kappa_j . x), kappa_j = k (cos(j pi/4),          */
+/* sin(j pi/4)), j = 1..8, times smooth ray functions a_j.  Reading taken   */
+/* (the construction of the cited wave-ray papers is not available): each   */
+/* a_j is bilinear on a vertex-centred ray grid of ray_n interior nodes per */
+/* side over the same square, so the correction space is spanned by the     */
+/* fine-grid vectors                                                        */
+/*     P e_(j,a) (x) = exp(i kappa_j . x) phi_a(x),                         */
+/* phi_a the bilinear hat of ray-grid node a, and the correction of a        */
+/* residual w is the Galerkin one, P (P^H L P)^{-1} P^H w.  The ray         */
+/* wavenumber is the mean of k over the nodes (k itself for the constant-k  */
+/* problems of the paper).  The basis is stored as a dense matrix here: the */
+/* oracle is for small grids.                                               */
+/* ------------------------------------------------------------------------ */
+
+static double nrm2_plain(size_t m, const orc_cplx *a)
+{
+    double s = 0.0;
+    for (size_t i = 0; i < m; ++i) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return sqrt(s);
+}
+
+/* value of the bilinear hat of ray-grid node (ia, ja) at the point (x, y);
+ * the ray grid spans the same square [0, len]^2 as the fine grid */
+static double ray_hat(int nr, double len, int ia, int ja, double x, double y)
+{
+    double Hr = len / (nr + 1);
+    double wx = 1.0 - fabs(x / Hr - ia), wy = 1.0 - fabs(y / Hr - ja);
+    return (wx > 0.0 && wy > 0.0) ? wx * wy : 0.0;
+}
+
+int orc_grid_set_ray(orc_grid *g, int ray_n)
+{
+    free(g->ray_P); free(g->ray_A); free(g->ray_piv);
+    g->ray_P = NULL; g->ray_A = NULL; g->ray_piv = NULL;
+    g->ray_n = 0;
+    if (ray_n <= 0) return 0;
+    int    n = g->n, M = n + 2, Mr = ray_n + 2;
+    size_t m = (size_t)M * M, K = (size_t)8 * Mr * Mr;
+    double h = g->h;
+    g->ray_P   = malloc(m * K * sizeof(orc_cplx));
+    g->ray_A   = malloc(K * K * sizeof(orc_cplx));
+    g->ray_piv = malloc(K * sizeof(int));
+    double kr = 0.0;
+    for (size_t p = 0; p < m; ++p) kr += g->k[0][p];
+    kr /= (double)m;
+    /* the basis, column (j, a) with j = 1..8 stored as 0..7 */
+    for (size_t p = 0; p < m; ++p) {
+        int    i = (int)(p % M), jj = (int)(p / M);
+        double x = i * h, y = jj * h, kp = kr;
+        for (int d = 0; d < 8; ++d) {
+            double   th = (d + 1) * ORC_PI / 4.0;
+            orc_cplx wave = cexp(I * kp * (cos(th) * x + sin(th) * y));
+            for (int a = 0; a < Mr * Mr; ++a)
+                g->ray_P[p * K + (size_t)d * Mr * Mr + a] =
+                    wave * ray_hat(ray_n, (n + 1) * h, a % Mr, a / Mr, x, y);
+        }
+    }
+    /* P^H L P, column by column */
+    orc_cplx *col = malloc(m * sizeof(orc_cplx)), *lcol = malloc(m * sizeof(orc_cplx));
+    for (size_t c = 0; c < K; ++c) {
+        for (size_t p = 0; p < m; ++p) col[p] = g->ray_P[p * K + c];
+        orc_apply(n, h, g->k[0], 0.0, col, lcol);
+        for (size_t r = 0; r < K; ++r) {
+            orc_cplx acc = 0.0;
+            for (size_t p = 0; p < m; ++p) acc += conj(g->ray_P[p * K + r]) * lcol[p];
+            g->ray_A[r * K + c] = acc;
+        }
+    }
+    free(col); free(lcol);
+    if (orc_lu_factor((int)K, g->ray_A, g->ray_piv) != 0) return -1;
+    g->ray_n = ray_n;
+    return 0;
+}
+
+/* u += P (P^H L P)^{-1} P^H (f - L u) */
+void orc_ray_correct(orc_grid *g, const orc_cplx *f, orc_cplx *u)
+{
+    if (!g->ray_n) return;
+    int    n = g->n, Mr = g->ray_n + 2;
+    size_t m = (size_t)(n + 2) * (n + 2), K = (size_t)8 * Mr * Mr;
+    orc_cplx *w = malloc(m * sizeof(orc_cplx)), *b = malloc(K * sizeof(orc_cplx));
+    orc_residual(n, g->h, g->k[0], 0.0, f, u, w);
+    for (size_t r = 0; r < K; ++r) {
+        orc_cplx acc = 0.0;
+        for (size_t p = 0; p < m; ++p) acc += conj(g->ray_P[p * K + r]) * w[p];
+        b[r] = acc;
+    }
+    orc_lu_solve((int)K, g->ray_A, g->ray_piv, b);
+    for (size_t p = 0; p < m; ++p) {
+        orc_cplx acc = 0.0;
+        for (size_t c = 0; c < K; ++c) acc += g->ray_P[p * K + c] * b[c];
+        u[p] += acc;
+    }
+    free(w); free(b);
+}
+
+/* The preconditioner with the ray correction after the V-cycle:
+ * z = B_V r, then z += C_R (r - L z), i.e. B = B_V + C_R (I - L B_V). */
+static void vcycle_ray(orc_grid *g, const orc_cplx *r, orc_cplx *z)
+{
+    orc_vcycle(g, r, z);
+    orc_ray_correct(g, r, z);
+}
+
+/* Stationary iteration with the (ray-corrected) V-cycle as the solver
+ * (Section 6.1, Table 4): x <- x + B (f - L x) until ||f - L x|| <= rtol
+ * ||f||; returns the number of cycles (maxit if not reached). */
+int orc_cycles(orc_grid *g, const orc_cplx *f, orc_cplx *x, double rtol, int maxit, double *res_hist)
+{
+    int    n = g->n;
+    size_t m = (size_t)(n + 2) * (n + 2);
+    orc_cplx *r = malloc(m * sizeof(orc_cplx)), *z = malloc(m * sizeof(orc_cplx));
+    double bn = nrm2_plain(m, f);
+    if (bn == 0.0) bn = 1.0;
+    int it = 0;
+    for (;; ++it) {
+        orc_residual(n, g->h, g->k[0], 0.0, f, x, r);
+        double rel = nrm2_plain(m, r) / bn;
+        if (res_hist) res_hist[it] = rel;
+        if (rel <= rtol || it >= maxit || !isfinite(rel)) break;
+        vcycle_ray(g, r, z);
+        for (size_t p = 0; p < m; ++p) x[p] += z[p];
+    }
+    free(r); free(z);
+    return it;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Bi-CGSTAB (Section 6): x^0 = 0, right preconditioning (so r is the true  */
 /* residual of the unpreconditioned system), preconditioner applied twice   */
 /* per iteration, iterations counted in halves.  Stop when ||r||/||b|| <=   */
@@ -704,7 +840,7 @@ static double nrm2(size_t m, const orc_cplx *a)
 static void precondition(orc_grid *g, int precond, const orc_cplx *in, orc_cplx *out, size_t m)
 {
     if (precond == ORC_PREC_VCYCLE) {
-        orc_vcycle(g, in, out);
+        vcycle_ray(g, in, out);
     } else if (precond == ORC_PREC_EXACT) {
         if (!g->exact_lu) {
             g->exact_lu  = malloc(m * m * sizeof(orc_cplx));

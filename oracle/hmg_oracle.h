@@ -107,6 +107,17 @@ void      orc_grid_set_mixed(orc_grid *g, int mode, int kacz_every, int block_n,
 void      orc_grid_set_mixed_ex(orc_grid *g, int mode, int kacz_every, int block_n, int round_io,
                                 int fp64_levels);
 
+/* ---- ray correction (Section 6.1): a Galerkin correction whose basis is
+ * each of the 8 plane waves exp(i k (cos(j pi/4) x + sin(j pi/4) y)) times
+ * the bilinear hats of a ray grid with ray_n interior nodes per side; set
+ * ray_n = 0 to switch it off.  With it, the grid's preconditioner is the
+ * V-cycle followed by the correction of its residual. ---- */
+int  orc_grid_set_ray(orc_grid *g, int ray_n);
+void orc_ray_correct(orc_grid *g, const orc_cplx *f, orc_cplx *u);   /* u += C_R (f - L u) */
+/* stationary iteration x <- x + B (f - L x) (Section 6.1, the solver form of
+ * Table 4); returns the number of cycles */
+int  orc_cycles(orc_grid *g, const orc_cplx *f, orc_cplx *x, double rtol, int maxit, double *res_hist);
+
 /* ---- Bi-CGSTAB (Section 6) ---- */
 enum { ORC_PREC_NONE = 0, ORC_PREC_VCYCLE = 1, ORC_PREC_EXACT = 2 };
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 4, ORC_BREAKDOWN = 5 };

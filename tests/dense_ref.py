@@ -296,3 +296,26 @@ class DenseMixedVCycle(DenseVCycle):
             f = round32(f)
         u = self._level(np.asarray(f, np.complex128), 0)
         return round32(u) if rio else u
+
+
+def ray_basis(n, h, k, ray_n):
+    """The ray correction's basis (Section 6.1 ansatz) as a dense matrix,
+    columns (d, a) for direction theta = (d + 1) pi / 4 and ray-grid node a:
+    exp(i kr (cos theta x + sin theta y)) times the bilinear hat of a, kr the
+    mean of k; built from the 1-D hats' tensor product."""
+    M = n + 2
+    Mr = ray_n + 2
+    L = (n + 1) * h
+    Hr = L / (ray_n + 1)
+    x = np.arange(M) * h
+    hat1 = np.maximum(0.0, 1.0 - np.abs(x[:, None] / Hr - np.arange(Mr)[None, :]))   # (M, Mr)
+    kr = float(np.mean(k))
+    cols = []
+    for d in range(8):
+        th = (d + 1) * np.pi / 4
+        wave = np.exp(1j * kr * (np.cos(th) * x[None, :] + np.sin(th) * x[:, None]))   # [j, i]
+        for a in range(Mr * Mr):
+            ia, ja = a % Mr, a // Mr
+            phi = np.outer(hat1[:, ja], hat1[:, ia])      # [j, i]
+            cols.append((wave * phi).reshape(-1))
+    return np.stack(cols, axis=1)
