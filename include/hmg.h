@@ -134,6 +134,17 @@ typedef struct {
                                 values beyond the levels above the bottom
                                 levels are clamped.  0: every level in float
                                 (default)                                      */
+    int    ray_n;            /* Section 6.1 ray correction after every V-cycle of
+                                a solve: 0 off (default); else the ray grid's
+                                interior nodes per side, with (n + 1) a
+                                multiple of ray_n + 1, at least 8 fine
+                                intervals per ray cell and ray_n <= 15 (the
+                                8 (ray_n + 2)^2 ray unknowns are solved
+                                densely).  The preconditioner becomes
+                                z = B_V r; z += P (P^H L P)^{-1} P^H (r - L z),
+                                P the 8 plane waves exp(i kr (cos(j pi/4) x +
+                                sin(j pi/4) y)), j = 1..8, times the bilinear
+                                hats of the ray grid, kr the mean of k          */
     int    reserved[1];
 } hmg_opts;
 
@@ -292,6 +303,12 @@ hmg_status hmg_cancel(hmg_ctx *ctx, uint64_t ticket);
 hmg_status hmg_ctx_set_max_active(hmg_ctx *ctx, int max_active);
 /* Seconds since the context was created (the clock of hmg_result). */
 double     hmg_ctx_clock(const hmg_ctx *ctx);
+
+/* The ray correction of Section 6.1 on caller-owned FP64 finest-level
+ * device fields: z += P (P^H L P)^{-1} P^H (r - L z) (see hmg_opts.ray_n;
+ * HMG_ERR_INVALID when the grid has none).  Uses the grid's first right-
+ * hand side's scratch, so it must not overlap a solve on the same grid. */
+hmg_status hmg_ray_correct_dev(hmg_grid *g, const void *d_r, void *d_z, void *stream);
 
 /* ---- single kernels on one level (parity tests) ----------------------------
  * Each call enqueues one building block of the V-cycle on level `level` of the

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["hmg_kernels.hip", "hmg_fused.hip", "hmg_lex.hip", "hmg_api.hip", "hmg_solve.hip"]
+SOURCES = ["hmg_kernels.hip", "hmg_fused.hip", "hmg_lex.hip", "hmg_ray.hip", "hmg_api.hip", "hmg_solve.hip"]
 OUT = os.path.join(HERE, "libhmg.so")
 ARCH = os.environ.get("HMG_OFFLOAD_ARCH", "gfx950")
 

@@ -206,6 +206,25 @@ struct Carver {
     }
 };
 
+// Ray grid over the finest level (Section 6.1 ray correction): returns the
+// number of ray unknowns 8 (nr + 2)^2, or 0 when ray_n is 0; -1 when n and
+// ray_n do not fit (ray_n <= 7, n + 1 a multiple of ray_n + 1 with cells of
+// at least 8 fine intervals, a multiple of 8).
+static int ray_geometry(int n, int ray_n, RayGeo &R) {
+    if (ray_n == 0) return 0;
+    if (ray_n < 1 || ray_n > 7 || (n + 1) % (ray_n + 1) != 0) return -1;
+    R.N = n + 1;
+    R.M = n + 2;
+    R.nr = ray_n;
+    R.Mr = ray_n + 2;
+    R.Nr = ray_n + 1;
+    R.c = (n + 1) / (ray_n + 1);
+    if (R.c < 8 || R.c % 8 != 0) return -1;
+    R.P = (R.c % 16 == 0) ? 16 : 8;
+    R.np = R.Nr * R.c / R.P + 1;
+    return 8 * R.Mr * R.Mr;
+}
+
 // Lay out (or size, when c.base is null) every device buffer of the grid.
 static void layout(hmg_grid *g, Carver &c) {
     for (int l = 0; l < g->nlev; ++l) {
@@ -222,6 +241,12 @@ static void layout(hmg_grid *g, Carver &c) {
     if (g->lb >= 0 && g->opts.bottom_dense) {
         g->bop_m = g->lev[g->lb].geo.M * g->lev[g->lb].geo.M;
         g->bop = (double *)c.take((size_t)g->bop_m * g->bop_m * 16);
+    }
+    const size_t K = (size_t)g->ray_K;
+    if (K) {
+        g->ray_ex = c.take((size_t)8 * g->ray.M * 16);
+        g->ray_ey = c.take((size_t)8 * g->ray.M * 16);
+        g->ray_Ainv = (double *)c.take(K * K * 16);
     }
     size_t m0 = (size_t)g->lev[0].geo.M * g->lev[0].geo.M;
     int nb = krylov_nblocks(g->lev[0].geo);
@@ -248,6 +273,11 @@ static void layout(hmg_grid *g, Carver &c) {
         S.hist_cap = 0;
         K.hist = nullptr;
         K.st = (KState *)c.take(sizeof(KState));
+        if (g->ray_K) {
+            S.ray_part = (double *)c.take((size_t)g->ray.np * g->ray.np * 64 * 8);
+            S.ray_b = c.take((size_t)g->ray_K * 16);
+            S.ray_a = c.take((size_t)g->ray_K * 16);
+        }
     }
 }
 
@@ -528,7 +558,8 @@ static long slot_stride(const hmg_grid *g) {
             v.push_back((const char *)S.u2[l]);
         }
         const Krylov &K = S.K;
-        const void *kv[] = {K.b, K.x, K.r, K.rh, K.p, K.v, K.s, K.t, K.ph, K.sh, K.partials, K.st};
+        const void *kv[] = {K.b, K.x, K.r, K.rh, K.p, K.v, K.s, K.t, K.ph, K.sh, K.partials, K.st,
+                            S.ray_part, S.ray_b, S.ray_a};
         for (const void *q : kv) v.push_back((const char *)q);
         return v;
     };
@@ -581,6 +612,7 @@ size_t estimate_footprint(int n, const hmg_opts &o) {
     }
     g.nlev = l + 1;
     g.opts = o;
+    g.ray_K = std::max(0, ray_geometry(n, o.ray_n, g.ray));
     g.lb = find_bottom(&g);
     {
         const int top = (g.lb < 0) ? g.nlev : g.lb;
@@ -597,6 +629,60 @@ size_t estimate_footprint(int n, const hmg_opts &o) {
     Carver c;
     layout(&g, c);
     return c.off + 256;
+}
+
+// The ray correction's tables and Galerkin matrix (Section 6.1): the wave
+// factors exp(i kr cos(theta_d) x) and exp(i kr sin(theta_d) y) per
+// direction theta_d = (d + 1) pi / 4 and fine line, kr the mean of k; A =
+// P^H L P built on the device column by column with the correction's own
+// kernels (prolong a unit vector, apply L, restrict), inverted on the host
+// (LU with partial pivoting) and stored row-major for the solve kernel.
+static hmg_status ray_setup(hmg_grid *g) {
+    const RayGeo &R = g->ray;
+    const int K = g->ray_K, M = R.M;
+    const size_t m0 = (size_t)M * M;
+    std::vector<double> k0(m0);
+    HIPCHK(hipMemcpy(k0.data(), g->k0, m0 * 8, hipMemcpyDeviceToHost));
+    double kr = 0.0;
+    for (double v : k0) kr += v;
+    kr /= (double)m0;
+    std::vector<cd> ex((size_t)8 * M), ey((size_t)8 * M);
+    for (int d = 0; d < 8; ++d) {
+        const double th = (d + 1) * M_PI / 4.0, cx = std::cos(th), sy = std::sin(th);
+        for (int i = 0; i < M; ++i) {
+            const double x = i * g->h;
+            ex[(size_t)d * M + i] = std::exp(cd(0.0, kr * cx * x));
+            ey[(size_t)d * M + i] = std::exp(cd(0.0, kr * sy * x));
+        }
+    }
+    HIPCHK(hipMemcpy(g->ray_ex, ex.data(), ex.size() * 16, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g->ray_ey, ey.data(), ey.size() * 16, hipMemcpyHostToDevice));
+    Slot &S = g->slot[0];
+    for (int col = 0; col < K; ++col)
+        launch_ray_column(g->stream, R, g->lev[0].geo.H, g->k0, g->ray_ex, g->ray_ey, S.K.t, S.ray_part, S.ray_b,
+                          S.ray_a, g->ray_Ainv, col);
+    HIPCHK(hipGetLastError());
+    std::vector<cd> A((size_t)K * K), inv;
+    HIPCHK(hipMemcpyAsync(A.data(), g->ray_Ainv, A.size() * 16, hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    if (!invert_dense((size_t)K, A, inv)) return hmg_fail(HMG_ERR_INVALID, "the ray Galerkin matrix is singular");
+    // invert_dense returns the inverse column-major; the solve kernel reads rows
+    for (int r = 0; r < K; ++r)
+        for (int c = 0; c < K; ++c) A[(size_t)r * K + c] = inv[(size_t)c * K + r];
+    HIPCHK(hipMemcpy(g->ray_Ainv, A.data(), A.size() * 16, hipMemcpyHostToDevice));
+    return HMG_OK;
+}
+
+extern "C" hmg_status hmg_ray_correct_dev(hmg_grid *g, const void *d_r, void *d_z, void *stream) {
+    if (!g || !d_r || !d_z) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    if (!g->ray_K) return hmg_fail(HMG_ERR_INVALID, "the grid has no ray correction (ray_n = 0)");
+    if (d_r == d_z) return hmg_fail(HMG_ERR_INVALID, "r and z must not alias");
+    HIPCHK(hipSetDevice(g->ctx->device));
+    Slot &S = g->slot[0];
+    launch_ray_correct(stream ? (hipStream_t)stream : g->stream, g->ray, g->lev[0].geo.H, g->k0, g->ray_ex,
+                       g->ray_ey, g->ray_Ainv, d_r, d_z, S.ray_part, S.ray_b, S.ray_a, nullptr);
+    HIPCHK(hipGetLastError());
+    return HMG_OK;
 }
 
 extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const double *k, const hmg_c64 *f, int nrhs,
@@ -623,6 +709,13 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     if (o.true_res_every < 0) return hmg_fail(HMG_ERR_INVALID, "true_res_every must be >= 0");
     if (o.nan_at < 0) return hmg_fail(HMG_ERR_INVALID, "nan_at must be >= 0");
     if (o.fp64_levels < 0) return hmg_fail(HMG_ERR_INVALID, "fp64_levels must be >= 0");
+    {
+        RayGeo rg{};
+        if (ray_geometry(n, o.ray_n, rg) < 0)
+            return hmg_fail(HMG_ERR_INVALID,
+                            "ray_n = %d: needs 1 <= ray_n <= 7 with n + 1 = %d a multiple of ray_n + 1 and ray cells "
+                            "of a multiple of 8 fine intervals", o.ray_n, n + 1);
+    }
     if (o.fp64_levels > 0 && o.precision == HMG_MIXED && (o.one_pass_kernels || o.relax_order == HMG_ORDER_LEX))
         return hmg_fail(HMG_ERR_INVALID, "fp64_levels needs the fused schedule with coloured sweeps");
     if (!std::isfinite(o.beta) || o.nu_pre < 0 || o.nu_post < 0 || o.kacz_pre < 0 || o.kacz_post < 0 ||
@@ -679,6 +772,7 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     }
 
     plan_paths(g);
+    g->ray_K = ray_geometry(n, o.ray_n, g->ray);
     {
         hmg_status pst = assign_precision(g);
         if (pst != HMG_OK) {
@@ -718,6 +812,7 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
         if (le != hipSuccess) st = hmg_fail(HMG_ERR_DEVICE, "bottom matrix: %s", hipGetErrorString(le));
     }
     if (st == HMG_OK) st = tune_levels(g);
+    if (st == HMG_OK && g->ray_K) st = ray_setup(g);
     if (st != HMG_OK) {
         hmg_grid_destroy(g);
         return st;

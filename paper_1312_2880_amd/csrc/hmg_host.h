@@ -58,6 +58,8 @@ struct Slot {
     void        *f[HMG_MAX_LEVELS] = {};
     void        *u[HMG_MAX_LEVELS] = {};
     void        *u2[HMG_MAX_LEVELS] = {};  // second buffer (tiled kernels never update in place)
+    double      *ray_part = nullptr;       // ray correction: patch records, then b and a (K each)
+    void        *ray_b = nullptr, *ray_a = nullptr;
     hmgk::Krylov K{};
     int          hist_cap = 0;
     int          last_halfsteps = -1;   // of the last finished solve
@@ -83,6 +85,10 @@ struct hmg_grid {
     size_t     bytes = 0;
     hipStream_t stream = nullptr;
     long       zs = 0;            // bytes between the buffers of consecutive slots (0: not uniform)
+    int        ray_K = 0;         // ray correction: unknowns 8 (nr + 2)^2 (0: off)
+    hmgk::RayGeo ray{};
+    void      *ray_ex = nullptr, *ray_ey = nullptr;   // wave tables, 8 x M complex each
+    double    *ray_Ainv = nullptr;                    // (P^H L P)^{-1}, row-major K x K complex
     double    *hist_all = nullptr;  // residual histories of every slot, hist_cap doubles each
     int        hist_cap = 0;
     hipGraphExec_t batch_graph = nullptr;  // one iteration of every right-hand side, batched

@@ -163,6 +163,28 @@ void launch_bottom_basis(Prec p, hipStream_t s, const BottomDesc &d, double *B);
 void launch_dense_apply(Prec p, bool io64, hipStream_t s, const double *B, int m, const void *f, void *u,
                         const int *skip, Bz bz = {});
 
+// ---- ray correction (hmg_ray.hip) -------------------------------------------
+// Geometry of the ray grid over the finest level: fine N = n + 1 intervals and
+// M = n + 2 nodes per side; ray grid nr interior nodes, Mr = nr + 2 nodes and
+// Nr = nr + 1 cells of c fine intervals per side; the restriction works on
+// patches of P x P fine nodes (P divides c), np per side.
+struct RayGeo {
+    int N, M;
+    int nr, Mr, Nr;
+    int c;
+    int P;
+    int np;
+};
+// z += P A^{-1} P^H (r - L z) on FP64 finest-level fields (k: FP64 finest k;
+// ex, ey: the wave tables; part, b, a: the correction's scratch)
+void launch_ray_correct(hipStream_t s, const RayGeo &R, double H, const double *k, const void *ex, const void *ey,
+                        const double *Ainv, const void *r, void *z, double *part, void *b, void *a,
+                        const int *skip, Bz bz = {});
+// column col of A = P^H L P (row-major K x K) into A; zfine: a scratch FP64
+// finest-level field
+void launch_ray_column(hipStream_t s, const RayGeo &R, double H, const double *k, const void *ex, const void *ey,
+                       void *zfine, double *part, void *b, void *a, void *A, int col);
+
 // ---- Bi-CGSTAB (FP64, finest level, L = A_0) -------------------------------
 // Every launcher runs on one slot K, or batched (kb.nz > 1) on the kb.nz
 // slots from K on: their vectors, partial sums and scalars kb.zs bytes apart,

@@ -105,7 +105,15 @@ extern "C" double hmg_ctx_clock(const hmg_ctx *ctx) { return ctx ? hmg_now() - c
 // up kernel forms the Krylov products, unless periodic true-residual checks
 // need the current x every iteration.
 static bool y_space(const hmg_grid *g, const Slot &S) {
-    return vcycle_forms_products(g, S) && g->opts.true_res_every == 0;
+    return vcycle_forms_products(g, S) && g->opts.true_res_every == 0 && g->ray_K == 0;
+}
+
+// The Section 6.1 ray correction of the preconditioner's result z for the
+// input r (when the grid has one): z += C_R (r - L z).
+static void ray_after(hmg_grid *g, Slot &S, const double *r, double *z, hipStream_t s, const int *skip, Bz bz) {
+    if (!g->ray_K) return;
+    launch_ray_correct(s, g->ray, g->lev[0].geo.H, g->k0, g->ray_ex, g->ray_ey, g->ray_Ainv, r, z, S.ray_part,
+                       S.ray_b, S.ray_a, skip, bz);
 }
 
 // One iteration of slot S, or batched (bz.nz > 1) of slots S .. S + nz - 1:
@@ -128,7 +136,10 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s, Bz bz = {}) {
     mv.dot = S.K.rh;
     mv.partials = S.K.partials;
     mv.no_z = ym;
-    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop, &mv, bz);
+    // with the ray correction the V-cycle's result changes after it, so the
+    // products come from kernels of their own
+    enqueue_vcycle(g, S, S.K.p, S.K.ph, s, stop, g->ray_K ? nullptr : &mv, bz);
+    ray_after(g, S, S.K.p, S.K.ph, s, stop, bz);
     if (mv.fused) kry_alpha_fin(s, S.K, mv.blocks, kb);
     else kry_matvec_alpha(s, g0, g->k0, S.K, kb);
     kry_update_s(s, g0, S.K, kb);
@@ -138,7 +149,8 @@ static void enqueue_iteration(hmg_grid *g, Slot &S, hipStream_t s, Bz bz = {}) {
     mv.dot = S.K.s;
     mv.partials = S.K.partials;
     mv.no_z = ym;
-    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop, &mv, bz);
+    enqueue_vcycle(g, S, S.K.s, S.K.sh, s, stop, g->ray_K ? nullptr : &mv, bz);
+    ray_after(g, S, S.K.s, S.K.sh, s, stop, bz);
     if (mv.fused) kry_omega_fin(s, S.K, mv.blocks, kb);
     else kry_matvec_omega(s, g0, g->k0, S.K, kb);
     if (ym) kry_update_yr(s, g0, S.K, kb);

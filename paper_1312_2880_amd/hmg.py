@@ -52,7 +52,7 @@ class Opts(ctypes.Structure):
                 ("bottom_dense", ctypes.c_int), ("relax_order", ctypes.c_int),
                 ("breakdown_at", ctypes.c_int), ("true_res_every", ctypes.c_int),
                 ("nan_at", ctypes.c_int), ("fp64_levels", ctypes.c_int),
-                ("reserved", ctypes.c_int * 1)]
+                ("ray_n", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 class Plan(ctypes.Structure):
@@ -102,6 +102,7 @@ _SIGS = {
     "hmg_solve": (_i, [P, P, P, _d, _i, P]),
     "hmg_solve_dev": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
     "hmg_solve_dev_static": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
+    "hmg_ray_correct_dev": (_i, [P, P, P, P]),
     "hmg_solve_batch": (_i, [P, _i, P, P, _d, _i, P]),
     "hmg_submit": (_i, [P, P, P]),
     "hmg_poll": (_i, [P, ctypes.c_uint64, P, P]),
@@ -352,6 +353,11 @@ class Grid:
                                        ctypes.byref(info), _stream(stream))
         _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
         return _info_dict(info)
+
+    def ray_correct_dev(self, d_r, d_z, stream=None):
+        """z += P (P^H L P)^{-1} P^H (r - L z) on FP64 finest-level fields
+        (Section 6.1 ray correction; the grid needs ray_n > 0)."""
+        _check(_lib.hmg_ray_correct_dev(self._h, _dptr(d_r), _dptr(d_z), _stream(stream)))
 
     # ---- single building blocks on device fields (level precision) ----
     def op_apply(self, level, sigma, d_u, d_out, stream=None):
