@@ -256,6 +256,17 @@ hmg_status hmg_solve_dev_static(hmg_grid *g, int rhs, const void *d_b, void *d_x
                                 int x0_given, double rtol, int maxit,
                                 hmg_solve_info *info, void *stream);
 
+/* The preconditioner as a stationary solver (Section 6.1, the form of its
+ * ray-correction table: no Krylov outer iteration):
+ *     x <- x + B (f - L x),   B the V-cycle (followed by the ray correction
+ *                             when opts.ray_n > 0),
+ * for every right-hand side from x0 (host, NULL = 0) until ||f - L x|| <=
+ * rtol ||f|| or maxit cycles.  x: nrhs fields (may equal x0); info: nrhs
+ * entries, iters = the number of cycles.  HMG_ERR_NOT_CONVERGED when maxit
+ * is reached or the residual stops being finite (x holds the last iterate). */
+hmg_status hmg_solve_cycles(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, double rtol, int maxit,
+                            hmg_solve_info *info);
+
 /* Relative residuals ||r|| / ||b|| of the last solve of right-hand side
  * `rhs`, one per half iteration (entry 0 = the initial residual): copies up
  * to cap values into out and returns how many the solve produced (-1 on

@@ -553,6 +553,67 @@ extern "C" hmg_status hmg_solve_dev_static(hmg_grid *g, int rhs, const void *d_b
 }
 
 // ---------------------------------------------------------------------------
+// stationary cycles: x <- x + B (f - L x)
+// ---------------------------------------------------------------------------
+extern "C" hmg_status hmg_solve_cycles(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, double rtol, int maxit,
+                                       hmg_solve_info *info) {
+    if (!g || !x) return hmg_fail(HMG_ERR_INVALID, "null argument");
+    hmg_status st = check_solve_args(rtol, maxit);
+    if (st) return st;
+    HIPCHK(hipSetDevice(g->ctx->device));
+    st = ensure_hist(g, maxit);
+    if (st) return st;
+    const Geo &g0 = g->lev[0].geo;
+    const size_t m0 = (size_t)g0.M * g0.M;
+    hipStream_t s = g->stream;
+    hmg_status worst = HMG_OK;
+    for (int r = 0; r < g->nrhs; ++r) {
+        Slot &S = g->slot[r];
+        const double t0 = hmg_now();
+        if (x0) HIPCHK(hipMemcpy(S.K.x, x0 + m0 * r, m0 * 16, hipMemcpyHostToDevice));
+        kry_init(s, g0, g->k0, S.K, x0 ? 1 : 0, rtol, 2 * maxit, 0);   // ||b||, x (0 unless x0)
+        std::vector<double> hist;
+        int cyc = 0;
+        hmg_status res = HMG_ERR_NOT_CONVERGED;
+        double rel = -1.0;
+        for (;; ++cyc) {
+            kry_true_residual(s, g0, g->k0, S.K);   // r = b - L x and ||r|| / ||b||
+            HIPCHK(hipMemcpyAsync(g->host_state, S.K.st, sizeof(KState), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            rel = g->host_state->true_rel;
+            hist.push_back(rel);
+            if (rel <= rtol) {
+                res = HMG_OK;
+                break;
+            }
+            if (cyc >= maxit || !std::isfinite(rel)) break;
+            enqueue_vcycle(g, S, S.K.r, S.K.sh, s, nullptr);
+            ray_after(g, S, S.K.r, S.K.sh, s, nullptr, Bz{});
+            kry_fold(s, g0, S.K);   // x += z
+            HIPCHK(hipGetLastError());
+        }
+        if (S.K.hist && !hist.empty())
+            HIPCHK(hipMemcpy(S.K.hist, hist.data(), std::min(hist.size(), (size_t)S.hist_cap) * 8,
+                             hipMemcpyHostToDevice));
+        S.last_halfsteps = (int)hist.size() - 1;
+        if (info) {
+            hmg_solve_info &I = info[r];
+            I = hmg_solve_info{};
+            I.iters = cyc;
+            I.halfsteps = cyc;
+            I.rel_res_true = rel;
+            I.status = res;
+            I.levels = g->nlev;
+            I.seconds = hmg_now() - t0;
+            I.flags = (g->plan.kHmax[0] > 0.2 * M_PI) ? HMG_INFO_KH_ABOVE_GUIDE : 0;
+        }
+        HIPCHK(hipMemcpy(x + m0 * r, S.K.x, m0 * 16, hipMemcpyDeviceToHost));
+        if (res != HMG_OK && worst == HMG_OK) worst = res;
+    }
+    return worst;
+}
+
+// ---------------------------------------------------------------------------
 // batched solves of many grids: each grid advances every right-hand side one
 // iteration per round on its own stream (one batched launch per kernel where
 // the grid allows it, else its right-hand sides one after another), so that

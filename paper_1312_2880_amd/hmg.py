@@ -103,6 +103,7 @@ _SIGS = {
     "hmg_solve_dev": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
     "hmg_solve_dev_static": (_i, [P, _i, P, P, _i, _d, _i, P, P]),
     "hmg_ray_correct_dev": (_i, [P, P, P, P]),
+    "hmg_solve_cycles": (_i, [P, P, P, _d, _i, P]),
     "hmg_solve_batch": (_i, [P, _i, P, P, _d, _i, P]),
     "hmg_submit": (_i, [P, P, P]),
     "hmg_poll": (_i, [P, ctypes.c_uint64, P, P]),
@@ -327,6 +328,19 @@ class Grid:
         infos = (SolveInfo * self.nrhs)()
         st = _lib.hmg_solve(self._h, x0p, _ptr(x), rtol, maxit, infos)
         _check(st, (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN))
+        return x, [_info_dict(i) for i in infos]
+
+    def solve_cycles(self, rtol=1e-7, maxit=200, x0=None):
+        """The preconditioner as a stationary solver, x <- x + B (f - L x)
+        (Section 6.1); info["iters"] counts cycles."""
+        x = np.zeros((self.nrhs, self.n + 2, self.n + 2), np.complex128)
+        x0p = None
+        if x0 is not None:
+            x0 = np.ascontiguousarray(np.broadcast_to(x0, x.shape), np.complex128)
+            x0p = _ptr(x0)
+        infos = (SolveInfo * self.nrhs)()
+        st = _lib.hmg_solve_cycles(self._h, x0p, _ptr(x), rtol, maxit, infos)
+        _check(st, (OK, ERR_NOT_CONVERGED))
         return x, [_info_dict(i) for i in infos]
 
     def history(self, rhs=0):

@@ -1364,6 +1364,29 @@ def test_ray_corrected_hlm_solve_matches_oracle(ctx, hmg, k0, n, ray_n):
     assert info0[0]["iters"] > 50 * info[0]["iters"] or info0[0]["status"] != hmg.OK
 
 
+@pytest.mark.parametrize("k0,n,ray_n", [(20, 63, 3), (40, 127, 7)])
+def test_ray_corrected_cycles_match_oracle(ctx, hmg, k0, n, ray_n):
+    """The ray-corrected HLM-V cycle as a stationary solver (Section 6.1, the
+    solver form of its ray-correction table): the same number of cycles to a
+    1e-7 reduction and the same residual history as the oracle; without the
+    correction the cycle diverges on both sides."""
+    say(f"case ray cycles k={k0}")
+    h = 1.0 / (n + 1)
+    k = np.full((n + 2, n + 2), float(k0))
+    f = inputs.centre_source(n)
+    nc = 3 if n == 63 else 7
+    g = hmg.Grid(ctx, h, k, f, variant=hmg.HLM, coarsest_n=nc, ray_n=ray_n)
+    x, info = g.solve_cycles(rtol=1e-7, maxit=60)
+    og = oracle.Grid(h, k, variant=oracle.HLM, coarsest_n=nc).set_ray(ray_n)
+    _, cyc, hist = og.cycles(f, rtol=1e-7, maxit=60)
+    say(f"  gpu {info[0]['iters']} cycles, oracle {cyc}")
+    assert info[0]["status"] == hmg.OK and info[0]["iters"] == cyc
+    np.testing.assert_allclose(g.history(0), hist, rtol=1e-6)
+    g0 = hmg.Grid(ctx, h, k, f, variant=hmg.HLM, coarsest_n=nc)
+    _, info0 = g0.solve_cycles(rtol=1e-7, maxit=30)
+    assert info0[0]["status"] == hmg.ERR_NOT_CONVERGED and g0.history(0)[-1] > 1.0
+
+
 def test_ray_corrected_batched_rhs(ctx, hmg):
     """The ray correction inside batched right-hand sides equals solving each
     alone, bit for bit."""
