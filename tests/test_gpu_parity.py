@@ -851,6 +851,36 @@ def test_forced_breakdown_restart_matches_oracle(ctx, hmg, K):
     g.close()
 
 
+def test_history_drift_point63_slv(ctx, hmg):
+    """Where the GPU and oracle residual histories part on the 63^2 SL-V
+    point-source problem (the smoke problem): both take the same number of
+    restarts; for the first six iterations (12 half steps) the relative gap
+    between the two histories stays at rounding level (below 1e-10); it
+    first exceeds 1e-6 at half step 27 of 85 (measured; asserted: not
+    before 20).  The growth is not smooth: at half step 21 the gap jumps
+    from 2e-11 to 1.4e-8 while the residual itself changes by 30 %, the
+    amplification of rounding by Bi-CGSTAB's scalars (alpha = rho / (rh, v)
+    with a small denominator), after which the counts end 2.5 apart (42
+    against 44.5)."""
+    say("case history drift point63 SL-V")
+    h, k, f = inputs.workload_const_point(63)
+    g = hmg.Grid(ctx, h, k, f, variant=hmg.SL)
+    _, info = g.solve(rtol=1e-6, maxit=300)
+    og = oracle.Grid(h, k, variant=oracle.SL)
+    _, ref = og.bicgstab(f, rtol=1e-6, maxit=300, history=True)
+    a, b = g.history(0), ref["history"]
+    m = min(len(a), len(b))
+    gap = np.abs(a[:m] - b[:m]) / b[:m]
+    over = np.nonzero(gap > 1e-6)[0]
+    first = int(over[0]) if len(over) else m
+    say(f"  gpu {info[0]['iters']} ({info[0]['restarts']} restarts), oracle {ref['iters']} "
+        f"({ref['restarts']}); first half step with gap > 1e-6: {first} of {m}")
+    say("  gaps: " + " ".join(f"{x:.1e}" for x in gap[: min(first + 2, m)]))
+    assert info[0]["restarts"] == ref["restarts"]
+    assert np.all(gap[:13] <= 1e-10), gap[:13]
+    assert first >= 20
+
+
 def test_single_level_exact_preconditioner_half_step(ctx, hmg):
     """n = coarsest_n: the V-cycle is the exact solve of L (HYB), so
     Bi-CGSTAB stops after half an iteration."""
@@ -975,7 +1005,9 @@ def test_vcycle_full_size_layered_2047(ctx, hmg):
     r = inputs.random_field(2047, 8)
     want = og.vcycle(r)
     g = hmg.Grid(ctx, h, k, f, variant=2)
-    assert rel(g.vcycle(r), want) <= 1e-11
+    e = rel(g.vcycle(r), want)
+    say(f"  V-cycle rel err at 2047^2: {e:.3e}")
+    assert e <= 1e-12
     g.close()
     gm = hmg.Grid(ctx, h, k, f, variant=2, precision=hmg.MIXED)
     assert rel(gm.vcycle(r), want) <= 1e-4
@@ -993,7 +1025,9 @@ def test_vcycle_and_solve_layered_4095(ctx, hmg):
     g = hmg.Grid(ctx, h, k, f, variant=0)
     assert [p["n"] for p in g.plan()] == [p["n"] for p in og.plan()]
     r = inputs.random_field(n, 9)
-    assert rel(g.vcycle(r), og.vcycle(r)) <= 1e-11
+    e = rel(g.vcycle(r), og.vcycle(r))
+    say(f"  V-cycle rel err at 4095^2: {e:.3e}")
+    assert e <= 1e-12
     _, info = g.solve(rtol=1e-6, maxit=4)
     _, ref = og.bicgstab(f, rtol=1e-6, maxit=4, history=True)
     np.testing.assert_allclose(g.history(0)[:8], ref["history"][:8], rtol=1e-7)
