@@ -285,7 +285,12 @@ hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *grids,
  * order while the sum of admitted device footprints stays within the context
  * budget, advances every admitted solve one Bi-CGSTAB iteration per step
  * (work of different requests overlaps on the device), and retires finished
- * ones.  poll returns HMG_PENDING until the request is finished, then its
+ * ones.  A retired request's grid stays allocated, idle, for the next
+ * request of the same n and options, which is loaded into it in place (no
+ * device allocation); idle grids of other sizes are freed, oldest first,
+ * only when a request would not fit the budget otherwise.  The server polls
+ * its requests' events without blocking, so a finished request is retired
+ * while slower ones run on.  poll returns HMG_PENDING until the request is finished, then its
  * final status and (if x_out != NULL) copies the solution; the ticket is
  * released by the first non-pending poll. */
 typedef struct {
@@ -304,6 +309,7 @@ typedef struct {
     double rel_res_true;
     double t_arrive, t_admit, t_done;   /* seconds on the context's clock     */
     size_t footprint_bytes;
+    int    reused;     /* 1: served on the kept grid of an earlier request    */
 } hmg_result;
 
 hmg_status hmg_submit(hmg_ctx *ctx, const hmg_request *req, uint64_t *ticket);

@@ -231,7 +231,10 @@ static void layout(hmg_grid *g, Carver &c) {
         Level &L = g->lev[l];
         size_t m = (size_t)L.geo.M * L.geo.M;
         L.k = c.take(m * (L.prec == P64 ? 8 : 4));
-        L.ktab = (L.mode == LM_KACZ_TILED || L.mode == LM_KACZ_LEVEL) ? (double *)c.take(m * 16) : nullptr;
+        // a row table on every level, so that the layout depends on n and
+        // the options only (a request server reuses the memory of a grid
+        // for the next problem of the same size, whose plan may differ)
+        L.ktab = (double *)c.take(m * 16);
     }
     g->k0 = (double *)c.take((size_t)g->lev[0].geo.M * g->lev[0].geo.M * 8);
     int mc = g->lev[g->nlev - 1].geo.M;
@@ -685,13 +688,8 @@ extern "C" hmg_status hmg_ray_correct_dev(hmg_grid *g, const void *d_r, void *d_
     return HMG_OK;
 }
 
-extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const double *k, const hmg_c64 *f, int nrhs,
-                                      const hmg_opts *opts, hmg_grid **out) {
-    if (!ctx || !out) return hmg_fail(HMG_ERR_INVALID, "null context or output handle");
-    *out = nullptr;
-    hmg_opts o;
-    if (opts) o = *opts;
-    else hmg_opts_default(&o);
+// Checks of the problem and options (the conventions of hmg_grid_create).
+static hmg_status check_problem(const hmg_opts &o, int n, double h, const double *k, const hmg_c64 *f, int nrhs) {
     if (o.coarsest_n < 1 || o.coarsest_n > 31)
         return hmg_fail(HMG_ERR_INVALID, "coarsest_n must be in [1, 31], got %d", o.coarsest_n);
     if (!valid_hierarchy(n, o.coarsest_n))
@@ -728,17 +726,20 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
         for (size_t q = 0; q < m0 * (size_t)nrhs; ++q)
             if (!std::isfinite(f[q].re) || !std::isfinite(f[q].im))
                 return hmg_fail(HMG_ERR_INVALID, "f must be finite");
+    return HMG_OK;
+}
 
-    hmg_grid *g = new hmg_grid();
-    g->ctx = ctx;
-    g->opts = o;
-    g->n = n;
+// The host side of a problem on a grid whose n, nrhs and options are set:
+// the hierarchy of k (injection), the level plan (Section 5), the level
+// schedule and precisions, and the coarsest inverse.
+static hmg_status plan_problem(hmg_grid *g, double h, const double *k, std::vector<std::vector<double>> &kl,
+                               std::vector<cd> &inv) {
+    const hmg_opts &o = g->opts;
+    const int n = g->n;
+    const size_t m0 = (size_t)(n + 2) * (n + 2);
     g->h = h;
-    g->nrhs = nrhs;
-    g->prec = (o.precision == HMG_MIXED) ? P32 : P64;
-
-    // hierarchy: halve the interval count until n <= coarsest_n, k by injection
-    std::vector<std::vector<double>> kl;
+    g->plan = hmg_plan{};
+    kl.clear();
     kl.emplace_back(k, k + m0);
     int nl = n;
     double H = h;
@@ -763,42 +764,25 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
         g->lev[l].geo = make_geo(g->plan.n[l], g->plan.H[l]);
     }
     int lc = g->nlev - 1;
-    std::vector<cd> A, inv;
+    std::vector<cd> A;
     dense_operator(g->plan.n[lc], g->plan.H[lc], kl[lc].data(), g->plan.sigma_relax[lc], A);
     size_t mc = (size_t)(g->plan.n[lc] + 2) * (g->plan.n[lc] + 2);
-    if (!invert_dense(mc, A, inv)) {
-        delete g;
-        return hmg_fail(HMG_ERR_INVALID, "coarsest operator is singular");
-    }
-
+    if (!invert_dense(mc, A, inv)) return hmg_fail(HMG_ERR_INVALID, "coarsest operator is singular");
     plan_paths(g);
     g->ray_K = ray_geometry(n, o.ray_n, g->ray);
-    {
-        hmg_status pst = assign_precision(g);
-        if (pst != HMG_OK) {
-            delete g;
-            return pst;
-        }
-    }
-    g->slot.resize(nrhs);
-    Carver sizer;
-    layout(g, sizer);
-    g->bytes = sizer.off + 256;
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e == hipSuccess) e = hipMalloc((void **)&g->mem, g->bytes);
-    if (e != hipSuccess) {
-        delete g;
-        return hmg_fail(HMG_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", sizer.off, hipGetErrorString(e));
-    }
-    Carver c;
-    c.base = g->mem;
-    layout(g, c);
+    return assign_precision(g);
+}
+
+// The device side of a problem on an allocated grid: k on every level, the
+// coarsest inverse, the right-hand sides, the Kaczmarz row tables, the
+// bottom-cycle matrix, the tuned tile configurations and the ray correction.
+static hmg_status load_problem(hmg_grid *g, const std::vector<std::vector<double>> &kl, const std::vector<cd> &inv,
+                               const hmg_c64 *f) {
     bottom_desc(g);
-    g->zs = slot_stride(g);
-    hmg_status st = grid_init_device(g, kl, inv, f);
+    hmg_status st = grid_upload(g, kl, inv, f);
     if (st == HMG_OK) {
         for (int l = 0; l < g->nlev; ++l)
-            if (g->lev[l].ktab)
+            if (g->lev[l].mode == LM_KACZ_TILED || g->lev[l].mode == LM_KACZ_LEVEL)
                 launch_kacz_table(g->lev[l].prec, g->stream, g->lev[l].geo, g->lev[l].k, g->plan.sigma_relax[l],
                                   g->lev[l].ktab);
         hipError_t le = hipGetLastError();
@@ -813,6 +797,48 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     }
     if (st == HMG_OK) st = tune_levels(g);
     if (st == HMG_OK && g->ray_K) st = ray_setup(g);
+    return st;
+}
+
+extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const double *k, const hmg_c64 *f, int nrhs,
+                                      const hmg_opts *opts, hmg_grid **out) {
+    if (!ctx || !out) return hmg_fail(HMG_ERR_INVALID, "null context or output handle");
+    *out = nullptr;
+    hmg_opts o;
+    if (opts) o = *opts;
+    else hmg_opts_default(&o);
+    hmg_status st = check_problem(o, n, h, k, f, nrhs);
+    if (st) return st;
+
+    hmg_grid *g = new hmg_grid();
+    g->ctx = ctx;
+    g->opts = o;
+    g->n = n;
+    g->nrhs = nrhs;
+    g->prec = (o.precision == HMG_MIXED) ? P32 : P64;
+    std::vector<std::vector<double>> kl;
+    std::vector<cd> inv;
+    st = plan_problem(g, h, k, kl, inv);
+    if (st) {
+        delete g;
+        return st;
+    }
+    g->slot.resize(nrhs);
+    Carver sizer;
+    layout(g, sizer);
+    g->bytes = sizer.off + 256;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&g->mem, g->bytes);
+    if (e != hipSuccess) {
+        delete g;
+        return hmg_fail(HMG_ERR_NOMEM, "hipMalloc of %zu bytes failed: %s", sizer.off, hipGetErrorString(e));
+    }
+    Carver c;
+    c.base = g->mem;
+    layout(g, c);
+    g->zs = slot_stride(g);
+    st = grid_init_device(g);
+    if (st == HMG_OK) st = load_problem(g, kl, inv, f);
     if (st != HMG_OK) {
         hmg_grid_destroy(g);
         return st;
@@ -821,8 +847,38 @@ extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const doubl
     return HMG_OK;
 }
 
-hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> &kl, const std::vector<cd> &inv,
-                            const hmg_c64 *f) {
+// Whether grid g can take a problem of size n with options o in place.
+bool grid_reusable(const hmg_grid *g, int n, int nrhs, const hmg_opts &o) {
+    return g && g->n == n && g->nrhs == nrhs && std::memcmp(&g->opts, &o, sizeof o) == 0;
+}
+
+// Put a new problem (spacing h, wavenumber k, right-hand sides f) on a grid
+// of the same size and options, in its memory: no device allocation (the
+// layout depends on n and the options only).  The level plan, tables,
+// coarsest inverse and bottom matrix are rebuilt and captured graphs dropped.
+hmg_status grid_reload(hmg_grid *g, double h, const double *k, const hmg_c64 *f) {
+    hmg_status st = check_problem(g->opts, g->n, h, k, f, g->nrhs);
+    if (st) return st;
+    HIPCHK(hipSetDevice(g->ctx->device));
+    HIPCHK(hipStreamSynchronize(g->stream));
+    for (Slot &S : g->slot) {
+        if (S.iter_graph) (void)hipGraphExecDestroy(S.iter_graph);
+        S.iter_graph = nullptr;
+        S.last_halfsteps = -1;
+    }
+    if (g->batch_graph) (void)hipGraphExecDestroy(g->batch_graph);
+    g->batch_graph = nullptr;
+    // the buffers stay where they are: the layout is a function of n and
+    // the options (level precisions included), which match
+    std::vector<std::vector<double>> kl;
+    std::vector<cd> inv;
+    st = plan_problem(g, h, k, kl, inv);
+    if (st) return st;
+    return load_problem(g, kl, inv, f);
+}
+
+// Per-grid runtime objects: the stream, pinned status records and events.
+hmg_status grid_init_device(hmg_grid *g) {
     HIPCHK(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void **)&g->host_state, 4 * sizeof(KState), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void **)&g->done_host, (size_t)g->nrhs * sizeof(int), hipHostMallocDefault));
@@ -831,6 +887,13 @@ hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> 
         g->slot[s].K.done_host = &g->done_host[s];
     }
     for (int q = 0; q < 4; ++q) HIPCHK(hipEventCreateWithFlags(&g->ev[q], hipEventDisableTiming));
+    return HMG_OK;
+}
+
+// k of every level in its precision, the FP64 finest k, the coarsest inverse
+// and the right-hand sides (zero where f is null).
+hmg_status grid_upload(hmg_grid *g, const std::vector<std::vector<double>> &kl, const std::vector<cd> &inv,
+                       const hmg_c64 *f) {
     for (int l = 0; l < g->nlev; ++l) {
         size_t m = kl[l].size();
         if (g->lev[l].prec == P64) {

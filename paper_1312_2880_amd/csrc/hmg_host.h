@@ -99,8 +99,14 @@ struct hmg_grid {
 
 hmg_status hmg_fail(hmg_status st, const char *fmt, ...);
 double     hmg_now();
-hmg_status grid_init_device(hmg_grid *g, const std::vector<std::vector<double>> &kl,
-                            const std::vector<std::complex<double>> &inv, const hmg_c64 *f);
+hmg_status grid_init_device(hmg_grid *g);
+hmg_status grid_upload(hmg_grid *g, const std::vector<std::vector<double>> &kl,
+                       const std::vector<std::complex<double>> &inv, const hmg_c64 *f);
+// Whether grid g can take a problem of size n with nrhs right-hand sides and
+// options o in its memory, and the call that puts one there (no device
+// allocation; plans, tables, coarsest inverse and bottom matrix rebuilt).
+bool       grid_reusable(const hmg_grid *g, int n, int nrhs, const hmg_opts &o);
+hmg_status grid_reload(hmg_grid *g, double h, const double *k, const hmg_c64 *f);
 size_t     estimate_footprint(int n, const hmg_opts &o);
 // A Bi-CGSTAB product the finest up kernel may take over: out = L z with the
 // partial sums of kind 1 ((dot, out)) or kind 2 ((out, dot), (out, out)) in

@@ -29,6 +29,12 @@ using namespace hmgk;
 // context
 // ---------------------------------------------------------------------------
 struct Request;
+// An idle grid kept by the request server for the next request of its size
+// and options, with the device bytes it holds.
+struct PoolEntry {
+    hmg_grid *grid = nullptr;
+    size_t    bytes = 0;
+};
 struct ServerState {
     std::mutex              mu;
     std::condition_variable cv;
@@ -36,10 +42,12 @@ struct ServerState {
     bool                    running = false;
     bool                    quit = false;
     uint64_t                next_ticket = 1;
-    size_t                  used = 0;
+    size_t                  used = 0;       // footprints of the admitted requests
+    size_t                  pooled = 0;     // bytes of the idle grids in pool
     int                     max_active = 0;
     std::deque<Request *>   queue;
     std::vector<Request *>  active;
+    std::vector<PoolEntry>  pool;           // oldest first
     std::map<uint64_t, Request *> all;
 };
 
@@ -734,26 +742,38 @@ struct Request {
     int                 maxit = 100;
     size_t              footprint = 0;
     int                 state = 0;      // 0 queued, 1 active, 2 finished
-    bool                cancel = false;
+    std::atomic<bool>   cancel{false};
     hmg_grid           *grid = nullptr;
+    bool                reuse = false;  // grid comes from the pool (reload in place)
     SolveRun            run;
     hmg_result          result{};
     std::vector<hmg_c64> x;
 };
 
+// Finish request q: copy its solution, return its grid to the pool (its
+// memory stays allocated for the next request of that size), publish the
+// result.
 static void retire(hmg_ctx *ctx, Request *q, hmg_status status) {
     ServerState &S = *ctx->server;
+    hmg_grid *keep = nullptr;
     if (q->grid) {
-        if (status == HMG_OK || status == HMG_ERR_NOT_CONVERGED) {
+        if (status == HMG_OK || status == HMG_ERR_NOT_CONVERGED || status == HMG_ERR_BREAKDOWN) {
             size_t m0 = (size_t)(q->n + 2) * (q->n + 2);
             q->x.resize(m0);
             if (hipMemcpy(q->x.data(), q->grid->slot[0].K.x, m0 * 16, hipMemcpyDeviceToHost) != hipSuccess)
                 status = HMG_ERR_DEVICE;
+        } else {
+            (void)hipStreamSynchronize(q->grid->stream);
         }
-        hmg_grid_destroy(q->grid);
+        if (status == HMG_ERR_DEVICE) hmg_grid_destroy(q->grid);
+        else keep = q->grid;
         q->grid = nullptr;
     }
     std::lock_guard<std::mutex> lk(S.mu);
+    if (keep) {
+        S.pool.push_back(PoolEntry{keep, q->footprint});
+        S.pooled += q->footprint;
+    }
     if (q->state == 1) S.used -= q->footprint;
     q->state = 2;
     q->result.status = status;
@@ -768,13 +788,14 @@ static void server_loop(hmg_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     for (;;) {
         std::vector<Request *> admit;
+        std::vector<hmg_grid *> evict;
         {
             std::unique_lock<std::mutex> lk(S.mu);
             S.cv.wait(lk, [&] { return S.quit || !S.queue.empty() || !S.active.empty(); });
             if (S.quit) return;
             while (!S.queue.empty()) {
                 Request *q = S.queue.front();
-                if (q->cancel) {
+                if (q->cancel.load()) {
                     S.queue.pop_front();
                     q->state = 2;
                     q->result.status = HMG_ERR_CANCELLED;
@@ -782,18 +803,50 @@ static void server_loop(hmg_ctx *ctx) {
                     S.cv.notify_all();
                     continue;
                 }
-                bool fits = S.used + q->footprint <= ctx->budget;
                 bool slot_ok = S.max_active <= 0 || (int)(S.active.size() + admit.size()) < S.max_active;
-                if (!fits || !slot_ok) break;
+                if (!slot_ok) break;
+                // an idle grid of the request's size and options takes it in
+                // place; idle grids of other sizes give their memory back
+                // (oldest first) only when the budget needs it
+                int match = -1;
+                for (int e = (int)S.pool.size() - 1; e >= 0; --e)
+                    if (grid_reusable(S.pool[e].grid, q->n, 1, q->opts)) {
+                        match = e;
+                        break;
+                    }
+                const size_t mine = match >= 0 ? S.pool[match].bytes : 0;
+                size_t avail = ctx->budget - std::min(ctx->budget, S.used + S.pooled - mine);
+                for (int e = 0; e < (int)S.pool.size() && q->footprint > avail;) {
+                    if (e == match) {
+                        ++e;
+                        continue;
+                    }
+                    avail += S.pool[e].bytes;
+                    S.pooled -= S.pool[e].bytes;
+                    evict.push_back(S.pool[e].grid);
+                    S.pool.erase(S.pool.begin() + e);
+                    if (match > e) --match;
+                }
+                if (q->footprint > avail) break;
                 S.queue.pop_front();
+                if (match >= 0) {
+                    q->grid = S.pool[match].grid;
+                    q->reuse = true;
+                    S.pooled -= S.pool[match].bytes;
+                    S.pool.erase(S.pool.begin() + match);
+                }
                 S.used += q->footprint;
                 q->state = 1;
+                q->result.reused = q->reuse ? 1 : 0;
                 q->result.t_admit = hmg_now() - ctx->t0;
                 admit.push_back(q);
             }
         }
+        for (hmg_grid *g : evict) hmg_grid_destroy(g);
         for (Request *q : admit) {
-            hmg_status st = hmg_grid_create(ctx, q->n, q->h, q->k.data(), q->f.data(), 1, &q->opts, &q->grid);
+            hmg_status st;
+            if (q->reuse) st = grid_reload(q->grid, q->h, q->k.data(), q->f.data());
+            else st = hmg_grid_create(ctx, q->n, q->h, q->k.data(), q->f.data(), 1, &q->opts, &q->grid);
             if (st == HMG_OK) {
                 run_init(q->run, q->grid, &q->grid->slot[0], q->grid->stream, q->rtol, q->maxit);
                 st = run_begin(q->run, 0);
@@ -816,22 +869,28 @@ static void server_loop(hmg_ctx *ctx) {
             std::lock_guard<std::mutex> lk(S.mu);
             act = S.active;
         }
-        // queue up to two iterations per active solve, then observe the
-        // oldest one of each; the streams of different requests overlap
+        // keep up to two iterations of every active solve queued (the streams
+        // of different requests overlap on the device), then look at each
+        // one's oldest iteration without blocking: a finished request does
+        // not wait behind a slow one
         for (Request *q : act)
-            while (q->run.inflight < 2 && !q->cancel) {
+            while (q->run.inflight < 2 && !q->cancel.load()) {
                 if (run_issue(q->run) != HMG_OK) break;
             }
+        bool progress = false;
         for (Request *q : act) {
             SolveRun &R = q->run;
-            if (q->cancel) {
-                (void)hipStreamSynchronize(R.s);
+            if (q->cancel.load()) {
                 retire(ctx, q, HMG_ERR_CANCELLED);
+                progress = true;
                 continue;
             }
             if (R.inflight == 0) continue;
             int e = (R.issued - R.inflight) & 1;
-            if (hipEventSynchronize(R.ev[e]) != hipSuccess) {
+            hipError_t qe = hipEventQuery(R.ev[e]);
+            if (qe == hipErrorNotReady) continue;
+            progress = true;
+            if (qe != hipSuccess) {
                 retire(ctx, q, HMG_ERR_DEVICE);
                 continue;
             }
@@ -847,6 +906,7 @@ static void server_loop(hmg_ctx *ctx) {
                 retire(ctx, q, st);
             }
         }
+        if (!progress && !act.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
@@ -873,6 +933,9 @@ static void server_stop(hmg_ctx *ctx) {
         if (q->grid) hmg_grid_destroy(q->grid);
         delete q;
     }
+    for (PoolEntry &e : S.pool) hmg_grid_destroy(e.grid);
+    S.pool.clear();
+    S.pooled = 0;
     S.all.clear();
     S.queue.clear();
     S.active.clear();
@@ -940,7 +1003,7 @@ extern "C" hmg_status hmg_cancel(hmg_ctx *ctx, uint64_t ticket) {
     std::lock_guard<std::mutex> lk(S.mu);
     auto it = S.all.find(ticket);
     if (it == S.all.end()) return hmg_fail(HMG_ERR_UNKNOWN_TICKET, "unknown ticket");
-    it->second->cancel = true;
+    it->second->cancel.store(true);
     S.cv.notify_all();
     return HMG_OK;
 }

@@ -82,7 +82,7 @@ class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("t_arrive", ctypes.c_double),
                 ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("footprint_bytes", ctypes.c_size_t)]
+                ("footprint_bytes", ctypes.c_size_t), ("reused", ctypes.c_int)]
 
 
 P = ctypes.c_void_p
@@ -233,7 +233,7 @@ class Context:
         st = _lib.hmg_poll(self._h, ticket, None if x is None else _ptr(x), ctypes.byref(res))
         if st == PENDING:
             return None
-        if st not in (OK, ERR_NOT_CONVERGED, ERR_CANCELLED):
+        if st not in (OK, ERR_NOT_CONVERGED, ERR_CANCELLED, ERR_BREAKDOWN):
             _check(st)
         out = {f: getattr(res, f) for f, _ in Result._fields_}
         out["status"] = st

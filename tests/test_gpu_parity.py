@@ -1603,3 +1603,46 @@ def test_serving_admission_budget_and_cancel(hmg):
     assert done[t1][1]["status"] == hmg.OK
     assert done[t2][1]["status"] in (hmg.ERR_CANCELLED, hmg.OK)
     c.close()
+
+
+def test_serving_reuses_idle_grids_in_place(hmg):
+    """A request of the same size and options as a finished one runs on that
+    request's grid, loaded in place, with the bits of a fresh grid; an idle
+    grid is freed when a request of another size needs its memory."""
+    say("case serving pool reuse")
+    reqs = _requests()
+    c = hmg.Context(0)
+    c.set_max_active(1)
+    first = _serve_all(c, reqs)
+    again = _serve_all(c, reqs)
+    for (x1, r1), (x2, r2) in zip(first, again):
+        assert r1["status"] == hmg.OK and r2["status"] == hmg.OK
+        assert r2["reused"] == 1
+        assert np.array_equal(x1, x2) and r1["iters"] == r2["iters"]
+    # the second 127^2 request of the first pass found the first one's grid
+    assert [r["reused"] for _, r in first] == [0, 0, 0, 1]
+    c.close()
+    probe = hmg.Context(0)
+    sizes = {}
+    for q in (0, 2):
+        g = hmg.Grid(probe, reqs[q]["h"], reqs[q]["k"], reqs[q]["f"], precision=1, variant=0)
+        sizes[q] = g.footprint + 64 * 1024     # the grid and the request's history
+        g.close()
+    probe.close()
+    # room for the 255^2 and the 63^2 request side by side: the second 255^2
+    # request waits for the first and takes its grid
+    c = hmg.Context(0, budget_bytes=sizes[2] + sizes[0])
+    out = _serve_all(c, [reqs[2], reqs[0], reqs[2]])
+    assert all(r["status"] == hmg.OK for _, r in out)
+    assert [r["reused"] for _, r in out] == [0, 0, 1]
+    assert np.array_equal(out[0][0], out[2][0]) and out[0][1]["iters"] == out[2][1]["iters"]
+    c.close()
+    # room for one of them at a time: the 63^2 request frees the idle 255^2
+    # grid to fit, so the second 255^2 request gets a new one
+    c = hmg.Context(0, budget_bytes=sizes[2] + sizes[0] // 2)
+    out = _serve_all(c, [reqs[2], reqs[0], reqs[2]])
+    assert all(r["status"] == hmg.OK for _, r in out)
+    assert [r["reused"] for _, r in out] == [0, 0, 0]
+    assert out[1][1]["t_admit"] >= out[0][1]["t_done"] and out[2][1]["t_admit"] >= out[1][1]["t_done"]
+    assert np.array_equal(out[0][0], out[2][0])
+    c.close()
