@@ -448,7 +448,7 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
                                                 const double (&kr)[2][GsBigMV::NS],
                                                 const C<double> *__restrict__ ec, C<double> *__restrict__ uo,
                                                 C<double> *__restrict__ mvo, const C<double> *__restrict__ dot,
-                                                double *partials) {
+                                                double *partials, const double *__restrict__ k) {
     using TL = GsBigMV;
     auto prolong = [&](int i, int j) { return prolong_at(ec, i, j, Mc); };
     auto outside = [&](int i, int j) { return !IN && (i < 0 || j < 0 || i > N || j > N); };
@@ -484,8 +484,7 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
     }
     __syncthreads();
     // red on tile + 2; then black on tile + 1 (black reads red only, so it
-    // writes its own cells in place) with the tile nodes of both colours ->
-    // uo in the same phase (whole cache lines leave together)
+    // writes its own cells in place)
 #pragma unroll
     for (int m = 0; m < TL::NS; ++m) {
         int lx, ly;
@@ -498,58 +497,62 @@ __device__ __forceinline__ void gs_up_mv_phases(C<double> *U, int tid, int ox, i
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int m = 0; m < TL::NS; ++m) {
-            int lx, ly;
-            bool own = TL::owned(tid, c, m, lx, ly);
-            int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, c) || outside(i, j)) continue;
-            int l = ly * TL::LW + lx;
-            C<double> v;
-            if (c == 1) {
-                Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
-                v = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
-                U[l] = v;
-            } else {
-                v = U[l];
-            }
-            if (uo && TL::ring(lx, ly, 0)) uo[(size_t)j * M + i] = v;
-        }
+    for (int m = 0; m < TL::NS; ++m) {
+        int lx, ly;
+        bool own = TL::owned(tid, 1, m, lx, ly);
+        int i = ox + lx, j = oy + ly;
+        if (!own || !TL::ring(lx, ly, 1) || outside(i, j)) continue;
+        int l = ly * TL::LW + lx;
+        Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[1][m], sa);
+        U[l] = cdiv(csub(fr[1][m], offsum_z(r, U, l, TL::LW)), r.dre, r.dim);
+    }
     __syncthreads();
-    // the product with L (sigma = 0) on the tile and the partial sums
+    // Results leave in row order: thread q of a pass takes tile node (q % X,
+    // q / X), so each wave stores whole 1 KB row segments (a colour-ordered
+    // store would leave every cache line in two halves, from two passes).
+    constexpr int NT_TILE = TL::X * TL::Y, NP = (NT_TILE + GNT - 1) / GNT;
+    if (uo) {
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+            const int q = tid + GNT * m;
+            const int tx = q % TL::X, ty = q / TL::X, i = ox + TL::RH + tx, j = oy + TL::RH + ty;
+            if (q >= NT_TILE || (!IN && (i > N || j > N))) continue;
+            uo[(size_t)j * M + i] = U[(ty + TL::RH) * TL::LW + tx + TL::RH];
+        }
+    }
+    // the product with L (sigma = 0) on the tile, in the same row order, with
+    // the block's partial sums; k of the tile is read again (in row order,
+    // from the cache: the tile's own k was loaded at the start) instead of
+    // keeping colour-ordered values in registers across the pass
     constexpr int NV = KIND == 1 ? 2 : 3;
-    // the slot positions are recomputed from an opaque copy of tid: reusing
-    // the ones of the sweeps would keep them live across every phase and
-    // push the kernel past 128 VGPRs (three waves per SIMD instead of four)
+    // an opaque copy of tid: reusing the positions of the sweeps would keep
+    // them live across every phase and push the kernel past 128 VGPRs (three
+    // waves per SIMD instead of four)
     int tid2 = tid;
     asm volatile("" : "+v"(tid2));
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-        for (int m = 0; m < TL::NS; ++m) {
-            int lx, ly;
-            bool own = TL::owned(tid2, c, m, lx, ly);
-            int i = ox + lx, j = oy + ly;
-            if (!own || !TL::ring(lx, ly, 0) || outside(i, j)) continue;
-            const int l = ly * TL::LW + lx;
-            const size_t p = (size_t)j * M + i;
-            const Row<double> r = row_in<IN>(i, j, N, H, ih2, kr[c][m], 0.0);
-            const C<double> w = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, TL::LW));
-            mvo[p] = w;
-            const C<double> a = dot[p];
-            if (KIND == 1) {
-                acc[0] += a.x * w.x + a.y * w.y;      // conj(rh) v
-                acc[NV - 1] += a.x * w.y - a.y * w.x;
-            } else {
-                acc[0] += w.x * a.x + w.y * a.y;      // conj(t) s
-                acc[1] += w.x * a.y - w.y * a.x;
-                acc[NV - 1] += w.x * w.x + w.y * w.y;
-            }
+    for (int m = 0; m < NP; ++m) {
+        const int q = tid2 + GNT * m;
+        const int tx = q % TL::X, ty = q / TL::X, i = ox + TL::RH + tx, j = oy + TL::RH + ty;
+        if (q >= NT_TILE || (!IN && (i > N || j > N))) continue;
+        const size_t p = (size_t)j * M + i;
+        const int l = (ty + TL::RH) * TL::LW + tx + TL::RH;
+        const Row<double> r = row_in<IN>(i, j, N, H, ih2, k[p], 0.0);
+        const C<double> v = cadd(cmul(cmk(r.dre, r.dim), U[l]), offsum_z(r, U, l, TL::LW));
+        mvo[p] = v;
+        const C<double> a = dot[p];
+        if (KIND == 1) {
+            acc[0] += a.x * v.x + a.y * v.y;      // conj(rh) v
+            acc[NV - 1] += a.x * v.y - a.y * v.x;
+        } else {
+            acc[0] += v.x * a.x + v.y * a.y;      // conj(t) s
+            acc[1] += v.x * a.y - v.y * a.x;
+            acc[NV - 1] += v.x * v.x + v.y * v.y;
         }
+    }
     block_partials<NV>(acc, partials);
 }
 
@@ -579,9 +582,9 @@ __global__ __launch_bounds__(GNT) void k_gs_up_mv(GeoT g, double H, double ih2, 
     gs_load<TL>(tid, ox, oy, N, M, f, k, fr, kr);
     if (flag_set(sk)) return;
     if (ox >= 1 && oy >= 1 && ox + TL::LW <= N && oy + TL::LH <= N)
-        gs_up_mv_phases<true, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials);
+        gs_up_mv_phases<true, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials, k);
     else
-        gs_up_mv_phases<false, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials);
+        gs_up_mv_phases<false, KIND>(U, tid, ox, oy, N, M, Mc, H, ih2, sa, fr, kr, ec, uo, mvo, dot, partials, k);
 }
 
 template <class TL, typename T, typename TF, typename TU>

@@ -2,11 +2,16 @@
 
     python -m paper_1312_2880_amd.profiling stats  <kernel_stats.csv> [title]
     python -m paper_1312_2880_amd.profiling trace  <kernel_trace.csv> [top]
+    python -m paper_1312_2880_amd.profiling phases <kernel_trace.csv> <kernel> [marker]
     python -m paper_1312_2880_amd.profiling traffic <fetch_dir> <write_dir> <kernel> <bytes> <hash> [key]
 
 `stats` prints a short markdown table (kernel, calls, average and total
 time, share).  `trace` splits the same time by kernel and launch shape
-(grid size: one row per level of the hierarchy), with the median duration.  `traffic` combines two `--pmc` runs (FETCH_SIZE, then
+(grid size: one row per level of the hierarchy), with the median duration.
+`phases` splits the launches of one kernel (name prefix) at the end of the
+last launch of a marker kernel (default the Krylov kernels, k_kry_): in a
+bench.py run the launches before it belong to the timed solves, the ones
+after it to the per-kernel timing that follows them.  `traffic` combines two `--pmc` runs (FETCH_SIZE, then
 WRITE_SIZE; KiB per dispatch) of `bench.py --traffic-probe`: the probe runs
 the dominant kernel on cold buffers and a plain device-to-device copy of a
 known size; each counter is scaled by (copy bytes / what the counter reads for
@@ -53,6 +58,27 @@ def kernel_trace(path: str, top: int = 20) -> str:
     return "\n".join(out)
 
 
+def kernel_phases(path: str, kernel: str, marker: str = "k_kry_") -> str:
+    rows = list(csv.DictReader(open(path)))
+
+    def short(r):
+        return r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hmgk::", "")
+
+    end = max(int(r["End_Timestamp"]) for r in rows if short(r).startswith(marker))
+    groups = {}
+    for r in rows:
+        name = short(r)
+        if not name.startswith(kernel):
+            continue
+        phase = "solves" if int(r["Start_Timestamp"]) < end else "kernel timing"
+        groups.setdefault((name, phase), []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = ["| kernel | phase | launches | mean (us) | median (us) |", "|---|---|---:|---:|---:|"]
+    for (name, phase), v in sorted(groups.items()):
+        v.sort()
+        out.append(f"| `{name}` | {phase} | {len(v)} | {sum(v) / len(v) / 1e3:.2f} | {v[len(v) // 2] / 1e3:.2f} |")
+    return "\n".join(out)
+
+
 def _counter_rows(d: str):
     files = glob.glob(os.path.join(d, "**", "*counter_collection*.csv"), recursive=True)
     rows = []
@@ -95,6 +121,8 @@ if __name__ == "__main__":
         print(kernel_stats(sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ""))
     elif len(sys.argv) >= 3 and sys.argv[1] == "trace":
         print(kernel_trace(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 20))
+    elif len(sys.argv) >= 4 and sys.argv[1] == "phases":
+        print(kernel_phases(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else "k_kry_"))
     elif len(sys.argv) >= 7 and sys.argv[1] == "traffic":
         key = sys.argv[7] if len(sys.argv) > 7 else f"{sys.argv[4]}:fp64"
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]),
