@@ -104,6 +104,8 @@ def lib():
             "orc_grid_set_ray": [P, i],
             "orc_ray_correct": [P, P, P],
             "orc_cycles": [P, P, P, d, i, P],
+            "orc_grid_set_study": [P, i, i],
+            "orc_set_boundary_row_scale": [i],
         }
         for name, args in sig.items():
             fn = getattr(_lib, name)
@@ -118,6 +120,13 @@ def lib():
         _lib.orc_cycles.restype = i
         _lib.orc_grid_override_level.restype = i
     return _lib
+
+
+def set_boundary_row_scale(on: bool) -> None:
+    """Study reading (process-wide): rows with b boundary faces multiplied by
+    2^-b in every operator of the oracle; the caller scales right-hand sides
+    the same way.  Leave it off outside a study."""
+    lib().orc_set_boundary_row_scale(int(bool(on)))
 
 
 def set_threads(n: int) -> None:
@@ -307,6 +316,14 @@ class Grid:
         returns double fields."""
         lib().orc_grid_set_mixed_ex(self._ptr, int(mode), int(kacz_every), int(block_n),
                                     int(bool(round_io)), int(fp64_levels))
+        return self
+
+    def set_study(self, fw_transpose=False, coarse_sweeps=0):
+        """Readings of Section 5 other than the default, for iteration-count
+        studies: ``fw_transpose`` restricts with P^T / 4 (no mirror folding at
+        the boundary); ``coarse_sweeps`` > 0 replaces the coarsest dense solve
+        by that many Gauss-Seidel sweeps from zero."""
+        lib().orc_grid_set_study(self._ptr, int(bool(fw_transpose)), int(coarse_sweeps))
         return self
 
     def set_ray(self, ray_n):

@@ -42,6 +42,13 @@ typedef struct {
     double   w[4];     /* neighbour weights / h^2: left, right, down, up */
 } orc_row;
 
+/* Study switch (not the default reading): rows with b boundary faces
+ * multiplied by 2^-b, which makes the matrix complex symmetric (the doubled
+ * inward weight is halved).  The solution of A x = f is that of the scaled
+ * system with the scaled right-hand side. */
+static int g_row_scale = 0;
+void orc_set_boundary_row_scale(int on) { g_row_scale = on ? 1 : 0; }
+
 static orc_row row_of(int N, double h, double kp, double sigma, int i, int j)
 {
     orc_row r;
@@ -52,6 +59,11 @@ static orc_row row_of(int N, double h, double kp, double sigma, int i, int j)
     r.w[1] = (i < N) ? ((i == 0) ? 2.0 : 1.0) * ih2 : 0.0;   /* (i+1, j) */
     r.w[2] = (j > 0) ? ((j == N) ? 2.0 : 1.0) * ih2 : 0.0;   /* (i, j-1) */
     r.w[3] = (j < N) ? ((j == 0) ? 2.0 : 1.0) * ih2 : 0.0;   /* (i, j+1) */
+    if (g_row_scale && b) {
+        double sc = ldexp(1.0, -b);
+        r.app *= sc;
+        for (int q = 0; q < 4; ++q) r.w[q] *= sc;
+    }
     return r;
 }
 
@@ -328,6 +340,9 @@ struct orc_grid {
     orc_cplx *ray_P;                /* basis, dense (n+2)^2 x 8 (ray_n+2)^2, row-major   */
     orc_cplx *ray_A;                /* Galerkin matrix P^H L P, LU-factored              */
     int      *ray_piv;
+    /* study switches (readings other than the default; see orc_grid_set_study) */
+    int       st_fw_transpose;
+    int       st_coarse_sweeps;
 };
 
 void orc_opts_default(orc_opts *o)
@@ -352,10 +367,13 @@ void orc_opts_default(orc_opts *o)
  *   2. kacz_band and the span meets [1.25/sqrt2, 1.25*sqrt2): four pre- and
  *      four post-sweeps of the normal-equation relaxation, on M (SL, HYB) or
  *      L (HLM);
- *   3. HYB only, span meets [0.625/sqrt2, 0.625*sqrt2): Gauss-Seidel on M;
- *   4. guard (not in the paper): when the relaxation operator would be L and
- *      an interior node has |k^2 H^2 - 4| < 1 (vanishing GS pivot), use the
- *      normal-equation relaxation on L, 4 + 4;
+ *   3. kacz_band and the span meets [1.25*sqrt2, 2.5): the same relaxation
+ *      on the variant's operator (M for SL, L for HLM and HYB): Section 4
+ *      finds Gauss-Seidel good only for kH up to about 0.625 and from about
+ *      2.5 on, and takes the normal equation where it fails (between them
+ *      lie 1.25 and the span up to 2.5; Gauss-Seidel on L also loses its
+ *      pivot at kH = 2);
+ *   4. HYB only, span meets [0.625/sqrt2, 0.625*sqrt2): Gauss-Seidel on M;
  *   5. otherwise Gauss-Seidel, on M for SL and on L for HLM and HYB.
  * The residual operator (role (B)) is M for SL and L for HLM and HYB. */
 static void classify(orc_grid *g, int l, int last)
@@ -364,14 +382,11 @@ static void classify(orc_grid *g, int l, int last)
     orc_plan       *pl = &g->plan;
     int    n = pl->n[l], M = n + 2;
     double H = pl->H[l], lo = 1e300, hi = -1e300, beta = o->beta;
-    int    pivot_guard = 0;
     for (int j = 0; j < M; ++j)
         for (int i = 0; i < M; ++i) {
             double kh = g->k[l][IDX(M, i, j)] * H;
             if (kh < lo) lo = kh;
             if (kh > hi) hi = kh;
-            if (i > 0 && j > 0 && i < M - 1 && j < M - 1 && fabs(kh * kh - 4.0) < 1.0)
-                pivot_guard = 1;
         }
     pl->kHmin[l] = lo;
     pl->kHmax[l] = hi;
@@ -384,10 +399,12 @@ static void classify(orc_grid *g, int l, int last)
     }
     double s2 = sqrt(2.0);
     int in_kacz = (hi >= 1.25 / s2) && (lo < 1.25 * s2);
+    int in_wide = (hi >= 1.25 * s2) && (lo < 2.5);
     int in_gsm  = (hi >= 0.625 / s2) && (lo < 0.625 * s2);
-    if (o->kacz_band && in_kacz) {
+    double sig = (o->variant == ORC_SL) ? beta : 0.0;
+    if (o->kacz_band && (in_kacz || in_wide)) {
         pl->smoother[l]    = ORC_SM_KACZ;
-        pl->sigma_relax[l] = (o->variant == ORC_HLM) ? 0.0 : beta;
+        pl->sigma_relax[l] = in_kacz ? ((o->variant == ORC_HLM) ? 0.0 : beta) : sig;
         pl->pre[l] = o->kacz_pre;
         pl->post[l] = o->kacz_post;
         return;
@@ -397,14 +414,6 @@ static void classify(orc_grid *g, int l, int last)
         pl->sigma_relax[l] = beta;
         pl->pre[l] = o->nu_pre;
         pl->post[l] = o->nu_post;
-        return;
-    }
-    double sig = (o->variant == ORC_SL) ? beta : 0.0;
-    if (sig == 0.0 && pivot_guard) {
-        pl->smoother[l]    = ORC_SM_KACZ;
-        pl->sigma_relax[l] = 0.0;
-        pl->pre[l] = o->kacz_pre;
-        pl->post[l] = o->kacz_post;
         return;
     }
     pl->smoother[l]    = ORC_SM_GS;
@@ -463,6 +472,12 @@ void orc_grid_destroy(orc_grid *g)
 
 void orc_grid_plan(const orc_grid *g, orc_plan *p) { *p = g->plan; }
 
+void orc_grid_set_study(orc_grid *g, int fw_transpose, int coarse_sweeps)
+{
+    g->st_fw_transpose  = fw_transpose ? 1 : 0;
+    g->st_coarse_sweeps = coarse_sweeps > 0 ? coarse_sweeps : 0;
+}
+
 /* Replace the classification of one non-coarsest level (tests and studies of
  * other plans); the coarsest factor is rebuilt when its shift changes. */
 int orc_grid_override_level(orc_grid *g, int l, int smoother, double sigma_relax,
@@ -505,12 +520,42 @@ static void relax(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u, int sweeps
 /* V-cycle with zero initial guess on each level:
  *   u = 0; relax (role A); r = f - B u (role B); f_c = R r;
  *   e_c = V(l+1, f_c); u += P e_c; relax (role A). */
+/* Study reading of the restriction: R = P^T / 4, the transpose of the
+ * bilinear interpolation (weights 4, 2, 1 over 16 around the coarse node),
+ * with the weights of fine nodes outside the grid dropped rather than
+ * folded back (row sums below one at the boundary). */
+static void restrict_transpose(int n, const orc_cplx *r, orc_cplx *fc)
+{
+    int N = n + 1, M = n + 2, Nc = N / 2, Mc = Nc + 1;
+    for (int cj = 0; cj <= Nc; ++cj)
+        for (int ci = 0; ci <= Nc; ++ci) {
+            orc_cplx s = 0.0;
+            for (int e = -1; e <= 1; ++e)
+                for (int d = -1; d <= 1; ++d) {
+                    int i = 2 * ci + d, j = 2 * cj + e;
+                    if (i < 0 || j < 0 || i > N || j > N) continue;
+                    s += (double)((2 - abs(d)) * (2 - abs(e))) * r[IDX(M, i, j)];
+                }
+            fc[IDX(Mc, ci, cj)] = s / 16.0;
+        }
+}
+
 static void vcycle_level(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u)
 {
     const orc_plan *pl = &g->plan;
     int    n = pl->n[l];
     size_t m = (size_t)(n + 2) * (n + 2);
     if (pl->smoother[l] == ORC_SM_LU) {
+        if (g->st_coarse_sweeps > 0) {
+            /* study reading: a few Gauss-Seidel sweeps from zero on the
+             * coarsest operator instead of the direct solve */
+            memset(u, 0, m * sizeof(orc_cplx));
+            for (int it = 0; it < g->st_coarse_sweeps; ++it) {
+                if (g->opts.gs_order == ORC_ORDER_LEX) orc_gs_lex(n, pl->H[l], g->kv[l], pl->sigma_relax[l], f, u);
+                else                                   orc_gs_rb(n, pl->H[l], g->kv[l], pl->sigma_relax[l], f, u);
+            }
+            return;
+        }
         memcpy(u, f, m * sizeof(orc_cplx));
         orc_lu_solve((int)m, g->lu, g->piv, u);
         return;
@@ -518,7 +563,8 @@ static void vcycle_level(orc_grid *g, int l, const orc_cplx *f, orc_cplx *u)
     memset(u, 0, m * sizeof(orc_cplx));
     relax(g, l, f, u, pl->pre[l]);
     orc_residual(n, pl->H[l], g->kv[l], pl->sigma_resid[l], f, u, g->r[l]);
-    orc_restrict_fw(n, g->r[l], g->f[l + 1]);
+    if (g->st_fw_transpose) restrict_transpose(n, g->r[l], g->f[l + 1]);
+    else                    orc_restrict_fw(n, g->r[l], g->f[l + 1]);
     vcycle_level(g, l + 1, g->f[l + 1], g->u[l + 1]);
     orc_prolong_add(pl->n[l + 1], g->u[l + 1], u);
     relax(g, l, f, u, pl->post[l]);

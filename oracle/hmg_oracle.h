@@ -93,6 +93,16 @@ void      orc_vcycle(orc_grid *g, const orc_cplx *f, orc_cplx *u);
 int       orc_grid_override_level(orc_grid *g, int l, int smoother, double sigma_relax,
                                   double sigma_resid, int pre, int post);
 
+/* ---- study switches: readings of Section 5 other than the default, for
+ * iteration-count studies (the default reading is what every pin fixes).
+ * fw_transpose: restriction R = P^T / 4 instead of full weighting with
+ * mirror folding at the boundary; coarse_sweeps > 0: the coarsest level runs
+ * that many Gauss-Seidel sweeps from zero instead of the dense solve.  The
+ * boundary row scale (process-wide; leave it off outside a study) multiplies
+ * rows with b boundary faces by 2^-b in every operator of the oracle. ---- */
+void      orc_grid_set_study(orc_grid *g, int fw_transpose, int coarse_sweeps);
+void      orc_set_boundary_row_scale(int on);
+
 /* ---- precision form (O11): the V-cycle with its fields stored in complex
  * float and its arithmetic in double; mode ORC_MIX_FUSED rounds where the
  * fused kernels store (Kaczmarz iterate every kacz_every sweeps, levels with

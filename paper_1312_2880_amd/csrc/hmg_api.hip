@@ -74,22 +74,23 @@ extern "C" void hmg_opts_default(hmg_opts *o) {
 //   last level                       -> dense LU on M (SL) or L (HLM, HYB);
 //   kacz_band, span meets [1.25/sqrt2, 1.25 sqrt2)
 //                                    -> Kaczmarz 4+4 on M (SL, HYB) or L (HLM);
+//   kacz_band, span meets [1.25 sqrt2, 2.5)
+//                                    -> Kaczmarz 4+4 on M (SL) or L (HLM, HYB)
+//                                       (Section 4: Gauss-Seidel is good only
+//                                       up to kH ~ 0.625 and from ~ 2.5 on;
+//                                       where it fails, the normal equation);
 //   HYB, span meets [0.625/sqrt2, 0.625 sqrt2)
 //                                    -> Gauss-Seidel on M;
-//   relaxation on L and an interior node with |k^2 H^2 - 4| < 1 (vanishing
-//   Gauss-Seidel pivot)              -> Kaczmarz 4+4 on L;
 //   otherwise                        -> Gauss-Seidel on M (SL) or L (HLM, HYB).
 // Residuals (role (B)) use M for SL and L for HLM and HYB.
 static void classify_level(const hmg_opts &o, hmg_plan &pl, int l, bool last, const double *k) {
     int n = pl.n[l], M = n + 2;
     double H = pl.H[l], lo = 1e300, hi = -1e300, beta = o.beta;
-    bool guard = false;
     for (int j = 0; j < M; ++j)
         for (int i = 0; i < M; ++i) {
             double kh = k[(size_t)j * M + i] * H;
             lo = std::min(lo, kh);
             hi = std::max(hi, kh);
-            if (i > 0 && j > 0 && i < M - 1 && j < M - 1 && std::fabs(kh * kh - 4.0) < 1.0) guard = true;
         }
     pl.kHmin[l] = lo;
     pl.kHmax[l] = hi;
@@ -102,11 +103,13 @@ static void classify_level(const hmg_opts &o, hmg_plan &pl, int l, bool last, co
         return;
     }
     const double r2 = std::sqrt(2.0);
+    const double sig = sl ? beta : 0.0;
     bool band_k = hi >= 1.25 / r2 && lo < 1.25 * r2;
+    bool band_w = hi >= 1.25 * r2 && lo < 2.5;
     bool band_m = hi >= 0.625 / r2 && lo < 0.625 * r2;
-    if (o.kacz_band && band_k) {
+    if (o.kacz_band && (band_k || band_w)) {
         pl.smoother[l] = HMG_SM_KACZ;
-        pl.sigma_relax[l] = (o.variant == HMG_HLM) ? 0.0 : beta;
+        pl.sigma_relax[l] = band_k ? ((o.variant == HMG_HLM) ? 0.0 : beta) : sig;
         pl.pre[l] = o.kacz_pre;
         pl.post[l] = o.kacz_post;
         return;
@@ -116,14 +119,6 @@ static void classify_level(const hmg_opts &o, hmg_plan &pl, int l, bool last, co
         pl.sigma_relax[l] = beta;
         pl.pre[l] = o.nu_pre;
         pl.post[l] = o.nu_post;
-        return;
-    }
-    double sig = sl ? beta : 0.0;
-    if (sig == 0.0 && guard) {
-        pl.smoother[l] = HMG_SM_KACZ;
-        pl.sigma_relax[l] = 0.0;
-        pl.pre[l] = o.kacz_pre;
-        pl.post[l] = o.kacz_post;
         return;
     }
     pl.smoother[l] = HMG_SM_GS;
@@ -570,8 +565,13 @@ static long slot_stride(const hmg_grid *g) {
     const long zs = (long)(p1[0] - p0[0]);
     for (int r = 1; r < g->nrhs; ++r) {
         const std::vector<const char *> pr = ptrs(g->slot[r]);
-        for (size_t q = 0; q < p0.size(); ++q)
+        for (size_t q = 0; q < p0.size(); ++q) {
+            if (!p0[q] || !pr[q]) {   // a part the grid does not use (the ray fields): absent in every slot
+                if (p0[q] != pr[q]) return 0;
+                continue;
+            }
             if (pr[q] - p0[q] != (long)r * zs) return 0;
+        }
     }
     return zs;
 }

@@ -487,6 +487,7 @@ extern "C" hmg_status hmg_solve(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, doub
         for (int r = 0; r < g->nrhs; ++r) {
             HIPCHK(hipMemcpy(x + m0 * r, g->slot[r].K.x, m0 * 16, hipMemcpyDeviceToHost));
             if (B.status[r] != HMG_OK && worst == HMG_OK) worst = B.status[r];
+            if (info) info[r].flags |= HMG_INFO_BATCHED;
         }
         return worst;
     }
@@ -698,6 +699,7 @@ extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *
                     for (int r = 0; r < grids[q]->nrhs; ++r) {
                         HIPCHK(hipMemcpy(x[q] + m0 * r, grids[q]->slot[r].K.x, m0 * 16, hipMemcpyDeviceToHost));
                         if (B.status[r] != HMG_OK && worst == HMG_OK) worst = B.status[r];
+                        if (info && info[q]) info[q][r].flags |= HMG_INFO_BATCHED;
                     }
                     live[q] = 0;
                 }

@@ -75,11 +75,19 @@ class LayeredMedium:
         self.gmax = float(np.abs(self._bumps(xs)).max())
 
     def _bumps(self, xs: np.ndarray) -> np.ndarray:
-        # separable Gaussians: g[j, i] = sum_m a_m gx_m(x_i) gy_m(y_j)
+        # separable Gaussians: g[j, i] = sum_m a_m gx_m(x_i) gy_m(y_j).  The
+        # same bits on every host and thread count: the exponentials come
+        # from the C library one value at a time (vectorised exponentials
+        # differ between instruction sets) and the sum over m is accumulated
+        # elementwise in a fixed order (a BLAS product rounds differently
+        # with the number of threads).
         s2 = 2.0 * BUMP_WIDTH ** 2
-        gx = np.exp(-(xs[None, :] - self.centres[:, 0:1]) ** 2 / s2)   # (m, nx)
-        gy = np.exp(-(xs[None, :] - self.centres[:, 1:2]) ** 2 / s2)   # (m, ny)
-        return (gy * self.amp[:, None]).T @ gx
+        gx = np.array([[math.exp(-(x - c) ** 2 / s2) for x in xs] for c in self.centres[:, 0]])   # (m, nx)
+        gy = np.array([[math.exp(-(y - c) ** 2 / s2) for y in xs] for c in self.centres[:, 1]])   # (m, ny)
+        g = np.zeros((xs.size, xs.size))
+        for m in range(self.amp.size):
+            g += np.multiply.outer(self.amp[m] * gy[m], gx[m])
+        return g
 
     def speed(self, n: int) -> np.ndarray:
         xs = node_coords(n)

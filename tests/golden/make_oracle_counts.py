@@ -4,9 +4,11 @@
 
     python tests/golden/make_oracle_counts.py        (about 10 minutes on 8 cores)
 
-Only the oracle is called.  The counts depend slightly on the host (the
-iteration is chaotic in its last digits), so the tests that use them allow
-a margin.
+Only the oracle is called.  The inputs are the same bits on every host
+(the generators avoid thread- and instruction-set-dependent rounding), but
+the iteration is chaotic in its last digits, so the tests that use the
+counts allow a margin; the restart count and a sampled residual history are
+stored beside them.
 """
 import json
 import os
@@ -27,9 +29,12 @@ def main():
         h, k, f = fn()
         g = oracle.Grid(h, k, variant=oracle.HYB)
         t0 = time.time()
-        _, info = g.bicgstab(f, rtol=1e-6, maxit=3000)
+        _, info = g.bicgstab(f, rtol=1e-6, maxit=3000, history=True)
+        hist = [float(v) for v in info["history"]]
         out[name] = {"iters": info["iters"], "status": info["status"], "rtol": 1e-6,
-                     "seconds": round(time.time() - t0, 1)}
+                     "restarts": info["restarts"], "seconds": round(time.time() - t0, 1),
+                     # relative residual after every 50th half step (entry 0: the start)
+                     "history_every_50": hist[::50]}
         print(name, out[name], flush=True)
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_counts.json")
     with open(path, "w") as fh:

@@ -422,14 +422,27 @@ def test_plan_hybrid_constant_k():
     assert hlm[2]["smoother"] == "KACZ" and hlm[2]["sigma_relax"] == 0.0
 
 
-def test_plan_pivot_guard():
-    """When Gauss-Seidel on L would meet kH ~ 2 (vanishing pivot) the level
-    takes the normal-equation relaxation on L instead."""
+def test_plan_between_the_kaczmarz_band_and_kh_2_5():
+    """Section 4: Gauss-Seidel is good only up to kH ~ 0.625 and from ~2.5 on;
+    a level between the 1.25 band and 2.5 (here kH = 2.0, where Gauss-Seidel
+    on L also loses its pivot) takes the normal-equation relaxation on the
+    variant's operator: M for SL-V, L for HYB-V and HLM-V.  Levels at
+    kH = 0.3125 * 2^j (the paper's grids) are unaffected (the plan test of
+    the constant-k hierarchy above)."""
     n = 127
     h = 1 / 128
     k = np.full((n + 2, n + 2), 0.5 / h)      # kH = 0.5, 1.0, 2.0, 4.0, 8.0
-    plan = oracle.Grid(h, k, variant=oracle.HYB).plan()
-    assert plan[2]["smoother"] == "KACZ" and plan[2]["sigma_relax"] == 0.0
+    want = {oracle.SL: [("GS", BETA), ("KACZ", BETA), ("KACZ", BETA), ("GS", BETA), ("LU", BETA)],
+            oracle.HYB: [("GS", BETA), ("KACZ", BETA), ("KACZ", 0.0), ("GS", 0.0), ("LU", 0.0)],
+            oracle.HLM: [("GS", 0.0), ("KACZ", 0.0), ("KACZ", 0.0), ("GS", 0.0), ("LU", 0.0)]}
+    for variant, plan_want in want.items():
+        plan = oracle.Grid(h, k, variant=variant).plan()
+        assert [(p["smoother"], p["sigma_relax"]) for p in plan] == plan_want, variant
+        assert all(p["pre"] == 4 for p in plan if p["smoother"] == "KACZ")
+    # kH = 2.5 exactly stays Gauss-Seidel (the constant-k hierarchy of Table 1)
+    k = np.full((n + 2, n + 2), 0.625 / h)     # kH = 0.625, 1.25, 2.5, 5, 10
+    plan = oracle.Grid(h, k, variant=oracle.SL).plan()
+    assert [p["smoother"] for p in plan] == ["GS", "KACZ", "GS", "GS", "LU"]
 
 
 CASES_P4 = [
@@ -751,3 +764,100 @@ def test_table1_trend_hybrid_not_worse_than_sl():
         assert info["status"] == oracle.OK
         its[v] = info["iters"]
     assert its[oracle.HYB] <= its[oracle.SL] + 1.0, its
+
+
+# ---------------------------------------------------------------------------
+# study switches (readings other than the default, for the iteration-count
+# study of Section 5's choices): each equals its dense composition
+# ---------------------------------------------------------------------------
+
+class _DenseCoarseSweeps(D.DenseVCycle):
+    """The dense V-cycle with the coarsest dense solve replaced by `sweeps`
+    red-black Gauss-Seidel sweeps from zero on the coarsest operator."""
+
+    def __init__(self, h, k, plan, sweeps):
+        super().__init__(h, k, plan)
+        self.sweeps = sweeps
+
+    def apply(self, f, l=0):
+        lev = self.levels[l]
+        if lev["smoother"] == "LU":
+            u = np.zeros_like(f)
+            for _ in range(self.sweeps):
+                u = D.sweep_gs_colour(lev["A_relax"], f, u, D.colour_rb(lev["n"]), 2)
+            return u
+        return super().apply(f, l)
+
+
+def _compare_vcycle(g, ref, n):
+    m = (n + 2) ** 2
+    for col in range(0, m, 11):
+        f = np.zeros(m, complex)
+        f[col] = 1.0
+        f[(col * 7 + 5) % m] = -0.25j
+        want = ref.apply(f)
+        got = g.vcycle(f.reshape(n + 2, n + 2)).reshape(-1)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("variant", [oracle.SL, oracle.HYB])
+def test_study_restriction_is_the_transpose_of_interpolation(variant):
+    """fw_transpose: the V-cycle with R = P^T / 4 on every level (the boundary
+    weights dropped, not mirrored) equals that dense composition."""
+    n, h = 15, 1 / 16
+    k = rng_k(n, 61, 4.0, 30.0)
+    g = oracle.Grid(h, k, variant=variant).set_study(fw_transpose=True)
+    ref = D.DenseVCycle(h, k, g.plan())
+    for lev in ref.levels[:-1]:
+        lev["R"] = lev["P"].T / 4.0
+    _compare_vcycle(g, ref, n)
+    # and it differs from full weighting with mirror folding at the boundary
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal((n + 2, n + 2)) + 1j * rng.standard_normal((n + 2, n + 2))
+    base = oracle.Grid(h, k, variant=variant).vcycle(f)
+    assert np.linalg.norm(g.vcycle(f) - base) > 1e-6 * np.linalg.norm(base)
+
+
+@pytest.mark.parametrize("sweeps", [1, 3])
+def test_study_coarsest_sweeps_replace_the_dense_solve(sweeps):
+    n, h = 15, 1 / 16
+    k = rng_k(n, 62, 4.0, 30.0)
+    g = oracle.Grid(h, k, variant=oracle.HYB).set_study(coarse_sweeps=sweeps)
+    _compare_vcycle(g, _DenseCoarseSweeps(h, k, g.plan(), sweeps), n)
+
+
+def test_study_boundary_row_scale():
+    """Rows with b boundary faces scaled by 2^-b: the operator equals D A with
+    A the independent ghost-point matrix, and the scaled operator is complex
+    symmetric (the doubled inward weights are halved); the V-cycle with it
+    equals the dense composition with D A for relaxation, residuals and the
+    coarsest solve."""
+    n, h = 7, 1 / 8
+    k = rng_k(n, 63, 2.0, 20.0)
+    M = n + 2
+    jj, ii = np.meshgrid(np.arange(M), np.arange(M), indexing="ij")
+    b = ((ii == 0).astype(int) + (ii == n + 1) + (jj == 0) + (jj == n + 1)).reshape(-1)
+    Dm = np.diag(2.0 ** (-b))
+    try:
+        oracle.set_boundary_row_scale(True)
+        for sigma in (0.0, 0.5):
+            A = oracle.dense(h, k, sigma)
+            want = Dm @ D.assemble_ghost(n, h, k, sigma)
+            np.testing.assert_allclose(A, want, rtol=0, atol=1e-12 * np.abs(want).max())
+            np.testing.assert_allclose(A, A.T, rtol=0, atol=1e-12 * np.abs(A).max())
+        g = oracle.Grid(h, k, variant=oracle.HYB)
+        ref = D.DenseVCycle(h, k, g.plan())
+        for lev in ref.levels:
+            nl = lev["n"]
+            Ml = nl + 2
+            jl, il = np.meshgrid(np.arange(Ml), np.arange(Ml), indexing="ij")
+            bl = ((il == 0).astype(int) + (il == nl + 1) + (jl == 0) + (jl == nl + 1)).reshape(-1)
+            Dl = np.diag(2.0 ** (-bl))
+            lev["A_relax"] = Dl @ lev["A_relax"]
+            lev["A_resid"] = Dl @ lev["A_resid"]
+        _compare_vcycle(g, ref, n)
+    finally:
+        oracle.set_boundary_row_scale(False)
+    # off again: the default rows
+    np.testing.assert_allclose(oracle.dense(h, k, 0.0), D.assemble_ghost(n, h, k, 0.0),
+                               rtol=0, atol=1e-12 * np.abs(D.assemble_ghost(n, h, k, 0.0)).max())
