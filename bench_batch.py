@@ -1,7 +1,9 @@
 """Batching benchmark: 64 independent constant-k instances of mixed size
 (n ~ U{127, 255, 511, 1023}, kh ~ U[0.3, 0.6]), 4 point-source right-hand
 sides each, solved together with hmg_solve_batch, against solving the same
-instances one after the other.
+instances one after the other (hmg_solve per instance: its four right-hand
+sides in one launch per kernel) and against solving every right-hand side
+alone (hmg_solve_dev per right-hand side: no batching at all).
 
     python bench_batch.py [--count 64] [--nrhs 4] [--precision mixed|fp64|both]
 
@@ -44,16 +46,29 @@ def main():
         grids = [hmg.Grid(ctx, it["h"], it["k"], np.stack(it["f"]), precision=prec, variant=hmg.SL)
                  for it in insts]
         print(f"# {pname}: {len(grids)} grids created in {time.perf_counter() - t0:.1f} s", flush=True)
-        for form in ("batched", "one-by-one"):
+        dev_f = [[torch.from_numpy(np.ascontiguousarray(fr)).to("cuda") for fr in it["f"]] for it in insts]
+        for form in ("batched", "one-by-one", "one-rhs-at-a-time"):
+            torch.cuda.synchronize()
             t0 = time.perf_counter()
             if form == "batched":
                 _, infos = ctx.solve_batch(grids, rtol=1e-6, maxit=args.maxit)
-            else:
+            elif form == "one-by-one":
                 infos = []
                 for q, g in enumerate(grids):
                     infos.append(g.solve(rtol=1e-6, maxit=args.maxit)[1])
                     if q % 16 == 15:
                         print(f"# {pname} one-by-one: {q + 1} instances", flush=True)
+            else:
+                infos = []
+                for q, g in enumerate(grids):
+                    row = []
+                    for r, d_b in enumerate(dev_f[q]):
+                        d_x = torch.zeros_like(d_b)
+                        row.append(g.solve_dev(d_x, d_b=d_b, rhs=r, rtol=1e-6, maxit=args.maxit))
+                    infos.append(row)
+                    if q % 16 == 15:
+                        print(f"# {pname} one rhs at a time: {q + 1} instances", flush=True)
+            torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             flat = [i for inf in infos for i in inf]
             bad = [i for i in flat if not (i["status"] == hmg.OK and i["rel_res_true"] <= 1e-6)]

@@ -138,9 +138,10 @@ typedef struct {
                                 a solve: 0 off (default); else the ray grid's
                                 interior nodes per side, with (n + 1) a
                                 multiple of ray_n + 1, at least 8 fine
-                                intervals per ray cell and ray_n <= 15 (the
-                                8 (ray_n + 2)^2 ray unknowns are solved
-                                densely).  The preconditioner becomes
+                                intervals per ray cell and ray_n <= 7 (the
+                                8 (ray_n + 2)^2 <= 648 ray unknowns are
+                                solved densely; the Galerkin matrix is
+                                factored on the host at grid creation).  The preconditioner becomes
                                 z = B_V r; z += P (P^H L P)^{-1} P^H (r - L z),
                                 P the 8 plane waves exp(i kr (cos(j pi/4) x +
                                 sin(j pi/4) y)), j = 1..8, times the bilinear
@@ -177,6 +178,11 @@ typedef struct {
  * i.e. fewer than ten nodes per wavelength somewhere (the resolution the
  * problem statement of Section 1 asks for); the solve is run regardless. */
 #define HMG_INFO_KH_ABOVE_GUIDE 1
+/* hmg_solve_info.flags: this right-hand side ran with every other right-hand
+ * side of its grid in one launch per kernel (a grid with nrhs >= 2 on the
+ * default fused schedule); otherwise the right-hand sides ran one after
+ * another. */
+#define HMG_INFO_BATCHED 2
 
 typedef struct hmg_ctx  hmg_ctx;
 typedef struct hmg_grid hmg_grid;

@@ -29,6 +29,7 @@ SL, HLM, HYB = 0, 1, 2
 FP64, MIXED = 0, 1
 SM_GS, SM_KACZ, SM_LU = 0, 1, 2
 INFO_KH_ABOVE_GUIDE = 1
+INFO_BATCHED = 2
 ORDER_COLOUR, ORDER_LEX = 0, 1
 MAX_LEVELS = 24
 STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "NOT_CONVERGED",

@@ -45,15 +45,17 @@ def kernel_trace(path: str, top: int = 20) -> str:
     for r in rows:
         name = r["Kernel_Name"].split("(")[0].replace("void ", "")
         wx, wy = int(r["Workgroup_Size_X"]), int(r.get("Workgroup_Size_Y", 1) or 1)
-        key = (name, int(r["Grid_Size_X"]) // max(wx, 1), int(r["Grid_Size_Y"]) // max(wy, 1), wx * wy)
+        wz = int(r.get("Workgroup_Size_Z", 1) or 1)
+        gz = int(r.get("Grid_Size_Z", 1) or 1) // max(wz, 1)
+        key = (name, int(r["Grid_Size_X"]) // max(wx, 1), int(r["Grid_Size_Y"]) // max(wy, 1), wx * wy * wz, gz)
         groups.setdefault(key, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     total = sum(sum(v) for v in groups.values())
-    out = ["| share | calls | median (us) | total (ms) | workgroups | threads | kernel |",
+    out = ["| share | calls | median (us) | total (ms) | workgroups (x by y by z) | threads | kernel |",
            "|---:|---:|---:|---:|---:|---:|---|"]
     for key, v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
         v.sort()
         out.append(f"| {100 * sum(v) / total:5.1f}% | {len(v)} | {v[len(v) // 2] / 1e3:.2f} | "
-                   f"{sum(v) / 1e6:.2f} | {key[1]}x{key[2]} | {key[3]} | `{key[0]}` |")
+                   f"{sum(v) / 1e6:.2f} | {key[1]}x{key[2]}x{key[4]} | {key[3]} | `{key[0]}` |")
     out.append(f"\nall kernels: {total / 1e6:.2f} ms")
     return "\n".join(out)
 
