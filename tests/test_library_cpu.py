@@ -98,3 +98,23 @@ def test_null_arguments_are_rejected():
     assert lib.hmg_solve(None, None, None, 1e-6, 10, None) == hmg.ERR_INVALID
     assert lib.hmg_poll(None, 1, None, None) == hmg.ERR_INVALID
     assert b"null" in lib.hmg_last_error()
+
+
+def test_input_generators_do_not_depend_on_thread_count():
+    """The seeded media are the same bits whatever the number of BLAS/OpenMP
+    threads (the oracle's stored counts and the GPU runs on another host use
+    the same problem)."""
+    import hashlib
+    import subprocess
+    import sys
+    code = ("import hashlib, sys; sys.path.insert(0, %r); "
+            "from paper_1312_2880_amd import inputs; "
+            "h, k, f = inputs.layered_problem(255, 2, 50.0); "
+            "w = inputs.wedge_problem(127); "
+            "print(hashlib.sha256(k.tobytes() + f.tobytes() + w[1].tobytes()).hexdigest())" % ROOT)
+    out = set()
+    for threads in ("1", "3", "8"):
+        env = dict(os.environ, OMP_NUM_THREADS=threads, OPENBLAS_NUM_THREADS=threads)
+        out.add(subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                               check=True).stdout.strip())
+    assert len(out) == 1, out
