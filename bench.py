@@ -309,6 +309,9 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=2,
                     help="timed solves of the same problem with the complex-float preconditioner "
                          "(reported beside the FP64 figure; 0: skip)")
+    ap.add_argument("--hyb-mid-steps", type=int, default=2,
+                    help="timed solves of the same problem with HYB-V's intermediate-scales reading "
+                         "(hmg_opts.hyb_mid = 1), reported beside the headline (0: skip)")
     ap.add_argument("--traffic-probe", default=None, metavar="KERNEL@N",
                     help="only launch this kernel (e.g. kacz_tb@127) as the timing does, then "
                          "a plain copy of known size, for the FETCH_SIZE / WRITE_SIZE runs")
@@ -417,6 +420,25 @@ def main():
                  "precision": "complex-float V-cycle storage, FP64 arithmetic; FP64 outer Bi-CGSTAB"}
         gm.close()
 
+    hyb_mid = None
+    if args.hyb_mid_steps > 0 and args.variant == "hyb" and args.precision == "fp64" and not lex:
+        gh = hmg.Grid(ctx, h, k, f, variant=variant, precision=prec, hyb_mid=1)
+        d_xh = torch.zeros_like(d_b)
+        hinfo = [gh.solve_dev(d_xh, d_b=d_b, rtol=1e-6, maxit=args.maxit, stream=stream)]   # warm-up
+        torch.cuda.synchronize()
+        t0h = time.perf_counter()
+        for _ in range(args.hyb_mid_steps):
+            hinfo.append(gh.solve_dev(d_xh, d_b=d_b, rtol=1e-6, maxit=args.maxit, stream=stream))
+        torch.cuda.synchronize()
+        dth = time.perf_counter() - t0h
+        hyb_mid = {"value": round(args.hyb_mid_steps / dth, 4), "unit": "solves/s",
+                   "ms_per_step": round(1e3 * dth / args.hyb_mid_steps, 3), "iters": hinfo[-1]["iters"],
+                   "rel_res_true": hinfo[-1]["rel_res_true"],
+                   "all_converged": all(i["status"] == hmg.OK and i["rel_res_true"] <= 1e-6 for i in hinfo),
+                   "reading": "HYB-V with M for relaxation on the intermediate scales up to kH ~ 2.5 "
+                              "(hmg_opts.hyb_mid = 1), FP64"}
+        gh.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -449,6 +471,7 @@ def main():
         "kernels": {k_["key"]: {"ms_per_launch": round(k_["ms"], 5), "launches_per_iter": k_["per_iter"],
                                 "share_of_solve": round(k_["share"], 3), **k_["roofline"]} for k_ in kt},
         "mixed": mixed,
+        "hyb_mid": hyb_mid,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

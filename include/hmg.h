@@ -146,7 +146,16 @@ typedef struct {
                                 P the 8 plane waves exp(i kr (cos(j pi/4) x +
                                 sin(j pi/4) y)), j = 1..8, times the bilinear
                                 hats of the ray grid, kr the mean of k          */
-    int    reserved[1];
+    int    hyb_mid;          /* HYB-V only: 1 = M for relaxation on the
+                                intermediate scales up to kH ~ 2.5 as well
+                                (levels whose kH span meets
+                                [0.625/sqrt2, 2.5 sqrt2)), L on the finer and
+                                the coarsest ones: the motivation of the
+                                hybrid in Section 5 (M's transformation of
+                                near-kernel error on intermediate scales, L's
+                                accuracy on the coarsest); 0 = the variant's
+                                definition, M only for 0.625 <~ kH <~ 1.25
+                                (default)                                     */
 } hmg_opts;
 
 #define HMG_MAX_LEVELS 24

@@ -49,7 +49,8 @@ class _Opts(ctypes.Structure):
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("kacz_pre", ctypes.c_int), ("kacz_post", ctypes.c_int),
                 ("kacz_band", ctypes.c_int), ("coarsest_n", ctypes.c_int),
-                ("gs_order", ctypes.c_int), ("kacz_order", ctypes.c_int)]
+                ("gs_order", ctypes.c_int), ("kacz_order", ctypes.c_int),
+                ("hyb_mid", ctypes.c_int)]
 
 
 class _Plan(ctypes.Structure):

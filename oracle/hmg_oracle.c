@@ -357,6 +357,7 @@ void orc_opts_default(orc_opts *o)
     o->coarsest_n = 7;
     o->gs_order   = ORC_ORDER_COLOUR;
     o->kacz_order = ORC_ORDER_COLOUR;
+    o->hyb_mid    = 0;
 }
 
 /* Level classification.  The paper states its rules for constant k on
@@ -375,7 +376,13 @@ void orc_opts_default(orc_opts *o)
  *      pivot at kH = 2);
  *   4. HYB only, span meets [0.625/sqrt2, 0.625*sqrt2): Gauss-Seidel on M;
  *   5. otherwise Gauss-Seidel, on M for SL and on L for HLM and HYB.
- * The residual operator (role (B)) is M for SL and L for HLM and HYB. */
+ * The residual operator (role (B)) is M for SL and L for HLM and HYB.
+ * With hyb_mid (HYB only) the relaxation operator is M on every level whose
+ * span meets [0.625/sqrt2, 2.5*sqrt2) (rules 3 and 4): Section 5 motivates
+ * the hybrid by M's transformation of near-kernel error on the intermediate
+ * scales and L's accuracy on the coarsest ones, and Section 3 finds M's
+ * approximation at kH = 2.5 wrong "in the right way" for a preconditioner,
+ * while the variant's definition keeps M to 0.625 <~ kH <~ 1.25. */
 static void classify(orc_grid *g, int l, int last)
 {
     const orc_opts *o  = &g->opts;
@@ -400,11 +407,12 @@ static void classify(orc_grid *g, int l, int last)
     double s2 = sqrt(2.0);
     int in_kacz = (hi >= 1.25 / s2) && (lo < 1.25 * s2);
     int in_wide = (hi >= 1.25 * s2) && (lo < 2.5);
-    int in_gsm  = (hi >= 0.625 / s2) && (lo < 0.625 * s2);
+    int mid     = (o->variant == ORC_HYB) && o->hyb_mid;
+    int in_gsm  = (hi >= 0.625 / s2) && (lo < (mid ? 2.5 : 0.625) * s2);
     double sig = (o->variant == ORC_SL) ? beta : 0.0;
     if (o->kacz_band && (in_kacz || in_wide)) {
         pl->smoother[l]    = ORC_SM_KACZ;
-        pl->sigma_relax[l] = in_kacz ? ((o->variant == ORC_HLM) ? 0.0 : beta) : sig;
+        pl->sigma_relax[l] = in_kacz ? ((o->variant == ORC_HLM) ? 0.0 : beta) : (mid ? beta : sig);
         pl->pre[l] = o->kacz_pre;
         pl->post[l] = o->kacz_post;
         return;

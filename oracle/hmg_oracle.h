@@ -69,6 +69,10 @@ typedef struct {
     int    coarsest_n;   /* interior size of the LU level (7)              */
     int    gs_order;     /* ORC_ORDER_COLOUR (red-black) or ORC_ORDER_LEX  */
     int    kacz_order;   /* ORC_ORDER_COLOUR (5 colours) or ORC_ORDER_LEX  */
+    int    hyb_mid;      /* HYB only: 1 = M for relaxation on the intermediate
+                            scales up to kH ~ 2.5 as well (the motivation of
+                            the hybrid in Section 5); 0 = the variant's
+                            definition, M only for 0.625 <~ kH <~ 1.25      */
 } orc_opts;
 
 #define ORC_MAX_LEVELS 24

@@ -82,6 +82,9 @@ extern "C" void hmg_opts_default(hmg_opts *o) {
 //   HYB, span meets [0.625/sqrt2, 0.625 sqrt2)
 //                                    -> Gauss-Seidel on M;
 //   otherwise                        -> Gauss-Seidel on M (SL) or L (HLM, HYB).
+// With opts.hyb_mid (HYB only) M is the relaxation operator on every level
+// whose span meets [0.625/sqrt2, 2.5 sqrt2) (the intermediate scales of the
+// hybrid's motivation in Section 5), the Kaczmarz levels of that span included.
 // Residuals (role (B)) use M for SL and L for HLM and HYB.
 static void classify_level(const hmg_opts &o, hmg_plan &pl, int l, bool last, const double *k) {
     int n = pl.n[l], M = n + 2;
@@ -106,10 +109,11 @@ static void classify_level(const hmg_opts &o, hmg_plan &pl, int l, bool last, co
     const double sig = sl ? beta : 0.0;
     bool band_k = hi >= 1.25 / r2 && lo < 1.25 * r2;
     bool band_w = hi >= 1.25 * r2 && lo < 2.5;
-    bool band_m = hi >= 0.625 / r2 && lo < 0.625 * r2;
+    const bool mid = o.variant == HMG_HYB && o.hyb_mid;
+    bool band_m = hi >= 0.625 / r2 && lo < (mid ? 2.5 : 0.625) * r2;
     if (o.kacz_band && (band_k || band_w)) {
         pl.smoother[l] = HMG_SM_KACZ;
-        pl.sigma_relax[l] = band_k ? ((o.variant == HMG_HLM) ? 0.0 : beta) : sig;
+        pl.sigma_relax[l] = band_k ? ((o.variant == HMG_HLM) ? 0.0 : beta) : (mid ? beta : sig);
         pl.pre[l] = o.kacz_pre;
         pl.post[l] = o.kacz_post;
         return;
@@ -707,6 +711,7 @@ static hmg_status check_problem(const hmg_opts &o, int n, double h, const double
     if (o.true_res_every < 0) return hmg_fail(HMG_ERR_INVALID, "true_res_every must be >= 0");
     if (o.nan_at < 0) return hmg_fail(HMG_ERR_INVALID, "nan_at must be >= 0");
     if (o.fp64_levels < 0) return hmg_fail(HMG_ERR_INVALID, "fp64_levels must be >= 0");
+    if (o.hyb_mid != 0 && o.hyb_mid != 1) return hmg_fail(HMG_ERR_INVALID, "hyb_mid must be 0 or 1");
     {
         RayGeo rg{};
         if (ray_geometry(n, o.ray_n, rg) < 0)

@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("bottom_dense", ctypes.c_int), ("relax_order", ctypes.c_int),
                 ("breakdown_at", ctypes.c_int), ("true_res_every", ctypes.c_int),
                 ("nan_at", ctypes.c_int), ("fp64_levels", ctypes.c_int),
-                ("ray_n", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
+                ("ray_n", ctypes.c_int), ("hyb_mid", ctypes.c_int)]
 
 
 class Plan(ctypes.Structure):

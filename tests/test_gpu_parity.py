@@ -513,6 +513,8 @@ def vcycle_cases():
                 dict(variant=0, coarsest_n=3)))
     h2, k2, _ = inputs.layered_problem(255, 2, 2 * math.pi * 10)
     out.append(("layered255_hyb", h2, k2, dict(variant=2)))
+    out.append(("layered255_hyb_mid", h2, k2, dict(variant=2, hyb_mid=1)))
+    out.append(("point127_hyb_mid", 1 / 128, inputs.constant_k(127, 0.625 * 128), dict(variant=2, hyb_mid=1)))
     return out
 
 
@@ -585,6 +587,29 @@ def test_lexicographic_solve_matches_oracle(ctx, hmg):
         margin = count_margin(ref["iters"]) if ref["iters"] < 100 else 0.25 * ref["iters"]
         assert abs(i0["iters"] - ref["iters"]) <= margin, (i0, ref)
         np.testing.assert_allclose(g.history(0)[:12], ref["history"][:12], rtol=1e-7)
+
+
+def test_hyb_mid_solve_matches_oracle(ctx, hmg):
+    """HYB-V with M on the intermediate scales (hyb_mid) on the 1023^2
+    layered medium: plan, early residual history and count against the
+    oracle with the same option; it needs about SL-V's iterations where the
+    variant's definition needs ~1.7x (the study of Section 5's readings)."""
+    say("case hyb_mid solve layered1023")
+    h, k, f = inputs.workload_layered_1023()
+    g = hmg.Grid(ctx, h, k, f, variant=hmg.HYB, hyb_mid=1)
+    og = oracle.Grid(h, k, variant=oracle.HYB, hyb_mid=1)
+    assert [(p["smoother"], p["sigma_relax"], p["sigma_resid"]) for p in g.plan()] == \
+        [(p["smoother"], p["sigma_relax"], p["sigma_resid"]) for p in og.plan()]
+    x, info = g.solve(rtol=1e-6, maxit=600)
+    _, ref = og.bicgstab(f, rtol=1e-6, maxit=600, history=True)
+    i0 = info[0]
+    say(f"  gpu {i0['iters']} oracle {ref['iters']}")
+    assert i0["status"] == hmg.OK and i0["rel_res_true"] <= 1e-6
+    assert abs(i0["iters"] - ref["iters"]) <= count_margin(ref["iters"]), (i0, ref)
+    np.testing.assert_allclose(g.history(0)[:12], ref["history"][:12], rtol=1e-7)
+    assert ref["iters"] < 120      # the definition's HYB-V needs 161 here
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
 
 
 # Grids whose interval count is not a power of two (Table 1: h = 1/80, 1/160,

@@ -422,6 +422,22 @@ def test_plan_hybrid_constant_k():
     assert hlm[2]["smoother"] == "KACZ" and hlm[2]["sigma_relax"] == 0.0
 
 
+def test_plan_hybrid_with_intermediate_scales_on_m():
+    """hyb_mid (HYB-V): the relaxation operator is M on the levels up to
+    kH ~ 2.5 (here kH = 0.625, 1.25 and 2.5), L on the finest (0.3125) and
+    on the coarsest scales (5 and beyond); residuals stay on L; SL-V and
+    HLM-V ignore the option."""
+    n = 255
+    h = 1 / 256
+    k = np.full((n + 2, n + 2), 0.3125 / h)     # kH = 0.3125, 0.625, 1.25, 2.5, 5, 10
+    plan = oracle.Grid(h, k, variant=oracle.HYB, hyb_mid=1).plan()
+    assert [(p["smoother"], p["sigma_relax"]) for p in plan] == [
+        ("GS", 0.0), ("GS", BETA), ("KACZ", BETA), ("GS", BETA), ("GS", 0.0), ("LU", 0.0)]
+    assert all(p["sigma_resid"] == 0.0 for p in plan)
+    for variant in (oracle.SL, oracle.HLM):
+        assert oracle.Grid(h, k, variant=variant, hyb_mid=1).plan() == oracle.Grid(h, k, variant=variant).plan()
+
+
 def test_plan_between_the_kaczmarz_band_and_kh_2_5():
     """Section 4: Gauss-Seidel is good only up to kH ~ 0.625 and from ~2.5 on;
     a level between the 1.25 band and 2.5 (here kH = 2.0, where Gauss-Seidel
@@ -454,6 +470,9 @@ CASES_P4 = [
          gs_order=oracle.ORDER_LEX, kacz_order=oracle.ORDER_LEX),
     # HYB level with Gauss-Seidel on M and residuals on L (kH in [0.45, 0.875])
     dict(variant=oracle.HYB, kacz_band=1, coarsest_n=3, k=(3.6, 7.0)),
+    # hyb_mid: Kaczmarz on M at kH in [1.25, 1.75], Gauss-Seidel on M at
+    # kH in [2.5, 3.5], residuals on L
+    dict(variant=oracle.HYB, kacz_band=1, coarsest_n=1, k=(10.0, 14.0), hyb_mid=1),
 ]
 
 
