@@ -162,10 +162,12 @@ struct GsTile {
 // small one, so that more workgroups share the latency of the dependent phases
 using GsBig = GsTile<64, 20>;
 using GsSmall = GsTile<32, 12>;
-// the down kernel holds fewer values per node and prefers many short tiles
-// on the finest levels too: 16 x 12 (one node of each colour per thread;
-// 5590 workgroups at n = 1023) measured faster than 64 x 12 and 32 x 12
-using GsDownBig = GsTile<16, 12>;
+// the down kernel holds fewer values per node and prefers narrow tiles on
+// the finest levels too: 16 x 16, the tallest with one node of each colour
+// per thread (11 x 22 = 242 per colour in the region; 16641 workgroups at
+// n = 2047), measured faster than 16 x 14, 16 x 12, 16 x 10 (40.3, 43.2,
+// 45.0, 46.1 us at n = 2047), 64 x 12 and 32 x 12
+using GsDownBig = GsTile<16, 16>;
 // the up kernel that reads the stored pre-smoothed iterate needs a halo of 2
 using GsBig2 = GsTile<64, 20, 2>;
 // the up kernel with the Bi-CGSTAB matrix-vector product needs its result on
