@@ -39,7 +39,8 @@ def _hipcc_cmd(opt, extra):
             # keep the compiler from forming packed FP32 instructions
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC] + extra + \
-        [os.path.join(CSRC, s) for s in SOURCES]
+        [os.path.join(CSRC, s) for s in SOURCES] + \
+        ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def build(verbose: bool = False) -> str:

@@ -588,6 +588,7 @@ bool grid_batchable(const hmg_grid *g) {
 }
 
 static hmg_status tune_levels(hmg_grid *g) {
+    MarkRange mark_("hmg tuner");
     if (!g->opts.autotune) return HMG_OK;
     for (int l = 0; l < g->nlev; ++l)
         if (g->lev[l].mode == LM_KACZ_TILED) {
@@ -807,6 +808,7 @@ static hmg_status load_problem(hmg_grid *g, const std::vector<std::vector<double
 
 extern "C" hmg_status hmg_grid_create(hmg_ctx *ctx, int n, double h, const double *k, const hmg_c64 *f, int nrhs,
                                       const hmg_opts *opts, hmg_grid **out) {
+    MarkRange mark_("hmg_grid_create");
     if (!ctx || !out) return hmg_fail(HMG_ERR_INVALID, "null context or output handle");
     *out = nullptr;
     hmg_opts o;
@@ -862,6 +864,7 @@ bool grid_reusable(const hmg_grid *g, int n, int nrhs, const hmg_opts &o) {
 // layout depends on n and the options only).  The level plan, tables,
 // coarsest inverse and bottom matrix are rebuilt and captured graphs dropped.
 hmg_status grid_reload(hmg_grid *g, double h, const double *k, const hmg_c64 *f) {
+    MarkRange mark_("hmg grid reload");
     hmg_status st = check_problem(g->opts, g->n, h, k, f, g->nrhs);
     if (st) return st;
     HIPCHK(hipSetDevice(g->ctx->device));

@@ -5,6 +5,8 @@
 #include "hmg.h"
 #include "hmg_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <complex>
 #include <condition_variable>
 #include <deque>
@@ -13,6 +15,16 @@
 #include <mutex>
 #include <thread>
 #include <vector>
+
+// A named host-side range for rocprofv3 --marker-trace (grid set-up, the
+// tuner, solves, batches, the server's admissions and retirements); a
+// function call when no tool is attached.
+struct MarkRange {
+    explicit MarkRange(const char *name) { roctxRangePushA(name); }
+    ~MarkRange() { roctxRangePop(); }
+    MarkRange(const MarkRange &) = delete;
+    MarkRange &operator=(const MarkRange &) = delete;
+};
 
 struct ServerState;
 

@@ -463,6 +463,7 @@ static hmg_status check_solve_args(double rtol, int maxit) {
 
 extern "C" hmg_status hmg_solve(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, double rtol, int maxit,
                                 hmg_solve_info *info) {
+    MarkRange mark_("hmg_solve");
     if (!g || !x) return hmg_fail(HMG_ERR_INVALID, "null argument");
     hmg_status st = check_solve_args(rtol, maxit);
     if (st) return st;
@@ -504,6 +505,7 @@ extern "C" hmg_status hmg_solve(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, doub
 
 extern "C" hmg_status hmg_solve_dev(hmg_grid *g, int rhs, const void *d_b, void *d_x, int x0_given, double rtol,
                                     int maxit, hmg_solve_info *info, void *stream) {
+    MarkRange mark_("hmg_solve_dev");
     if (!g || !d_x || rhs < 0 || rhs >= g->nrhs) return hmg_fail(HMG_ERR_INVALID, "bad argument");
     hmg_status st = check_solve_args(rtol, maxit);
     if (st) return st;
@@ -566,6 +568,7 @@ extern "C" hmg_status hmg_solve_dev_static(hmg_grid *g, int rhs, const void *d_b
 // ---------------------------------------------------------------------------
 extern "C" hmg_status hmg_solve_cycles(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *x, double rtol, int maxit,
                                        hmg_solve_info *info) {
+    MarkRange mark_("hmg_solve_cycles");
     if (!g || !x) return hmg_fail(HMG_ERR_INVALID, "null argument");
     hmg_status st = check_solve_args(rtol, maxit);
     if (st) return st;
@@ -630,6 +633,7 @@ extern "C" hmg_status hmg_solve_cycles(hmg_grid *g, const hmg_c64 *x0, hmg_c64 *
 // ---------------------------------------------------------------------------
 extern "C" hmg_status hmg_solve_batch(hmg_ctx *ctx, int count, hmg_grid *const *grids, hmg_c64 *const *x,
                                       double rtol, int maxit, hmg_solve_info *const *info) {
+    MarkRange mark_("hmg_solve_batch");
     if (!ctx || count < 0 || (count > 0 && (!grids || !x))) return hmg_fail(HMG_ERR_INVALID, "bad argument");
     hmg_status st = check_solve_args(rtol, maxit);
     if (st) return st;
@@ -756,6 +760,7 @@ struct Request {
 // memory stays allocated for the next request of that size), publish the
 // result.
 static void retire(hmg_ctx *ctx, Request *q, hmg_status status) {
+    MarkRange mark_("hmg server retire");
     ServerState &S = *ctx->server;
     hmg_grid *keep = nullptr;
     if (q->grid) {
