@@ -14,7 +14,8 @@ row (n_c = 7, 9, 15, 19, 29), so each row has the same level sequence in kH
 of paper_1312_2880_amd.inputs (k_ref h = 15/64, k_ref = 15, 30, 60, 120 on
 h = 1/64 ... 1/512, source at the middle of the upper edge), the coarsest
 level the one whose largest kH lies in [3.75, 7.5) (n_c = 7, 7, 15, 31).
-Columns: SL-V, HYB-V and HLM-V, each with the coloured sweeps and with the
+Columns: SL-V, HYB-V, HLM-V and HYB-V-mid (HYB-V with M on the intermediate
+scales, the hyb_mid option), each with the coloured sweeps and with the
 lexicographic sweeps of Section 4.  At most 400 iterations (HLM-V does not
 converge on most of these problems).
 
@@ -46,7 +47,9 @@ def problem(table, k0, n):
     return inputs.grid_h(n), inputs.constant_k(n, float(k0)), inputs.centre_source(n)
 
 
-VARIANTS = (("SL-V", oracle.SL), ("HYB-V", oracle.HYB), ("HLM-V", oracle.HLM))
+# HYB-V-mid: HYB-V with M on the intermediate scales (the hyb_mid option)
+VARIANTS = (("SL-V", oracle.SL, 0), ("HYB-V", oracle.HYB, 0), ("HLM-V", oracle.HLM, 0),
+            ("HYB-V-mid", oracle.HYB, 1))
 RTOL, MAXIT = 1e-7, 400
 
 
@@ -57,10 +60,11 @@ def main():
         h, k, f = problem(table, k0, n)
         row = {"table": table, "k": k0, "N": N, "n": n, "coarsest_n": nc,
                "medium": "wedge" if table == "table3" else "constant", "counts": {}}
-        for vname, v in VARIANTS:
+        for vname, v, mid in VARIANTS:
             for order, tag in ((0, ""), (1, "-lex")):
                 t0 = time.time()
-                g = oracle.Grid(h, k, variant=v, coarsest_n=nc, gs_order=order, kacz_order=order)
+                g = oracle.Grid(h, k, variant=v, coarsest_n=nc, gs_order=order, kacz_order=order,
+                                hyb_mid=mid)
                 _, info = g.bicgstab(f, rtol=RTOL, maxit=MAXIT)
                 row["counts"][vname + tag] = {"iters": info["iters"], "status": info["status"],
                                               "seconds": round(time.time() - t0, 2)}

@@ -664,14 +664,15 @@ def test_table_counts_match_oracle(ctx, hmg, row, key, ref_iters, rtol):
         h, k, f = inputs.grid_h(n), inputs.constant_k(n, float(row["k"])), inputs.centre_source(n)
     variant = {"SL": hmg.SL, "HY": hmg.HYB, "HL": hmg.HLM}[key[:2]]
     order = hmg.ORDER_LEX if key.endswith("-lex") else hmg.ORDER_COLOUR
-    g = hmg.Grid(ctx, h, k, f, variant=variant, coarsest_n=row["coarsest_n"], relax_order=order)
+    mid = 1 if "-mid" in key else 0
+    g = hmg.Grid(ctx, h, k, f, variant=variant, coarsest_n=row["coarsest_n"], relax_order=order, hyb_mid=mid)
     assert [p["n"] for p in g.plan()] == row["levels"]
     x, info = g.solve(rtol=rtol, maxit=400)
     i0 = info[0]
     say(f"gpu {i0['iters']} oracle {ref_iters}")
     assert i0["status"] == hmg.OK and i0["rel_res_true"] <= rtol
     og = oracle.Grid(h, k, variant=variant, coarsest_n=row["coarsest_n"], gs_order=int(order),
-                     kacz_order=int(order))
+                     kacz_order=int(order), hyb_mid=mid)
     _, early = og.bicgstab(f, rtol=rtol, maxit=6, history=True)
     np.testing.assert_allclose(g.history(0)[:12], early["history"][:12], rtol=1e-7)
     margin = count_margin(ref_iters) if ref_iters < 100 else 0.25 * ref_iters

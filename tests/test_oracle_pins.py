@@ -785,6 +785,30 @@ def test_table1_trend_hybrid_not_worse_than_sl():
     assert its[oracle.HYB] <= its[oracle.SL] + 1.0, its
 
 
+@pytest.mark.slow
+def test_table1_trend_hybrid_below_sl_with_intermediate_scales_on_m():
+    """Under the motivation's reading of the hybrid (hyb_mid: M for
+    relaxation on the intermediate scales up to kH ~ 2.5), Table 1's
+    ordering holds: HYB-V needs no more iterations than SL-V at k = 40, 80
+    and 150 (kh = 0.625, coarsest level at kH = 5), and the gap widens with
+    k as in the paper (trend only; parity unpinned)."""
+    its = {}
+    for n, k0, nc in ((63, 40.0, 7), (127, 80.0, 15), (239, 150.0, 29)):
+        h = 1.0 / (n + 1)
+        k = np.full((n + 2, n + 2), k0)
+        f = np.zeros((n + 2, n + 2), complex)
+        f[(n + 1) // 2, (n + 1) // 2] = 1
+        row = []
+        for v, mid in ((oracle.SL, 0), (oracle.HYB, 1)):
+            _, info = oracle.Grid(h, k, variant=v, coarsest_n=nc, hyb_mid=mid).bicgstab(f, rtol=1e-7, maxit=300)
+            assert info["status"] == oracle.OK
+            row.append(info["iters"])
+        its[k0] = row
+    assert all(hyb <= sl for sl, hyb in its.values()), its
+    gaps = [sl - hyb for sl, hyb in its.values()]
+    assert gaps[-1] > gaps[0], its
+
+
 # ---------------------------------------------------------------------------
 # study switches (readings other than the default, for the iteration-count
 # study of Section 5's choices): each equals its dense composition
