@@ -1325,7 +1325,7 @@ def test_mixed_solve_acceptance(ctx, hmg, n, t):
 
 
 @pytest.mark.xfail(strict=False, reason="HYB-V with complex-float storage needs about twice the FP64 "
-                   "iterations on the 2047^2 layered problem (2080.5 vs 984 measured): HYB-V runs Gauss-"
+                   "iterations on the 2047^2 layered problem (1510 vs 854.5, and 2080.5 vs 984 on an earlier build): HYB-V runs Gauss-"
                    "Seidel on L on its coarse levels, is already near breakdown in FP64, and the float "
                    "stores perturb every application by ~1e-7 relative")
 def test_mixed_solve_acceptance_2047_hyb(ctx, hmg):
@@ -1341,6 +1341,28 @@ def test_mixed_solve_acceptance_2047_hyb(ctx, hmg):
     g64.close()
     g = hmg.Grid(ctx, h, k, f, variant=2, precision=hmg.MIXED)
     x, info = g.solve(rtol=1e-6, maxit=3000)
+    say(f"  mixed {info[0]['iters']} FP64 {i64[0]['iters']}")
+    assert info[0]["status"] == hmg.OK and info[0]["rel_res_true"] <= 1e-6
+    r = oracle.residual(h, k, 0.0, f, x[0])
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-6
+    assert info[0]["iters"] <= i64[0]["iters"] + 2.0
+
+
+@pytest.mark.xfail(strict=False, reason="at the limit of the +2 criterion on the measured build (mixed 201.5 "
+                   "against FP64 202 with the finest level in double; the count moves by a few iterations "
+                   "with rounding-level changes)")
+def test_mixed_solve_acceptance_2047_hyb_mid(ctx, hmg):
+    """The precision form on the 2047^2 problem with HYB-V's intermediate-
+    scales reading (hyb_mid) and the finest level in double (fp64_levels =
+    1): (i) the FP64 true residual meets 1e-6, (ii) at most 2 more iterations
+    than the FP64 solve of the same reading."""
+    say("case mixed solve acceptance layered2047 HYB hyb_mid")
+    h, k, f = inputs.workload_layered_2047()
+    g64 = hmg.Grid(ctx, h, k, f, variant=2, hyb_mid=1)
+    _, i64 = g64.solve(rtol=1e-6, maxit=1000)
+    g64.close()
+    g = hmg.Grid(ctx, h, k, f, variant=2, hyb_mid=1, precision=hmg.MIXED, fp64_levels=1)
+    x, info = g.solve(rtol=1e-6, maxit=1000)
     say(f"  mixed {info[0]['iters']} FP64 {i64[0]['iters']}")
     assert info[0]["status"] == hmg.OK and info[0]["rel_res_true"] <= 1e-6
     r = oracle.residual(h, k, 0.0, f, x[0])
