@@ -778,8 +778,11 @@ static void retire(hmg_ctx *ctx, Request *q, hmg_status status) {
     }
     std::lock_guard<std::mutex> lk(S.mu);
     if (keep) {
-        S.pool.push_back(PoolEntry{keep, q->footprint});
-        S.pooled += q->footprint;
+        // what the kept grid holds: its carved memory and its history (at
+        // least this request's, maybe an earlier, longer one's)
+        const size_t held = std::max(q->footprint, keep->bytes + (size_t)keep->hist_cap * 8 * keep->nrhs);
+        S.pool.push_back(PoolEntry{keep, held});
+        S.pooled += held;
     }
     if (q->state == 1) S.used -= q->footprint;
     q->state = 2;
@@ -815,9 +818,12 @@ static void server_loop(hmg_ctx *ctx) {
                 // an idle grid of the request's size and options takes it in
                 // place; idle grids of other sizes give their memory back
                 // (oldest first) only when the budget needs it
+                // (its residual history must hold this request's maxit too,
+                // or the solve would reallocate it)
                 int match = -1;
                 for (int e = (int)S.pool.size() - 1; e >= 0; --e)
-                    if (grid_reusable(S.pool[e].grid, q->n, 1, q->opts)) {
+                    if (grid_reusable(S.pool[e].grid, q->n, 1, q->opts) &&
+                        S.pool[e].grid->hist_cap >= 2 * q->maxit + 2) {
                         match = e;
                         break;
                     }
