@@ -6,7 +6,8 @@ footprint), against the same stream served one request at a time in FP64.
 
 Each request: n ~ U{255, 511, 1023, 2047}, a seeded layered medium with
 omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, SL-V
-preconditioner, relative residual 1e-6.  The served form runs the V-cycle in
+preconditioner (--variant hyb-mid: HYB-V with M on the intermediate scales,
+--variant hyb: HYB-V as defined), relative residual 1e-6.  The served form runs the V-cycle in
 complex float under the FP64 Bi-CGSTAB; the baseline runs plain FP64 with at
 most one request in flight.  Latency = completion time - submission time on
 the library's clock.  Prints one JSON line per (form, rate); the served FP64
@@ -50,7 +51,7 @@ def make_requests(rate, count, warmup, seed):
     return reqs
 
 
-def serve(hmg, reqs, precision, max_active, warmup, maxit):
+def serve(hmg, reqs, precision, max_active, warmup, maxit, vopts):
     ctx = hmg.Context(0)
     ctx.set_max_active(max_active)
     tickets = [None] * len(reqs)
@@ -63,7 +64,7 @@ def serve(hmg, reqs, precision, max_active, warmup, maxit):
             if delay > 0:
                 time.sleep(delay)
             tickets[q] = ctx.submit(n=r["n"], h=r["h"], k=r["k"], f=r["f"], rtol=1e-6,
-                                    maxit=maxit, variant=hmg.SL, precision=precision)
+                                    maxit=maxit, precision=precision, **vopts)
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -98,16 +99,20 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--max-active", type=int, default=0)
     ap.add_argument("--maxit", type=int, default=3000)
+    ap.add_argument("--variant", choices=["sl", "hyb", "hyb-mid"], default="sl")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     from paper_1312_2880_amd import hmg
+    vopts = {"sl": dict(variant=hmg.SL), "hyb": dict(variant=hmg.HYB),
+             "hyb-mid": dict(variant=hmg.HYB, hyb_mid=1)}[args.variant]
+    vname = {"sl": "SL-V", "hyb": "HYB-V", "hyb-mid": "HYB-V, M on the intermediate scales"}[args.variant]
     for rate in [float(x) for x in args.rates.split(",")]:
         reqs = make_requests(rate, args.count, args.warmup, args.seed)
         for form, prec, act in (("served-fp64", hmg.FP64, args.max_active),
                                 ("served-mixed", hmg.MIXED, args.max_active),
                                 ("serial-fp64", hmg.FP64, 1)):
-            out = serve(hmg, reqs, prec, act, args.warmup, args.maxit)
+            out = serve(hmg, reqs, prec, act, args.warmup, args.maxit, vopts)
             line = {"metric": "solves/s and p50/p99 latency, Poisson request stream",
                     "form": form, "rate_req_s": rate, "unit": "solves/s",
                     "value": round(out["value"], 3),
@@ -116,7 +121,7 @@ def main():
                     "mean_iters": round(out["mean_iters"], 2), "max_iters": out["max_iters"],
                     "solves": out["solves"],
                     "all_converged": out["all_converged"], "data": "synthetic",
-                    "config": {"sizes": [255, 511, 1023, 2047], "variant": "SL-V",
+                    "config": {"sizes": [255, 511, 1023, 2047], "variant": vname,
                                "seed": args.seed, "rtol": 1e-6}}
             print(json.dumps(line), flush=True)
 

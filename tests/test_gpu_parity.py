@@ -419,6 +419,9 @@ def test_kaczmarz_down_matches_oracle(ctx, hmg, cfg, start, n):
         want = oracle.kacz_5c(h, k, 0.5, f, want)
     assert rel(host(d_uo), want) <= 1e-12
     want_fc = oracle.restrict_fw(oracle.residual(h, k, 0.0, f, want))
+    # full weighting averages out most of the rough residual the sweeps leave
+    # (||R r|| is 5-9x below ||L u|| on these cases, by the oracle), so an
+    # error of u at the 1e-12 bound above reaches f_c up to ~9x larger
     assert rel(host(d_fc), want_fc) <= 1e-11
 
 
@@ -450,6 +453,7 @@ def test_kaczmarz_level_matches_oracle(ctx, hmg, sweeps, start, n):
     for _ in range(sweeps):
         want = oracle.kacz_5c(h, k, 0.5, f, want)
     assert rel(host(d_uo), want) <= 1e-12
+    # the restriction amplifies u's relative error up to ~9x (see above)
     assert rel(host(d_fc), oracle.restrict_fw(oracle.residual(h, k, 0.0, f, want))) <= 1e-11
 
 
