@@ -7,10 +7,9 @@ alone (hmg_solve_dev per right-hand side: no batching at all).
 
     python bench_batch.py [--count 64] [--nrhs 4] [--precision mixed|fp64|both]
 
-SL-V preconditioner by default (HYB-V as defined does not converge on the
-high-kh constant-k instances of this mix; --variant hyb-mid runs HYB-V with M
-on the intermediate scales, --variant hyb the definition), relative residual
-1e-6, x0 = 0.  Prints a progress
+HYB-V preconditioner with M on the intermediate scales by default (HYB-V as
+defined, --variant hyb, does not converge on the high-kh constant-k instances
+of this mix; --variant sl runs SL-V), relative residual 1e-6, x0 = 0.  Prints a progress
 line per phase and one JSON line per form with right-hand-side solves per
 second and node-RHS per second.
 """
@@ -33,7 +32,7 @@ def main():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--precision", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--maxit", type=int, default=2000)
-    ap.add_argument("--variant", choices=["sl", "hyb", "hyb-mid"], default="sl")
+    ap.add_argument("--variant", choices=["sl", "hyb", "hyb-mid"], default="hyb-mid")
     args = ap.parse_args()
     import numpy as np
     import torch

@@ -5,9 +5,9 @@ footprint), against the same stream served one request at a time in FP64.
     python bench_serve.py [--rates 5,50,200] [--count 30] [--warmup 4]
 
 Each request: n ~ U{255, 511, 1023, 2047}, a seeded layered medium with
-omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, SL-V
-preconditioner (--variant hyb-mid: HYB-V with M on the intermediate scales,
---variant hyb: HYB-V as defined), relative residual 1e-6.  The served form runs the V-cycle in
+omega = 2 pi 40 (n+1)/1024 (max kh fixed), one seeded point source, HYB-V
+preconditioner with M on the intermediate scales (--variant hyb: HYB-V as
+defined, --variant sl: SL-V), relative residual 1e-6.  The served form runs the V-cycle in
 complex float under the FP64 Bi-CGSTAB; the baseline runs plain FP64 with at
 most one request in flight.  Latency = completion time - submission time on
 the library's clock.  Prints one JSON line per (form, rate); the served FP64
@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--max-active", type=int, default=0)
     ap.add_argument("--maxit", type=int, default=3000)
-    ap.add_argument("--variant", choices=["sl", "hyb", "hyb-mid"], default="sl")
+    ap.add_argument("--variant", choices=["sl", "hyb", "hyb-mid"], default="hyb-mid")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
