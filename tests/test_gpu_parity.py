@@ -1546,21 +1546,24 @@ def test_batched_rhs_equal_single_rhs_solves(ctx, hmg, name, n, variant, precisi
             assert info[q]["iters"] == 0 and not np.any(x[q])
 
 
+@pytest.mark.parametrize("variant", ["sl", "hyb-mid"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batch_of_16_instances_by_4_rhs(ctx, hmg, precision):
+def test_batch_of_16_instances_by_4_rhs(ctx, hmg, precision, variant):
     """hmg_solve_batch on 16 constant-k instances of mixed size (n in {63,
     127, 255}, kh in [0.3, 0.45]), 4 point sources each: every grid runs its
     four right-hand sides in batched launches, the grids overlap on their own
     streams, and every result equals the right-hand side solved alone, bit
-    for bit; the oracle recomputes all 64 residuals."""
-    say(f"case batch 16x4 precision={precision}")
+    for bit; the oracle recomputes all 64 residuals.  SL-V, and HYB-V with M
+    on the intermediate scales (the batch benchmark's preconditioner)."""
+    say(f"case batch 16x4 precision={precision} variant={variant}")
+    vk = dict(variant=hmg.SL) if variant == "sl" else dict(variant=hmg.HYB, hyb_mid=1)
     insts = inputs.batch_instances(seed=7, count=16, nrhs=4, sizes=(63, 127, 255), kh_range=(0.3, 0.45))
-    grids = [hmg.Grid(ctx, it["h"], it["k"], np.stack(it["f"]), precision=precision, variant=hmg.SL)
+    grids = [hmg.Grid(ctx, it["h"], it["k"], np.stack(it["f"]), precision=precision, **vk)
              for it in insts]
     xb, ib = ctx.solve_batch(grids, rtol=1e-6, maxit=600)
     for q, (it, xs, infos) in enumerate(zip(insts, xb, ib)):
         for r in range(4):
-            g1 = hmg.Grid(ctx, it["h"], it["k"], it["f"][r], precision=precision, variant=hmg.SL)
+            g1 = hmg.Grid(ctx, it["h"], it["k"], it["f"][r], precision=precision, **vk)
             x1, i1 = g1.solve(rtol=1e-6, maxit=600)
             g1.close()
             assert infos[r]["status"] == hmg.OK and infos[r]["rel_res_true"] <= 1e-6, (q, r, infos[r])
