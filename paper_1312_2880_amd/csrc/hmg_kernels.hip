@@ -300,23 +300,52 @@ void launch_convert(hipStream_t s, int to_float, const void *src, void *dst, siz
 // entries t, t + 256, ... in eight interleaved accumulators (independent
 // loads in flight instead of one dependent chain), combined in a fixed
 // order, then a fixed tree across the block: the result depends only on nb.
+// Accumulator u of thread t takes the entries t + u NT + 8 NT r below nb in
+// increasing r.  Up to FIN_R rounds, every entry of every row is loaded
+// before the first add (one memory round trip instead of one per round and
+// row: the partials come from another kernel, through the last-level
+// cache); the adds keep that order, so the sums are the same bit for bit.
+constexpr int FIN_R = 3;
 template <int NV>
 __device__ __forceinline__ void finalize_sums(const double *partials, int nb, double *tot) {
     double v[NV];
     int tid = threadIdx.y * BX + threadIdx.x;
+    if (nb <= FIN_R * 8 * NT) {
+        double e[NV][FIN_R][8];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        const double *P = partials + (size_t)q * nb;
-        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int b = tid;
-        for (; b + 7 * NT < nb; b += 8 * NT) {
+        for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] += P[b + u * NT];
+            for (int r = 0; r < FIN_R; ++r)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int b = tid + u * NT + 8 * NT * r;
+                    e[q][r][u] = b < nb ? partials[(size_t)q * nb + b] : 0.0;
+                }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < FIN_R; ++r)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (tid + u * NT + 8 * NT * r < nb) a[u] += e[q][r][u];
+            v[q] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         }
+    } else {
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (b + u * NT < nb) a[u] += P[b + u * NT];
-        v[q] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        for (int q = 0; q < NV; ++q) {
+            const double *P = partials + (size_t)q * nb;
+            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int b = tid;
+            for (; b + 7 * NT < nb; b += 8 * NT) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += P[b + u * NT];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (b + u * NT < nb) a[u] += P[b + u * NT];
+            v[q] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        }
     }
     __shared__ double out[NV];
     block_sum<NV>(v, out);
