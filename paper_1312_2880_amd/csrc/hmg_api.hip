@@ -457,6 +457,11 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                     cur = bufs[w];
                     w ^= 1;
                 }
+                // a configuration without the fused residual pays for the
+                // separate residual and restriction, as in the V-cycle
+                if (!kacz_cfg_resid(cfg) && cur)
+                    launch_residual_fw(L.prec, g->stream, L.geo, L.k, pl.sigma_resid[l], S.f[l], cur, S.f[l + 1],
+                                       nullptr);
                 for (int q = 0; q < pl.post[l] && cur; q += sw) {
                     launch_kacz_tb(L.prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l], cur,
                                    q == 0 ? S.u[l + 1] : nullptr, bufs[w], nullptr);

@@ -875,10 +875,19 @@ __global__ __launch_bounds__(NT) void k_kacz_tb(GeoT g, double H, double ih2, co
                 const C<double> fp = FS[l];
                 kacz_row_lds(U, l, LW, row_at<double>(i, j, N, H, ih2, kc.x, sig), fp, kc.y);
             } else {
+                // (k, 1/||a_p||^2) from the row table when there is one, the
+                // values the staged configurations read, so that every
+                // configuration gives the same bits
                 const size_t p = (size_t)j * M + i;
-                Row<double> r = row_at<double>(i, j, N, H, ih2, (double)k[p], sig);
-                double nrm = r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr + r.wd * r.wd + r.wu * r.wu;
-                kacz_row_lds(U, l, LW, r, ldr<double>(f, p), 1.0 / nrm);
+                C<double> kc;
+                if (ktab) {
+                    kc = ktab[p];
+                } else {
+                    const Row<double> r = row_at<double>(i, j, N, H, ih2, (double)k[p], sig);
+                    kc = cmk((double)k[p], 1.0 / (r.dre * r.dre + r.dim * r.dim + r.wl * r.wl + r.wr * r.wr +
+                                                  r.wd * r.wd + r.wu * r.wu));
+                }
+                kacz_row_lds(U, l, LW, row_at<double>(i, j, N, H, ih2, kc.x, sig), ldr<double>(f, p), kc.y);
             }
         }
         __syncthreads();
