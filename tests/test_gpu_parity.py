@@ -1348,9 +1348,9 @@ def test_mixed_solve_acceptance(ctx, hmg, n, t):
     assert rel(x10[0], x10_ref) <= 1e-6
 
 
-@pytest.mark.xfail(strict=False, reason="HYB-V with complex-float storage needs about twice the FP64 "
-                   "iterations on the 2047^2 layered problem (1510 vs 854.5, and 2080.5 vs 984 on an earlier "
-                   "build; with the finest one or two levels in double 3000+ and 2011.5): HYB-V runs Gauss-"
+@pytest.mark.xfail(strict=False, reason="HYB-V with complex-float storage needs far more than the FP64 "
+                   "iterations on the 2047^2 layered problem (1510 vs 964; 2080.5 vs 984 on an earlier "
+                   "build, and with the finest one or two levels in double 3000+ and 2011.5): HYB-V runs Gauss-"
                    "Seidel on L on its coarse levels, is already near breakdown in FP64, and the float "
                    "stores perturb every application by ~1e-7 relative")
 def test_mixed_solve_acceptance_2047_hyb(ctx, hmg):
@@ -1373,10 +1373,10 @@ def test_mixed_solve_acceptance_2047_hyb(ctx, hmg):
     assert info[0]["iters"] <= i64[0]["iters"] + 2.0
 
 
-@pytest.mark.xfail(strict=False, reason="met or missed by the choice of Kaczmarz tile on the 255^2 level, "
-                   "which changes only the rounding: with the finest level in double, mixed 201.5 against "
-                   "FP64 202 with the tuned configurations (32-wide tiles there), 202.5 against 193.5 with "
-                   "the default ones; every level in float: 228 and 232.5")
+@pytest.mark.xfail(strict=False, reason="with the finest level in double, mixed 202.5 against FP64 193.5 "
+                   "(every level in float: 232.5); a build that differed only in the rounding of 1/||a_p||^2 "
+                   "on the 255^2 level gave 201.5 against 202, within the +2: the excess is of the size "
+                   "rounding alone moves these counts")
 def test_mixed_solve_acceptance_2047_hyb_mid(ctx, hmg):
     """The precision form on the 2047^2 problem with HYB-V's intermediate-
     scales reading (hyb_mid) and the finest level in double (fp64_levels =
