@@ -100,7 +100,9 @@ typedef struct {
                                 and the bottom levels as one cycle (default) */
     int    autotune;         /* 1: time the Kaczmarz tile configurations on the
                                 level's shape at grid creation (cached per
-                                process); 0: fixed default                      */
+                                process); 0: fixed default.  The choice
+                                changes only the speed: every configuration
+                                gives the same results, bit for bit          */
     int    bottom_dense;     /* 1: the cycle on the bottom levels (n <= 31) is a
                                 fixed linear map of its right-hand side; form
                                 its matrix (complex FP64, m^2 entries for
