@@ -101,8 +101,8 @@ typedef struct {
     int    autotune;         /* 1: time the Kaczmarz tile configurations on the
                                 level's shape at grid creation (cached per
                                 process); 0: fixed default.  The choice
-                                changes only the speed: every configuration
-                                gives the same results, bit for bit          */
+                                changes only the speed: every tile
+                                configuration gives the same bits            */
     int    bottom_dense;     /* 1: the cycle on the bottom levels (n <= 31) is a
                                 fixed linear map of its right-hand side; form
                                 its matrix (complex FP64, m^2 entries for
