@@ -73,6 +73,43 @@ def algorithmic_bytes(kind: str, nodes: int, coarse_nodes: int, cbytes: int, rby
     raise KeyError(kind)
 
 
+def vcycle_model_bytes(plan, cbytes: int, rbytes: int) -> float:
+    """Bytes one V-cycle must move by the per-level model (c, r as above;
+    N nodes of the level, its coarse nodes N/4): a relaxation sweep from
+    zero reads f, k and writes u (2c + r), any other sweep also reads u
+    (3c + r); the residual with full weighting reads f, k, u and writes
+    the coarse right-hand side (2c + r + c/4); the correction reads the
+    coarse error and u and writes u (2c + c/4).  A V(1,1) Gauss-Seidel level
+    is then N (9.5c + 3r), a 4+4 Kaczmarz level N (27.5c + 9r); the dense
+    coarsest level is not counted."""
+    c, r = cbytes, rbytes
+    tot = 0.0
+    for p in plan:
+        sweeps = p["pre"] + p["post"]
+        if p["smoother"] not in ("GS", "KACZ") or sweeps == 0:
+            continue
+        nodes = (p["n"] + 2) ** 2
+        tot += nodes * ((2 * c + r) + (sweeps - 1) * (3 * c + r) + (2 * c + r + c / 4) + (2 * c + c / 4))
+    return tot
+
+
+def time_vcycle(torch, g, plan, precision, sets=8, count=16):
+    """One V-cycle through the C-ABI (hmg_vcycle_dev) on FP64 fields, as
+    graph replays over `sets` input/output pairs (about 1 GB at 2047^2, so
+    that the finest level reads from HBM), rated on vcycle_model_bytes."""
+    n = plan[0]["n"]
+    gen = torch.Generator(device="cuda").manual_seed(1)
+    rs = [torch.randn((n + 2, n + 2), dtype=torch.complex128, device="cuda", generator=gen) for _ in range(sets)]
+    zs = [torch.empty_like(rs[0]) for _ in range(sets)]
+    stream = torch.cuda.Stream()
+    ms = graph_time(torch, stream, lambda q: g.vcycle_dev(rs[q % sets], zs[q % sets], stream=stream), count)
+    cb, rb = (16, 8) if precision == "fp64" else (8, 4)
+    model = vcycle_model_bytes(plan, cb, rb)
+    achieved = model / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 5), "bytes_model": round(model), "bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+
 def graph_time(torch, stream, fn, count, reps=3):
     """Average duration of one launch of fn: `count` launches are captured
     into one HIP graph on `stream` and replayed, bracketed by HIP events on
@@ -380,6 +417,8 @@ def main():
         k_["share"] = k_["ms"] * k_["per_iter"] / it_ms
         k_["roofline"] = roofline_of(k_["model"], k_["ms"])
     dom = max(kt, key=lambda k_: k_["share"])
+    # the whole V-cycle, rated on the per-level byte model
+    vcycle = time_vcycle(torch, g, plan, args.precision) if not lex else None
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -470,6 +509,7 @@ def main():
         "roofline": roofline,
         "kernels": {k_["key"]: {"ms_per_launch": round(k_["ms"], 5), "launches_per_iter": k_["per_iter"],
                                 "share_of_solve": round(k_["share"], 3), **k_["roofline"]} for k_ in kt},
+        "vcycle": vcycle,
         "mixed": mixed,
         "hyb_mid": hyb_mid,
         "cpu_baseline": cpu,
