@@ -110,6 +110,30 @@ def time_vcycle(torch, g, plan, precision, sets=8, count=16):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
 
 
+def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
+    """Attained bandwidth of a plain device-to-device copy of nbytes (read
+    plus write counted, as STREAM does), best of reps, HIP events."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * nbytes, "ms": round(best, 4), "achieved": round(2 * nbytes / (best * 1e-3) / 1e9, 1),
+            "unit": "GB/s", "frac": round(2 * nbytes / (best * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def graph_time(torch, stream, fn, count, reps=3):
     """Average duration of one launch of fn: `count` launches are captured
     into one HIP graph on `stream` and replayed, bracketed by HIP events on
@@ -419,6 +443,7 @@ def main():
     dom = max(kt, key=lambda k_: k_["share"])
     # the whole V-cycle, rated on the per-level byte model
     vcycle = time_vcycle(torch, g, plan, args.precision) if not lex else None
+    copy = copy_bandwidth(torch)
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -510,6 +535,7 @@ def main():
         "kernels": {k_["key"]: {"ms_per_launch": round(k_["ms"], 5), "launches_per_iter": k_["per_iter"],
                                 "share_of_solve": round(k_["share"], 3), **k_["roofline"]} for k_ in kt},
         "vcycle": vcycle,
+        "copy_4gib": copy,
         "mixed": mixed,
         "hyb_mid": hyb_mid,
         "cpu_baseline": cpu,
