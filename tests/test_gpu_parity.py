@@ -1350,7 +1350,7 @@ def test_mixed_solve_acceptance(ctx, hmg, n, t):
 
 
 @pytest.mark.xfail(strict=False, reason="HYB-V with complex-float storage needs far more than the FP64 "
-                   "iterations on the 2047^2 layered problem (1510 vs 964; 2080.5 vs 984 on an earlier "
+                   "iterations on the 2047^2 layered problem (2747.5 vs 964; 1510 and 2080.5 on earlier "
                    "build, and with the finest one or two levels in double 3000+ and 2011.5): HYB-V runs Gauss-"
                    "Seidel on L on its coarse levels, is already near breakdown in FP64, and the float "
                    "stores perturb every application by ~1e-7 relative")
