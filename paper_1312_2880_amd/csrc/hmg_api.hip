@@ -413,18 +413,15 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         }
     }
     // On complex-float levels the sweeps per launch decide where the iterate
-    // is rounded to float, and the fused residual restricts the iterate
-    // before its last rounding (the separate residual kernel reads it
-    // rounded), so the candidates keep the default's sweep count and have
-    // the fused residual (tile shape and size do not change any value: each
-    // node sees the same row updates in the same order); the results then
-    // do not depend on timing.
+    // is rounded to float, so the candidates keep the default's count (tile
+    // shape and size do not change any value: each node sees the same row
+    // updates in the same order); the results then do not depend on timing.
     const bool float_level = g->lev[l].prec == P32;
     const int sw_default = kKaczCfgs[g->lev[l].kacz_cfg].sweeps;
     std::vector<int> cand;
     for (int cfg = 0; cfg < KACZ_NCFG; ++cfg) {
         int sw = kKaczCfgs[cfg].sweeps;
-        if (float_level && (sw != sw_default || !kacz_cfg_resid(cfg))) continue;
+        if (float_level && sw != sw_default) continue;
         if (kacz_cfg_fits(g->lev[l].prec, cfg) && pl.pre[l] % sw == 0 && pl.post[l] % sw == 0) cand.push_back(cfg);
     }
     if (cand.size() > 1 && pl.pre[l] > 0) {
