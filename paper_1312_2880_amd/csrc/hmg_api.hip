@@ -310,6 +310,20 @@ static int find_bottom(const hmg_grid *g) {
     return -1;
 }
 
+// The configuration whose RESID form ends the pre-smoothing of a level run
+// with cfg: cfg itself, or else one with the same sweeps per launch (the
+// default first), whose sweeps give the same values as cfg's, so that the
+// residual is always restricted from the iterate before its last rounding
+// to the level's storage; -1 if there is none.
+static int kacz_resid_config(int cfg) {
+    if (kacz_cfg_resid(cfg)) return cfg;
+    const int sw = kKaczCfgs[cfg].sweeps;
+    if (kKaczCfgs[KACZ_DEFAULT].sweeps == sw && kacz_cfg_resid(KACZ_DEFAULT)) return KACZ_DEFAULT;
+    for (int c = 0; c < KACZ_NCFG; ++c)
+        if (kKaczCfgs[c].sweeps == sw && kacz_cfg_resid(c)) return c;
+    return -1;
+}
+
 static void plan_paths(hmg_grid *g) {
     for (int l = 0; l < g->nlev; ++l) {
         g->lev[l].mode = LM_SIMPLE;
@@ -327,7 +341,7 @@ static void plan_paths(hmg_grid *g) {
             // default before tuning: the LDS-staged 16 x 8 tile with 2
             // sweeps per launch (1024 threads) if 2 divides both sweep
             // counts, else one sweep per launch on 16 x 16 tiles
-            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? 7 : 5;
+            int best = (pl.pre[l] % 2 == 0 && pl.post[l] % 2 == 0) ? KACZ_DEFAULT : 5;
             g->lev[l].kacz_cfg = best;
         }
     }
@@ -413,15 +427,17 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
         }
     }
     // On complex-float levels the sweeps per launch decide where the iterate
-    // is rounded to float, so the candidates keep the default's count (tile
-    // shape and size do not change any value: each node sees the same row
-    // updates in the same order); the results then do not depend on timing.
+    // is rounded to float, so the candidates keep the default's count, and
+    // the pre-smoothing always ends with a fused residual (kacz_resid_config),
+    // which restricts the iterate before its rounding; tile shape and size
+    // change no value (each node sees the same row updates in the same
+    // order), so the results do not depend on timing.
     const bool float_level = g->lev[l].prec == P32;
     const int sw_default = kKaczCfgs[g->lev[l].kacz_cfg].sweeps;
     std::vector<int> cand;
     for (int cfg = 0; cfg < KACZ_NCFG; ++cfg) {
         int sw = kKaczCfgs[cfg].sweeps;
-        if (float_level && sw != sw_default) continue;
+        if (float_level && (sw != sw_default || kacz_resid_config(cfg) < 0)) continue;
         if (kacz_cfg_fits(g->lev[l].prec, cfg) && pl.pre[l] % sw == 0 && pl.post[l] % sw == 0) cand.push_back(cfg);
     }
     if (cand.size() > 1 && pl.pre[l] > 0) {
@@ -447,9 +463,10 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                 const void *cur = nullptr;
                 void *bufs[2] = {S.u[l], S.u2[l]};
                 int w = 0;
+                const int rcfg = kacz_resid_config(cfg);
                 for (int q = 0; q < pl.pre[l]; q += sw) {
-                    if (kacz_cfg_resid(cfg) && q + sw >= pl.pre[l])
-                        launch_kacz_tb_resid(L.prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l],
+                    if (rcfg >= 0 && q + sw >= pl.pre[l])
+                        launch_kacz_tb_resid(L.prec, rcfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l],
                                              pl.sigma_resid[l], S.f[l], cur, bufs[w], S.f[l + 1], nullptr);
                     else
                         launch_kacz_tb(L.prec, cfg, g->stream, L.geo, L.k, L.ktab, pl.sigma_relax[l], S.f[l],
@@ -457,9 +474,9 @@ static hmg_status tune_kacz_level(hmg_grid *g, int l) {
                     cur = bufs[w];
                     w ^= 1;
                 }
-                // a configuration without the fused residual pays for the
-                // separate residual and restriction, as in the V-cycle
-                if (!kacz_cfg_resid(cfg) && cur)
+                // without a fused residual the separate residual and
+                // restriction kernel runs, as in the V-cycle
+                if (rcfg < 0 && cur)
                     launch_residual_fw(L.prec, g->stream, L.geo, L.k, pl.sigma_resid[l], S.f[l], cur, S.f[l + 1],
                                        nullptr);
                 for (int q = 0; q < pl.post[l] && cur; q += sw) {
@@ -1065,11 +1082,14 @@ static const void *vc_fast(hmg_grid *g, Slot &S, int l, const void *f, bool f64,
         void *bufs[2] = {S.u[l], S.u2[l]};
         const void *cur = nullptr;
         int w = 0;
-        // the last pre-smoothing launch also restricts the residual
-        const bool fuse = pl.pre[l] > 0 && kacz_cfg_resid(cfg);
+        // the last pre-smoothing launch also restricts the residual (in the
+        // RESID form of cfg, or of a configuration with cfg's sweeps per
+        // launch when cfg's region is too large for it)
+        const int rcfg = pl.pre[l] > 0 ? kacz_resid_config(cfg) : -1;
+        const bool fuse = rcfg >= 0;
         for (int q = 0; q < pl.pre[l]; q += sw) {
             if (fuse && q + sw >= pl.pre[l])
-                launch_kacz_tb_resid(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], f, cur, bufs[w],
+                launch_kacz_tb_resid(L.prec, rcfg, s, L.geo, L.k, L.ktab, sig, pl.sigma_resid[l], f, cur, bufs[w],
                                      S.f[l + 1], skip, bz);
             else
                 launch_kacz_tb(L.prec, cfg, s, L.geo, L.k, L.ktab, sig, f, cur, nullptr, bufs[w], skip, bz);

@@ -114,6 +114,7 @@ struct KaczCfg {
     int ty, rty;                // tile height; that of the RESID form before its shrink by 4
 };
 constexpr int KACZ_NCFG = 8;
+constexpr int KACZ_DEFAULT = 7;   // the LDS-staged 16 x 8 tile, 2 sweeps per launch
 extern const KaczCfg kKaczCfgs[KACZ_NCFG];
 bool   kacz_cfg_fits(Prec p, int cfg);
 int    bottom_complex_slots();   // LDS capacity of the bottom solver
